@@ -1,0 +1,381 @@
+// Rigid-body dynamics of a revolute serial chain for one knot point, written in
+// link-local spatial-vector form (6D motion/force vectors, Featherstone style).
+//
+// The paper computes "gradients and Hessians of the costs and dynamics
+// functions across all problems and timesteps" with GRiD (Sec. III-A); that
+// library is not used here. These routines give, per lane:
+//   * inverse dynamics (recursive Newton-Euler), templated on the scalar so the
+//     same code runs on plain floats and on forward-mode dual numbers,
+//   * the joint-space inertia matrix (composite rigid bodies),
+//   * forward dynamics qdd = M^-1 (tau - b) via an in-register Cholesky.
+// Derivatives of forward dynamics follow from d/dx[ID(q, qd, FD(q, qd, u))] = 0:
+// dqdd/dx = -M^-1 dID/dx at fixed qdd, with dID/dx from one dual-number RNEA
+// pass per state direction.
+//
+// Chain convention: joint i rotates about z (even i) or y (odd i) of its own
+// frame; frame i sits at length_{i-1} along +z of frame i-1 (frame 0 at the
+// base origin); the centre of mass of link i is at length_i / 2 on +z with
+// diagonal inertia (Ixx, Iyy, Izz) about it; gravity acts along -z of the base.
+//
+// Everything here is __host__ __device__ so that a CPU build can be checked
+// without a GPU; the kernels include it for the device.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace gato {
+
+constexpr int kMaxDof = 7;
+
+// Per-solve chain parameters, pre-processed once per solve.
+struct Chain {
+  int n;          // degrees of freedom
+  int model;      // 0 revolute chain, 1 spring-coupled unit masses
+  float g;        // gravity magnitude
+  float ks;       // spring stiffness (model 1)
+  float Lp[kMaxDof];      // offset of joint i along +z of link i-1 (0 for i = 0)
+  float m[kMaxDof];       // mass
+  float cz[kMaxDof];      // centre-of-mass offset along +z
+  float Io[kMaxDof][3];   // rotational inertia about the joint (diagonal)
+};
+
+// ---------------------------------------------------------------------------
+// Forward-mode dual number: value + one tangent.
+// ---------------------------------------------------------------------------
+struct df {
+  float v, d;
+};
+__host__ __device__ inline df operator+(df a, df b) { return {a.v + b.v, a.d + b.d}; }
+__host__ __device__ inline df operator-(df a, df b) { return {a.v - b.v, a.d - b.d}; }
+__host__ __device__ inline df operator-(df a) { return {-a.v, -a.d}; }
+__host__ __device__ inline df operator*(df a, df b) { return {a.v * b.v, fmaf(a.d, b.v, a.v * b.d)}; }
+__host__ __device__ inline df operator*(float s, df a) { return {s * a.v, s * a.d}; }
+__host__ __device__ inline df &operator+=(df &a, df b) { a = a + b; return a; }
+__host__ __device__ inline df &operator-=(df &a, df b) { a = a - b; return a; }
+
+__host__ __device__ inline float value_of(float x) { return x; }
+__host__ __device__ inline float value_of(df x) { return x.v; }
+template <class T> __host__ __device__ inline T cst(float x);
+template <> __host__ __device__ inline float cst<float>(float x) { return x; }
+template <> __host__ __device__ inline df cst<df>(float x) { return {x, 0.0f}; }
+
+__host__ __device__ inline void sin_cos(float x, float *s, float *c) {
+  *s = sinf(x);
+  *c = cosf(x);
+}
+__host__ __device__ inline void sin_cos(df x, df *s, df *c) {
+  float sv, cv;
+  sin_cos(x.v, &sv, &cv);
+  *s = {sv, x.d * cv};
+  *c = {cv, -x.d * sv};
+}
+
+// ---------------------------------------------------------------------------
+// Frame maps. Y selects the joint axis (false: z, true: y). R is the rotation of
+// the child frame expressed in the parent frame; E = R^T maps parent
+// coordinates into child coordinates.
+// ---------------------------------------------------------------------------
+template <bool Y, class T>
+__host__ __device__ inline void rot_E(T c, T s, T &x, T &y, T &z) {  // a <- E a
+  if (Y) {
+    T nx = c * x - s * z, nz = s * x + c * z;
+    x = nx; z = nz;
+  } else {
+    T nx = c * x + s * y, ny = c * y - s * x;
+    x = nx; y = ny;
+  }
+}
+template <bool Y, class T>
+__host__ __device__ inline void rot_R(T c, T s, T &x, T &y, T &z) {  // a <- R a
+  if (Y) {
+    T nx = c * x + s * z, nz = c * z - s * x;
+    x = nx; z = nz;
+  } else {
+    T nx = c * x - s * y, ny = s * x + c * y;
+    x = nx; y = ny;
+  }
+}
+
+// Motion vector (w, v) at the parent origin -> child frame; the child origin
+// sits at r = (0, 0, L) in the parent: v_child = E (v - r x w).
+template <bool Y, class T>
+__host__ __device__ inline void motion_to_child(T c, T s, float L, T *w, T *v) {
+  v[0] = v[0] + L * w[1];
+  v[1] = v[1] - L * w[0];
+  rot_E<Y>(c, s, w[0], w[1], w[2]);
+  rot_E<Y>(c, s, v[0], v[1], v[2]);
+}
+
+// Force vector (n, f) at the child origin -> parent frame at the parent origin:
+// f_p = R f, n_p = R n + r x f_p.
+template <bool Y, class T>
+__host__ __device__ inline void force_to_parent(T c, T s, float L, T *n, T *f) {
+  rot_R<Y>(c, s, n[0], n[1], n[2]);
+  rot_R<Y>(c, s, f[0], f[1], f[2]);
+  n[0] = n[0] - L * f[1];
+  n[1] = n[1] + L * f[0];
+}
+
+// ---------------------------------------------------------------------------
+// Inverse dynamics (recursive Newton-Euler). Gravity is an upward acceleration
+// of the base. ch.model == 1 gives tau = qdd + ks T q (T = tridiag(-1, 2, -1)).
+// ---------------------------------------------------------------------------
+template <int ND, class T>
+__host__ __device__ inline void rnea(const Chain &ch, const T *q, const T *qd, const T *qdd, bool gravity,
+                                     T *tau) {
+  if (ch.model == 1) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      T s = 2.0f * q[i];
+      if (i > 0) s = s - q[i - 1];
+      if (i < ND - 1) s = s - q[i + 1];
+      tau[i] = qdd[i] + ch.ks * s;
+    }
+    return;
+  }
+  T cq[ND], sq[ND];
+  T fn[ND][3], ff[ND][3];
+  T w[3] = {cst<T>(0.f), cst<T>(0.f), cst<T>(0.f)};
+  T v[3] = {cst<T>(0.f), cst<T>(0.f), cst<T>(0.f)};
+  T aw[3] = {cst<T>(0.f), cst<T>(0.f), cst<T>(0.f)};
+  T av[3] = {cst<T>(0.f), cst<T>(0.f), cst<T>(gravity ? ch.g : 0.f)};
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    sin_cos(q[i], &sq[i], &cq[i]);
+    const float L = ch.Lp[i];
+    if (i & 1) {
+      motion_to_child<true>(cq[i], sq[i], L, w, v);
+      motion_to_child<true>(cq[i], sq[i], L, aw, av);
+      // v += S qd; a += S qdd + v x (S qd) with S = (e_y, 0)
+      w[1] = w[1] + qd[i];
+      aw[1] = aw[1] + qdd[i];
+      aw[0] = aw[0] - w[2] * qd[i];
+      aw[2] = aw[2] + w[0] * qd[i];
+      av[0] = av[0] - v[2] * qd[i];
+      av[2] = av[2] + v[0] * qd[i];
+    } else {
+      motion_to_child<false>(cq[i], sq[i], L, w, v);
+      motion_to_child<false>(cq[i], sq[i], L, aw, av);
+      // S = (e_z, 0)
+      w[2] = w[2] + qd[i];
+      aw[2] = aw[2] + qdd[i];
+      aw[0] = aw[0] + w[1] * qd[i];
+      aw[1] = aw[1] - w[0] * qd[i];
+      av[0] = av[0] + v[1] * qd[i];
+      av[1] = av[1] - v[0] * qd[i];
+    }
+    // Spatial inertia about the joint with the centre of mass at c = (0, 0, cz):
+    // I (w, v) = (Io w + m c x v, m v - m c x w).
+    const float m = ch.m[i], mc = ch.m[i] * ch.cz[i];
+    const float Ix = ch.Io[i][0], Iy = ch.Io[i][1], Iz = ch.Io[i][2];
+    T hvn[3] = {Ix * w[0] - mc * v[1], Iy * w[1] + mc * v[0], Iz * w[2]};
+    T hvf[3] = {m * v[0] + mc * w[1], m * v[1] - mc * w[0], m * v[2]};
+    T han[3] = {Ix * aw[0] - mc * av[1], Iy * aw[1] + mc * av[0], Iz * aw[2]};
+    T haf[3] = {m * av[0] + mc * aw[1], m * av[1] - mc * aw[0], m * av[2]};
+    // f = I a + v x* (I v), with v x* (hn, hf) = (w x hn + v x hf, w x hf)
+    fn[i][0] = han[0] + (w[1] * hvn[2] - w[2] * hvn[1]) + (v[1] * hvf[2] - v[2] * hvf[1]);
+    fn[i][1] = han[1] + (w[2] * hvn[0] - w[0] * hvn[2]) + (v[2] * hvf[0] - v[0] * hvf[2]);
+    fn[i][2] = han[2] + (w[0] * hvn[1] - w[1] * hvn[0]) + (v[0] * hvf[1] - v[1] * hvf[0]);
+    ff[i][0] = haf[0] + (w[1] * hvf[2] - w[2] * hvf[1]);
+    ff[i][1] = haf[1] + (w[2] * hvf[0] - w[0] * hvf[2]);
+    ff[i][2] = haf[2] + (w[0] * hvf[1] - w[1] * hvf[0]);
+  }
+#pragma unroll
+  for (int i = ND - 1; i >= 0; --i) {
+    tau[i] = (i & 1) ? fn[i][1] : fn[i][2];
+    if (i > 0) {
+      T n[3] = {fn[i][0], fn[i][1], fn[i][2]};
+      T f[3] = {ff[i][0], ff[i][1], ff[i][2]};
+      if (i & 1) force_to_parent<true>(cq[i], sq[i], ch.Lp[i], n, f);
+      else force_to_parent<false>(cq[i], sq[i], ch.Lp[i], n, f);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        fn[i - 1][a] = fn[i - 1][a] + n[a];
+        ff[i - 1][a] = ff[i - 1][a] + f[a];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Joint-space inertia by composite rigid bodies. Each composite is kept as mass
+// m, first moment h = m c and rotational inertia I (about the joint, symmetric,
+// stored xx yy zz xy xz yz) in its own frame. Only the lower triangle is used
+// by the Cholesky below, but the full matrix is written.
+// ---------------------------------------------------------------------------
+template <bool Y>
+__host__ __device__ inline void rotate_inertia(float c, float s, float *I) {
+  // I <- R I R^T for R the rotation about the joint axis.
+  float Rm[3][3];
+  if (Y) {
+    Rm[0][0] = c;  Rm[0][1] = 0.f; Rm[0][2] = s;
+    Rm[1][0] = 0.f; Rm[1][1] = 1.f; Rm[1][2] = 0.f;
+    Rm[2][0] = -s; Rm[2][1] = 0.f; Rm[2][2] = c;
+  } else {
+    Rm[0][0] = c;  Rm[0][1] = -s; Rm[0][2] = 0.f;
+    Rm[1][0] = s;  Rm[1][1] = c;  Rm[1][2] = 0.f;
+    Rm[2][0] = 0.f; Rm[2][1] = 0.f; Rm[2][2] = 1.f;
+  }
+  const float A[3][3] = {{I[0], I[3], I[4]}, {I[3], I[1], I[5]}, {I[4], I[5], I[2]}};
+  float T[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) T[i][j] = Rm[i][0] * A[0][j] + Rm[i][1] * A[1][j] + Rm[i][2] * A[2][j];
+  float B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) B[i][j] = T[i][0] * Rm[j][0] + T[i][1] * Rm[j][1] + T[i][2] * Rm[j][2];
+  I[0] = B[0][0]; I[1] = B[1][1]; I[2] = B[2][2];
+  I[3] = 0.5f * (B[0][1] + B[1][0]);
+  I[4] = 0.5f * (B[0][2] + B[2][0]);
+  I[5] = 0.5f * (B[1][2] + B[2][1]);
+}
+
+template <int ND>
+__host__ __device__ inline void crba(const Chain &ch, const float *cq, const float *sq, float (*M)[ND]) {
+  if (ch.model == 1) {
+#pragma unroll
+    for (int i = 0; i < ND; ++i)
+#pragma unroll
+      for (int j = 0; j < ND; ++j) M[i][j] = (i == j) ? 1.f : 0.f;
+    return;
+  }
+  float cm[ND], ch3[ND][3], cI[ND][6];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    cm[i] = ch.m[i];
+    ch3[i][0] = 0.f; ch3[i][1] = 0.f; ch3[i][2] = ch.m[i] * ch.cz[i];
+    cI[i][0] = ch.Io[i][0]; cI[i][1] = ch.Io[i][1]; cI[i][2] = ch.Io[i][2];
+    cI[i][3] = 0.f; cI[i][4] = 0.f; cI[i][5] = 0.f;
+  }
+  // Accumulate composites towards the base.
+#pragma unroll
+  for (int i = ND - 1; i >= 1; --i) {
+    float h[3] = {ch3[i][0], ch3[i][1], ch3[i][2]};
+    float I[6] = {cI[i][0], cI[i][1], cI[i][2], cI[i][3], cI[i][4], cI[i][5]};
+    if (i & 1) { rot_R<true>(cq[i], sq[i], h[0], h[1], h[2]); rotate_inertia<true>(cq[i], sq[i], I); }
+    else { rot_R<false>(cq[i], sq[i], h[0], h[1], h[2]); rotate_inertia<false>(cq[i], sq[i], I); }
+    // Shift from the child joint to the parent joint, r = (0, 0, L):
+    // I += -m [r]^2 - [h][r] - [r][h], h += m r.
+    const float L = ch.Lp[i], m = cm[i];
+    const float t = 2.f * h[2] * L + m * L * L;
+    I[0] += t;
+    I[1] += t;
+    I[4] -= h[0] * L;
+    I[5] -= h[1] * L;
+    h[2] += m * L;
+    cm[i - 1] += m;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) ch3[i - 1][a] += h[a];
+#pragma unroll
+    for (int a = 0; a < 6; ++a) cI[i - 1][a] += I[a];
+  }
+  // Column i: force of unit motion about joint i, carried towards the base.
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    float n[3], f[3];
+    if (i & 1) {  // e = e_y: n = I e_y, f = e_y x h
+      n[0] = cI[i][3]; n[1] = cI[i][1]; n[2] = cI[i][5];
+      f[0] = ch3[i][2]; f[1] = 0.f; f[2] = -ch3[i][0];
+      M[i][i] = n[1];
+    } else {      // e = e_z
+      n[0] = cI[i][4]; n[1] = cI[i][5]; n[2] = cI[i][2];
+      f[0] = -ch3[i][1]; f[1] = ch3[i][0]; f[2] = 0.f;
+      M[i][i] = n[2];
+    }
+#pragma unroll
+    for (int j = i; j >= 1; --j) {
+      if (j & 1) force_to_parent<true>(cq[j], sq[j], ch.Lp[j], n, f);
+      else force_to_parent<false>(cq[j], sq[j], ch.Lp[j], n, f);
+      const float mij = ((j - 1) & 1) ? n[1] : n[2];
+      M[i][j - 1] = mij;
+      M[j - 1][i] = mij;
+    }
+  }
+}
+
+// In-place Cholesky of an SPD ND x ND matrix (lower triangle); returns false if
+// a pivot is not positive.
+template <int ND>
+__host__ __device__ inline bool cholesky(float (*A)[ND]) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    float s = A[j][j];
+#pragma unroll
+    for (int k = 0; k < j; ++k) s -= A[j][k] * A[j][k];
+    ok = ok && (s > 0.f);
+    const float d = sqrtf(fmaxf(s, 1e-30f));
+    const float inv = 1.f / d;
+    A[j][j] = d;
+#pragma unroll
+    for (int i = j + 1; i < ND; ++i) {
+      float t = A[i][j];
+#pragma unroll
+      for (int k = 0; k < j; ++k) t -= A[i][k] * A[j][k];
+      A[i][j] = t * inv;
+    }
+  }
+  return ok;
+}
+
+template <int ND>
+__host__ __device__ inline void chol_solve(const float (*L)[ND], float *b) {
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    float s = b[i];
+#pragma unroll
+    for (int k = 0; k < i; ++k) s -= L[i][k] * b[k];
+    b[i] = s / L[i][i];
+  }
+#pragma unroll
+  for (int i = ND - 1; i >= 0; --i) {
+    float s = b[i];
+#pragma unroll
+    for (int k = i + 1; k < ND; ++k) s -= L[k][i] * b[k];
+    b[i] = s / L[i][i];
+  }
+}
+
+// Forward dynamics qdd = M(q)^-1 (tau - b(q, qd)). Leaves the Cholesky factor
+// of M in L for later solves. Returns false if M is not positive definite.
+template <int ND>
+__host__ __device__ inline bool forward_dynamics(const Chain &ch, const float *q, const float *qd,
+                                                 const float *tau, float *qdd, float (*L)[ND]) {
+  float cq[ND], sq[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) sin_cos(q[i], &sq[i], &cq[i]);
+  crba<ND>(ch, cq, sq, L);
+  float zero[ND], b[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) zero[i] = 0.f;
+  rnea<ND, float>(ch, q, qd, zero, true, b);
+  const bool ok = cholesky<ND>(L);
+#pragma unroll
+  for (int i = 0; i < ND; ++i) qdd[i] = tau[i] - b[i];
+  chol_solve<ND>(L, qdd);
+  return ok;
+}
+
+// One column of the Jacobian of forward dynamics: direction dir < ND is q_dir,
+// dir >= ND is qd_(dir-ND). Uses the factor L and qdd from forward_dynamics.
+template <int ND>
+__host__ __device__ inline void fd_jacobian_column(const Chain &ch, const float *q, const float *qd,
+                                                   const float *qdd, const float (*L)[ND], int dir, float *col) {
+  df Q[ND], QD[ND], QDD[ND], TAU[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) {
+    Q[i] = {q[i], (dir == i) ? 1.f : 0.f};
+    QD[i] = {qd[i], (dir == ND + i) ? 1.f : 0.f};
+    QDD[i] = {qdd[i], 0.f};
+  }
+  rnea<ND, df>(ch, Q, QD, QDD, true, TAU);
+#pragma unroll
+  for (int i = 0; i < ND; ++i) col[i] = -TAU[i].d;
+  chol_solve<ND>(L, col);
+}
+
+}  // namespace gato
