@@ -1,0 +1,206 @@
+/*
+ * gato.h - C ABI of the MI355X (gfx950) batched trajectory-optimisation library.
+ *
+ * The library runs the data-parallel hot path of GATO (Du, Adabag,
+ * Bravo-Palacios, Plancher, arXiv 2510.07625): SQP iterations over a batch of M
+ * independent trajectory optimisation problems, each iteration forming the QP
+ * of Eq. (1) from the rigid-body dynamics at every knot point, reducing its KKT
+ * system (Eq. (2)) to the block-tridiagonal Schur complement of Eqs. (4)-(6),
+ * solving it with the stair-preconditioned conjugate gradient (Sec. II-B,
+ * Sec. III-B), recovering the step (Eq. (4)) and choosing it with the L1-merit
+ * line search of Eqs. (3) and (7) (Algorithm 1).
+ *
+ * Conventions shared by every entry point:
+ *   - Sizes: n = DoF (1..GATO_MAX_DOF), nx = 2n (state [q; qd]), nu = n
+ *     (joint torques). N counts knot points: states x_0..x_{N-1} and controls
+ *     u_0..u_{N-2} (the paper's x_0..x_N has N+1 states; here N is the number
+ *     of states).
+ *   - Device buffers (d_*) are caller-owned device pointers (e.g. torch
+ *     data_ptr()), float32, row-major, padded per solve to the batch maxima:
+ *       X     [M][N_max][nx_max]     U   [M][N_max-1][nu_max]
+ *       xs    [M][nx_max]            goal[M][nu_max]  (joint-angle goal)
+ *     nx_max = 2 n_max, nu_max = n_max. Entries beyond a solve's own n / N are
+ *     neither read nor written.
+ *   - Ordering: every call is stream-ordered on the HIP stream given at create
+ *     time and returns before the GPU finishes, except where stated.
+ *   - Errors: functions return an int status (GATO_OK or a negative code) and
+ *     never throw; gato_last_error() gives a message for the calling thread.
+ *     Per-solve numerical trouble sets status bits and never fails the batch.
+ *   - A batch handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef GATO_H
+#define GATO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define GATO_OK 0
+#define GATO_EINVAL (-1)       /* invalid argument; nothing was launched */
+#define GATO_ENOMEM (-2)       /* device allocation failed */
+#define GATO_EDEVICE (-3)      /* HIP runtime error (launch, copy, sync) */
+#define GATO_EUNSUPPORTED (-4) /* shape outside the compiled kernels */
+
+/* Per-solve status bits (gato_solve_stats.status). */
+#define GATO_ST_PCG_MAXITER 1u /* PCG hit its iteration cap before the tolerance */
+#define GATO_ST_NONFINITE 2u   /* non-finite step or merit; the iterate was kept */
+#define GATO_ST_NO_DESCENT 4u  /* no candidate step lowered the merit (stepped anyway) */
+
+/* Robot models. */
+#define GATO_MODEL_SERIAL_CHAIN 0        /* revolute chain, joint axes z, y, z, y, ... */
+#define GATO_MODEL_DOUBLE_INTEGRATOR 1   /* unit masses, qdd = u - k T q, T = tridiag(-1, 2, -1) */
+
+#define GATO_MAX_DOF 7
+#define GATO_MAX_KNOTS 128
+#define GATO_MAX_ALPHA 16
+
+typedef struct gato_batch gato_batch; /* opaque, library-owned */
+
+/*
+ * Robot description (host memory, copied at create time).
+ * Serial chain: joint i rotates about z (even i) or y (odd i) of its own frame;
+ * frame i sits at length_{i-1} along +z of frame i-1; link i has its centre of
+ * mass at length_i/2 on +z and diagonal inertia (Ixx, Iyy, Izz) about it;
+ * gravity acts along -z of the base. Stands in for the manipulators of Sec. IV.
+ */
+typedef struct {
+  int model;           /* GATO_MODEL_* */
+  int n_dof;           /* 1..GATO_MAX_DOF */
+  const double *link;  /* [n_dof][5]: length, mass, Ixx, Iyy, Izz (serial chain) */
+  double gravity;      /* m/s^2 along -z (serial chain) */
+  double spring_k;     /* k (double integrator) */
+} gato_robot;
+
+/*
+ * One problem of Eq. (1): horizon, Euler time step h and the diagonal tracking
+ * weights Q (stages 0..N-2), R and Q_N (knot N-1). The tracked state is
+ * [q_goal; 0]. Host memory, copied at create time.
+ */
+typedef struct {
+  int N;               /* knot points, 2..GATO_MAX_KNOTS */
+  double dt;           /* time step h > 0 */
+  const double *Q_diag;  /* [2 n_dof], > 0 */
+  const double *R_diag;  /* [n_dof], > 0 */
+  const double *QN_diag; /* [2 n_dof], > 0 */
+} gato_problem;
+
+/*
+ * Solver settings. The paper defers its values to its code; the defaults set
+ * by gato_default_params are: sqp_iters 10, pcg_tol 1e-5, pcg_max_iter 0
+ * (= N nx), mu 10, beta 2, n_alpha 8 (alpha_i = beta^-i, i = 0..7), rho 0,
+ * schur_fp64 1, warm_lambda 1.
+ */
+typedef struct {
+  int sqp_iters;       /* SQP iterations per gato_solve */
+  double pcg_tol;      /* PCG stops when r^T P r <= tol^2 gamma^T P gamma */
+  int pcg_max_iter;    /* 0: N * nx */
+  double mu;           /* merit weight on ||c||_1, Eq. (3) */
+  double beta;         /* > 1, Eq. (7) */
+  int n_alpha;         /* candidate steps, 1..GATO_MAX_ALPHA */
+  double rho;          /* added to the diagonal of every Q_k (incl. Q_N) */
+  int schur_fp64;      /* 1: Schur complement, PCG vectors and dot products in
+                          FP64 (preconditioner applied in FP32); 0: all FP32 */
+  int warm_lambda;     /* 1: PCG starts from the solve's previous multipliers */
+} gato_params;
+
+/* Per solve and SQP iteration. */
+typedef struct {
+  float merit0;        /* merit at the iterate before the step */
+  float merit;         /* merit of the accepted candidate */
+  float alpha;         /* accepted step */
+  int pcg_iters;       /* PCG iterations of this SQP iteration */
+  unsigned status;     /* GATO_ST_* bits */
+} gato_solve_stats;
+
+/* Fills *p with the defaults listed above. */
+void gato_default_params(gato_params *p);
+
+/*
+ * Device workspace one solve of this shape needs (bytes). Pure host
+ * computation; usable for memory-based admission. Returns 0 for invalid input.
+ */
+size_t gato_workspace_bytes(int n_dof, int N, const gato_params *p);
+
+/*
+ * Creates a batch of M solves (Algorithm 1's M). robots[M] and probs[M] are
+ * host arrays; solves may differ in n_dof and N (an uneven batch is launched
+ * as one persistent kernel). p may be NULL for the defaults. hip_stream is a
+ * hipStream_t (NULL: the null stream). Allocates and zeroes the device
+ * workspace (including the per-solve PCG warm-start multipliers) and
+ * synchronises. On success *out owns everything until gato_batch_destroy.
+ * Errors: GATO_EINVAL (sizes, weights, NULL pointers), GATO_ENOMEM,
+ * GATO_EDEVICE.
+ */
+int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs, const gato_params *p,
+                      void *hip_stream, gato_batch **out);
+
+/* Frees all device memory of the batch (synchronises its stream). NULL is ignored. */
+void gato_batch_destroy(gato_batch *b);
+
+/* Number of solves, and the padded maxima n_max, N_max of the batch. */
+int gato_batch_shape(const gato_batch *b, int *M, int *n_max, int *N_max);
+
+/*
+ * Algorithm 1: runs p->sqp_iters SQP iterations on every solve. d_X / d_U hold
+ * the initial trajectories on entry and X*, U* on exit (in place); d_xs and
+ * d_goal hold each solve's start state and joint goal. If h_stats is non-NULL
+ * it receives [M][sqp_iters] per-iteration statistics and the call
+ * synchronises; otherwise the call is asynchronous. Returns GATO_OK, or 1 if
+ * some solve set a status bit (only known when h_stats is given).
+ */
+int gato_solve(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U,
+               gato_solve_stats *h_stats);
+
+/*
+ * Asynchronous form of gato_solve with a caller-chosen iteration count and
+ * device-side statistics: d_stats (device, [M][n_iters] gato_solve_stats, or
+ * NULL). No host synchronisation and no host I/O.
+ */
+int gato_step(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U, int n_iters,
+              gato_solve_stats *d_stats);
+
+/*
+ * The same iterations as gato_step, one solve per kernel launch (M launches
+ * in order on the batch stream): the plain one-solve-per-launch form the
+ * batched launch is compared against. Same arguments and results.
+ */
+int gato_step_plain(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U,
+                    int n_iters, gato_solve_stats *d_stats);
+
+/*
+ * Stage entry point: the QP data of Eq. (1) at (X, U) for every solve, as the
+ * kernel forms it in the first phase of an SQP iteration (dynamics,
+ * derivatives and Euler discretisation). Outputs are device buffers:
+ *   d_A [M][N_max-1][nx_max][nx_max], d_B [M][N_max-1][nx_max][nu_max],
+ *   d_e [M][N_max-1][nx_max]  (e_k = f(x_k, u_k) - x_{k+1}).
+ */
+int gato_debug_lq(gato_batch *b, const float *d_xs, const float *d_goal, const float *d_X, const float *d_U,
+                  float *d_A, float *d_B, float *d_e);
+
+/*
+ * Stage entry point: the KKT solve of one SQP step (Eqs. (4)-(6) and the PCG)
+ * on caller-given QP data in the layout of gato_debug_lq, plus
+ *   d_q [M][N_max][nx_max] (state gradients), d_r [M][N_max-1][nu_max]
+ *   (control gradients), d_c0 [M][nx_max] (x_s - x_0).
+ * Writes d_dX [M][N_max][nx_max], d_dU [M][N_max-1][nu_max], d_lambda
+ * [M][N_max][nx_max] (double) and, if non-NULL, d_pcg_iters [M] (int).
+ * The PCG starts from zero multipliers.
+ */
+int gato_debug_kkt(gato_batch *b, const float *d_A, const float *d_B, const float *d_e, const float *d_q,
+                   const float *d_r, const float *d_c0, float *d_dX, float *d_dU, double *d_lambda,
+                   int *d_pcg_iters);
+
+/* Resets the PCG warm-start multipliers of every solve to zero (stream-ordered). */
+int gato_reset_warm_start(gato_batch *b);
+
+/* Thread-local message describing the last non-OK return (never NULL). */
+const char *gato_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GATO_H */

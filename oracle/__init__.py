@@ -92,6 +92,8 @@ def lib():
         L.orc_pcg_dense.argtypes = [C.c_int, dp, dp, dp, dp, C.c_double, C.c_int, C.POINTER(C.c_int)]
         L.orc_qp_step.argtypes = [rp, pp, C.c_double, dp, dp, dp, dp, C.c_int, C.c_double, C.c_int, dp, dp,
                                   C.POINTER(C.c_int), dp]
+        L.orc_kkt_from_lq.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, C.c_int, dp, dp,
+                                      dp]
         L.orc_merit.argtypes = [rp, pp, dp, dp, dp, dp, C.c_double, dp, dp]
         L.orc_merit.restype = C.c_double
         L.orc_sqp.argtypes = [rp, pp, C.POINTER(_Params), dp, dp, dp, dp, dp, C.POINTER(_IterLog), dp]
@@ -252,6 +254,32 @@ def qp_step(s, X, U, mode: int = 0, rho: float = 0.0, pcg_tol: float = 1e-6, pcg
         raise FloatingPointError("QP step failed")
     dX, dU = split_dz(s, dZ)
     return dX, dU, lam.reshape(N, nx), its.value, res.value
+
+
+def kkt_from_lq(A, B, e, q, r, c0, Qh, Rh, mode: int = 0):
+    """KKT solve (Eq. (2)) on given QP data; returns (dX [N, nx], dU [N-1, nu], lambda [N, nx], residual).
+
+    Qh is the [N, nx] Hessian diagonal of the states (Q_k + rho, Q_N + rho at
+    the last knot), Rh the [nu] control Hessian diagonal.
+    """
+    A, B, e, q, r, c0, Qh, Rh = (_f64(v) for v in (A, B, e, q, r, c0, Qh, Rh))
+    N, nx = q.shape
+    nu = Rh.shape[0]
+    dZ = np.zeros(N * nx + (N - 1) * nu)
+    lam = np.zeros(N * nx)
+    res = C.c_double(0.0)
+    rc = lib().orc_kkt_from_lq(nx, nu, N, _ptr(A), _ptr(B), _ptr(e), _ptr(q), _ptr(r), _ptr(c0), _ptr(Qh),
+                               _ptr(Rh), int(mode), _ptr(dZ), _ptr(lam), C.byref(res))
+    if rc != 0:
+        raise FloatingPointError("KKT solve failed")
+    dX = np.zeros((N, nx))
+    dU = np.zeros((N - 1, nu))
+    for k in range(N):
+        o = k * (nx + nu)
+        dX[k] = dZ[o:o + nx]
+        if k < N - 1:
+            dU[k] = dZ[o + nx:o + nx + nu]
+    return dX, dU, lam.reshape(N, nx), res.value
 
 
 def merit(s, X, U, mu: float = 10.0):

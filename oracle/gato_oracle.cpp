@@ -786,21 +786,49 @@ bool solve_riccati(const Lq &lq, double *dZ, double *lam) {
       for (int j = 0; j < nx; ++j) Kk[i * nx + j] = rhs[(size_t)i * (nx + 1) + j];
       dk[i] = rhs[(size_t)i * (nx + 1) + nx];
     }
-    // P_k = Q + A^T P A - G_ux^T K ; p_k = q + A^T v - G_ux^T d
+    // Joseph form, with Acl = A - B K:
+    //   P_k = Q + K^T R K + Acl^T P_{k+1} Acl,
+    //   p_k = q + K^T (R d - r) + Acl^T (P_{k+1} (e - B d) + p_{k+1}).
+    // It equals the plain update Q + A^T P A - G_ux^T K for the optimal K but
+    // stays symmetric positive definite in rounding; the plain form loses
+    // symmetry and diverges over long horizons when A is open-loop unstable.
     double *Pk = &P[(size_t)k * nx * nx];
     double *pk = &p[(size_t)k * nx];
+    std::vector<double> Acl((size_t)nx * nx), PAcl((size_t)nx * nx), w(nx);
+    for (int i = 0; i < nx; ++i)
+      for (int j = 0; j < nx; ++j) {
+        double t = A[i * nx + j];
+        for (int m = 0; m < nu; ++m) t -= B[i * nu + m] * Kk[m * nx + j];
+        Acl[i * nx + j] = t;
+      }
+    matmul(P1, Acl.data(), PAcl.data(), nx, nx, nx);
+    for (int i = 0; i < nx; ++i) {               // w = P_{k+1} (e - B d) + p_{k+1}
+      double t = p1[i];
+      for (int j = 0; j < nx; ++j) {
+        double ebd = e[j];
+        for (int m = 0; m < nu; ++m) ebd -= B[j * nu + m] * dk[m];
+        t += P1[i * nx + j] * ebd;
+      }
+      w[i] = t;
+    }
     for (int i = 0; i < nx; ++i) {
       for (int j = 0; j < nx; ++j) {
         double t = (i == j) ? lq.Qh[(size_t)k * nx + i] : 0.0;
-        for (int m = 0; m < nx; ++m) t += A[m * nx + i] * PA[m * nx + j];
-        for (int m = 0; m < nu; ++m) t -= Gux[m * nx + i] * Kk[m * nx + j];
+        for (int m = 0; m < nu; ++m) t += Kk[m * nx + i] * lq.Rh[m] * Kk[m * nx + j];
+        for (int m = 0; m < nx; ++m) t += Acl[m * nx + i] * PAcl[m * nx + j];
         Pk[i * nx + j] = t;
       }
       double t = lq.q[(size_t)k * nx + i];
-      for (int m = 0; m < nx; ++m) t += A[m * nx + i] * v[m];
-      for (int m = 0; m < nu; ++m) t -= Gux[m * nx + i] * dk[m];
+      for (int m = 0; m < nu; ++m) t += Kk[m * nx + i] * (lq.Rh[m] * dk[m] - lq.r[(size_t)k * nu + m]);
+      for (int m = 0; m < nx; ++m) t += Acl[m * nx + i] * w[m];
       pk[i] = t;
     }
+    for (int i = 0; i < nx; ++i)
+      for (int j = i + 1; j < nx; ++j) {
+        const double avg = 0.5 * (Pk[i * nx + j] + Pk[j * nx + i]);
+        Pk[i * nx + j] = avg;
+        Pk[j * nx + i] = avg;
+      }
   }
   // Forward roll from dx_0 = x_s - x_0; lambda_k = P_k dx_k + p_k.
   std::vector<double> dx(lq.c0);
@@ -981,6 +1009,28 @@ int orc_qp_step(const orc_robot *rb, const orc_problem *pr, double rho, const do
     ok = solve_riccati(lq, dZ, lam);
   }
   if (pcg_iters) *pcg_iters = its;
+  if (kkt_res) *kkt_res = kkt_residual(lq, dZ, lam);
+  return ok ? 0 : -1;
+}
+
+// The KKT solve of one SQP step on caller-given QP data (Eq. (2)):
+// A[N-1][nx][nx], B[N-1][nx][nu], e[N-1][nx], q[N][nx], r[N-1][nu], c0[nx],
+// Hessian diagonals Qh[N][nx] and Rh[nu]. mode 0 dense LU, 2 Riccati.
+// Writes dZ [nz] and lambda [N nx].
+int orc_kkt_from_lq(int nx, int nu, int N, const double *A, const double *B, const double *e, const double *q,
+                    const double *r, const double *c0, const double *Qh, const double *Rh, int mode, double *dZ,
+                    double *lam, double *kkt_res) {
+  Lq lq;
+  lq.n = nu; lq.nx = nx; lq.nu = nu; lq.N = N; lq.ok = true;
+  lq.A.assign(A, A + (size_t)(N - 1) * nx * nx);
+  lq.B.assign(B, B + (size_t)(N - 1) * nx * nu);
+  lq.e.assign(e, e + (size_t)(N - 1) * nx);
+  lq.q.assign(q, q + (size_t)N * nx);
+  lq.r.assign(r, r + (size_t)(N - 1) * nu);
+  lq.Qh.assign(Qh, Qh + (size_t)N * nx);
+  lq.Rh.assign(Rh, Rh + nu);
+  lq.c0.assign(c0, c0 + nx);
+  const bool ok = (mode == 2) ? solve_riccati(lq, dZ, lam) : solve_kkt_dense(lq, dZ, lam);
   if (kkt_res) *kkt_res = kkt_residual(lq, dZ, lam);
   return ok ? 0 : -1;
 }

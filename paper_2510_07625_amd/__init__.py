@@ -1,0 +1,295 @@
+"""Python binding of libgato (include/gato.h): argument marshalling only.
+
+Every step of the SQP iteration runs in the HIP kernels of libgato.so; this
+module checks tensor shapes and dtypes, builds the C structs and passes device
+pointers. PyTorch is used for device memory and streams only. There is no CPU
+fallback: if the library is missing, loading it raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgato.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "gato.h")
+
+GATO_OK, GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE, GATO_EUNSUPPORTED = 0, -1, -2, -3, -4
+ST_PCG_MAXITER, ST_NONFINITE, ST_NO_DESCENT = 1, 2, 4
+MODEL_SERIAL_CHAIN, MODEL_DOUBLE_INTEGRATOR = 0, 1
+MAX_DOF, MAX_KNOTS, MAX_ALPHA = 7, 128, 16
+
+
+class GatoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"gato error {code}: {msg}")
+        self.code = code
+
+
+class _Robot(C.Structure):
+    _fields_ = [("model", C.c_int), ("n_dof", C.c_int), ("link", C.POINTER(C.c_double)),
+                ("gravity", C.c_double), ("spring_k", C.c_double)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("N", C.c_int), ("dt", C.c_double), ("Q_diag", C.POINTER(C.c_double)),
+                ("R_diag", C.POINTER(C.c_double)), ("QN_diag", C.POINTER(C.c_double))]
+
+
+class _Params(C.Structure):
+    _fields_ = [("sqp_iters", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int),
+                ("mu", C.c_double), ("beta", C.c_double), ("n_alpha", C.c_int), ("rho", C.c_double),
+                ("schur_fp64", C.c_int), ("warm_lambda", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("merit0", C.c_float), ("merit", C.c_float), ("alpha", C.c_float), ("pcg_iters", C.c_int),
+                ("status", C.c_uint)]
+
+
+STATS_DTYPE = np.dtype([("merit0", np.float32), ("merit", np.float32), ("alpha", np.float32),
+                        ("pcg_iters", np.int32), ("status", np.uint32)])
+
+# Entry points declared in include/gato.h.
+EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "gato_batch_destroy",
+           "gato_batch_shape", "gato_solve", "gato_step", "gato_step_plain", "gato_debug_lq",
+           "gato_debug_kkt", "gato_reset_warm_start", "gato_last_error")
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Loads libgato.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2510_07625_amd/build.py "
+                               "(or __graft_entry__.build()); there is no fallback path")
+        L = C.CDLL(LIB_PATH)
+        vp, ip = C.c_void_p, C.c_int
+        L.gato_default_params.argtypes = [C.POINTER(_Params)]
+        L.gato_default_params.restype = None
+        L.gato_workspace_bytes.argtypes = [ip, ip, C.POINTER(_Params)]
+        L.gato_workspace_bytes.restype = C.c_size_t
+        L.gato_batch_create.argtypes = [ip, C.POINTER(_Robot), C.POINTER(_Problem), C.POINTER(_Params), vp,
+                                        C.POINTER(vp)]
+        L.gato_batch_destroy.argtypes = [vp]
+        L.gato_batch_destroy.restype = None
+        L.gato_batch_shape.argtypes = [vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]
+        L.gato_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(SolveStats)]
+        L.gato_step.argtypes = [vp, vp, vp, vp, vp, ip, vp]
+        L.gato_step_plain.argtypes = [vp, vp, vp, vp, vp, ip, vp]
+        L.gato_debug_lq.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+        L.gato_debug_kkt.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.gato_reset_warm_start.argtypes = [vp]
+        L.gato_last_error.argtypes = []
+        L.gato_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise GatoError(rc, lib().gato_last_error().decode())
+    return rc
+
+
+@dataclass
+class Params:
+    """Mirror of gato_params (defaults of gato_default_params)."""
+
+    sqp_iters: int = 10
+    pcg_tol: float = 1e-5
+    pcg_max_iter: int = 0
+    mu: float = 10.0
+    beta: float = 2.0
+    n_alpha: int = 8
+    rho: float = 0.0
+    schur_fp64: int = 1
+    warm_lambda: int = 1
+
+    def c(self) -> _Params:
+        return _Params(self.sqp_iters, self.pcg_tol, self.pcg_max_iter, self.mu, self.beta, self.n_alpha,
+                       self.rho, self.schur_fp64, self.warm_lambda)
+
+
+@dataclass
+class Robot:
+    n_dof: int
+    link: np.ndarray = None          # [n, 5] length, mass, Ixx, Iyy, Izz
+    model: int = MODEL_SERIAL_CHAIN
+    gravity: float = 9.81
+    spring_k: float = 0.0
+
+
+@dataclass
+class Problem:
+    N: int
+    dt: float
+    Q_diag: np.ndarray
+    R_diag: np.ndarray
+    QN_diag: np.ndarray
+
+
+def workspace_bytes(n_dof: int, N: int, params: Params | None = None) -> int:
+    p = (params or Params()).c()
+    return int(lib().gato_workspace_bytes(n_dof, N, C.byref(p)))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _dptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+class Batch:
+    """A batch of M trajectory-optimisation solves living on one GPU."""
+
+    def __init__(self, robots: Sequence[Robot], problems: Sequence[Problem], params: Params | None = None,
+                 stream=None):
+        import torch  # device memory and streams only
+
+        if len(robots) != len(problems) or not robots:
+            raise ValueError("robots and problems must be non-empty and of equal length")
+        self.params = params or Params()
+        self.M = len(robots)
+        keep = []
+        rob = (_Robot * self.M)()
+        prob = (_Problem * self.M)()
+        for i, (r, p) in enumerate(zip(robots, problems)):
+            link = _f64(r.link if r.link is not None else np.zeros((r.n_dof, 5))).reshape(-1)
+            Q, R, QN = _f64(p.Q_diag), _f64(p.R_diag), _f64(p.QN_diag)
+            keep += [link, Q, R, QN]
+            rob[i] = _Robot(int(r.model), int(r.n_dof), link.ctypes.data_as(C.POINTER(C.c_double)),
+                            float(r.gravity), float(r.spring_k))
+            prob[i] = _Problem(int(p.N), float(p.dt), Q.ctypes.data_as(C.POINTER(C.c_double)),
+                               R.ctypes.data_as(C.POINTER(C.c_double)), QN.ctypes.data_as(C.POINTER(C.c_double)))
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        handle = C.c_void_p()
+        prm = self.params.c()
+        _check(lib().gato_batch_create(self.M, rob, prob, C.byref(prm), C.c_void_p(self.stream.cuda_stream),
+                                       C.byref(handle)))
+        self._h = handle
+        M, n, N = C.c_int(), C.c_int(), C.c_int()
+        _check(lib().gato_batch_shape(self._h, C.byref(M), C.byref(n), C.byref(N)))
+        self.n_max, self.N_max = n.value, N.value
+        self.nx_max, self.nu_max = 2 * self.n_max, self.n_max
+
+    @classmethod
+    def from_solves(cls, solves, params: Params | None = None, stream=None) -> "Batch":
+        """Builds a batch from objects with the fields of workload.Solve."""
+        robots = [Robot(s.n, s.links, s.model, s.gravity, s.spring_k) for s in solves]
+        problems = [Problem(s.N, s.dt, s.Qd, s.Rd, s.QNd) for s in solves]
+        return cls(robots, problems, params, stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gato_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- shape checks ------------------------------------------------------
+    def _chk(self, t, shape, dtype=None):
+        import torch
+        dtype = dtype or torch.float32
+        if t is None:
+            raise ValueError("tensor is None")
+        if not t.is_cuda or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected contiguous {dtype} cuda tensor of shape {tuple(shape)}, got "
+                             f"{t.dtype} {tuple(t.shape)} on {t.device}")
+        return t
+
+    def _io(self, xs, goal, X, U):
+        M, N, nx, nu = self.M, self.N_max, self.nx_max, self.nu_max
+        self._chk(xs, (M, nx))
+        self._chk(goal, (M, nu))
+        self._chk(X, (M, N, nx))
+        self._chk(U, (M, N - 1, nu))
+
+    # ---- entry points ------------------------------------------------------
+    def solve(self, xs, goal, X, U, stats: bool = True):
+        """gato_solve: sqp_iters iterations in place on X, U; returns per-iteration stats."""
+        self._io(xs, goal, X, U)
+        if stats:
+            h = (SolveStats * (self.M * max(self.params.sqp_iters, 1)))()
+            _check(lib().gato_solve(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), h))
+            arr = np.frombuffer(h, dtype=STATS_DTYPE).copy()
+            return arr.reshape(self.M, max(self.params.sqp_iters, 1))
+        _check(lib().gato_solve(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), None))
+        return None
+
+    def step(self, xs, goal, X, U, n_iters: int, d_stats=None, plain: bool = False):
+        """gato_step / gato_step_plain: asynchronous, device-side stats (uint8 tensor or None)."""
+        self._io(xs, goal, X, U)
+        fn = lib().gato_step_plain if plain else lib().gato_step
+        _check(fn(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), int(n_iters), _dptr(d_stats)))
+
+    def stats_buffer(self, n_iters: int):
+        import torch
+        return torch.zeros(self.M * n_iters * STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+
+    @staticmethod
+    def decode_stats(buf, M: int, n_iters: int) -> np.ndarray:
+        return np.frombuffer(buf.cpu().numpy().tobytes(), dtype=STATS_DTYPE).reshape(M, n_iters)
+
+    def debug_lq(self, xs, goal, X, U):
+        import torch
+        self._io(xs, goal, X, U)
+        M, N, nx, nu = self.M, self.N_max, self.nx_max, self.nu_max
+        A = torch.zeros((M, N - 1, nx, nx), dtype=torch.float32, device="cuda")
+        B = torch.zeros((M, N - 1, nx, nu), dtype=torch.float32, device="cuda")
+        e = torch.zeros((M, N - 1, nx), dtype=torch.float32, device="cuda")
+        _check(lib().gato_debug_lq(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), _dptr(A), _dptr(B),
+                                   _dptr(e)))
+        return A, B, e
+
+    def debug_kkt(self, A, B, e, q, r, c0):
+        import torch
+        M, N, nx, nu = self.M, self.N_max, self.nx_max, self.nu_max
+        self._chk(A, (M, N - 1, nx, nx))
+        self._chk(B, (M, N - 1, nx, nu))
+        self._chk(e, (M, N - 1, nx))
+        self._chk(q, (M, N, nx))
+        self._chk(r, (M, N - 1, nu))
+        self._chk(c0, (M, nx))
+        dX = torch.zeros((M, N, nx), dtype=torch.float32, device="cuda")
+        dU = torch.zeros((M, N - 1, nu), dtype=torch.float32, device="cuda")
+        lam = torch.zeros((M, N, nx), dtype=torch.float64, device="cuda")
+        its = torch.zeros((M,), dtype=torch.int32, device="cuda")
+        _check(lib().gato_debug_kkt(self._h, _dptr(A), _dptr(B), _dptr(e), _dptr(q), _dptr(r), _dptr(c0),
+                                    _dptr(dX), _dptr(dU), _dptr(lam), _dptr(its)))
+        return dX, dU, lam, its
+
+    def reset_warm_start(self):
+        _check(lib().gato_reset_warm_start(self._h))
+
+
+def pack_inputs(solves, device="cuda"):
+    """Pads a list of problems into the boundary layout: xs, goal, X, U tensors."""
+    import torch
+    M = len(solves)
+    n_max = max(s.n for s in solves)
+    N_max = max(s.N for s in solves)
+    nx, nu = 2 * n_max, n_max
+    xs = np.zeros((M, nx), np.float32)
+    goal = np.zeros((M, nu), np.float32)
+    X = np.zeros((M, N_max, nx), np.float32)
+    U = np.zeros((M, N_max - 1, nu), np.float32)
+    for i, s in enumerate(solves):
+        xs[i, :2 * s.n] = s.xs
+        goal[i, :s.n] = s.qgoal
+        X[i, :s.N, :2 * s.n] = s.X0
+        U[i, :s.N - 1, :s.n] = s.U0
+    t = lambda a: torch.from_numpy(a).to(device)
+    return t(xs), t(goal), t(X), t(U)

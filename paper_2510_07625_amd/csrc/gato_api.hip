@@ -1,0 +1,440 @@
+// Host side of the C ABI declared in include/gato.h: argument validation,
+// per-solve descriptors, workspace layout and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gato.h"
+#include "gato_internal.hpp"
+#include "gato_launch.hpp"
+
+namespace gato {
+hipError_t launch_sqp_n3(int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_n6(int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_n7(int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
+
+hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s) {
+  switch (nd) {
+    case 3: return launch_sqp_n3(kpt, f64, grid, a, s);
+    case 6: return launch_sqp_n6(kpt, f64, grid, a, s);
+    case 7: return launch_sqp_n7(kpt, f64, grid, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+}  // namespace gato
+
+using gato::SolveDesc;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(e == hipErrorOutOfMemory ? GATO_ENOMEM : GATO_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool dof_supported(int n) { return n == 3 || n == 6 || n == 7; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t offA, offB, offD, total;
+};
+
+Layout layout_for(int n, int N) {
+  const size_t nx = 2 * (size_t)n, nu = (size_t)n;
+  Layout l;
+  l.offA = 0;
+  l.offB = align256(l.offA + (size_t)(N - 1) * nx * nx * sizeof(float));
+  l.offD = align256(l.offB + (size_t)(N - 1) * nx * nu * sizeof(float));
+  l.total = align256(l.offD + (size_t)N * nx * nx * sizeof(double));
+  return l;
+}
+
+bool pos_finite(double x) { return std::isfinite(x) && x > 0.0; }
+
+}  // namespace
+
+struct gato_batch {
+  int M = 0, n_max = 0, N_max = 0;
+  gato_params p{};
+  hipStream_t stream = nullptr;
+  std::vector<SolveDesc> desc;
+  SolveDesc *d_desc = nullptr;
+  char *d_ws = nullptr;
+  size_t ws_bytes = 0;
+  double *d_lam = nullptr;   // [M][N_max][nx_max]
+  size_t lam_bytes = 0;
+  gato_solve_stats *d_stats = nullptr;
+  size_t stats_cap = 0;
+  // Launch groups: solves of one (n, kpt) shape, longest horizon first.
+  struct Group {
+    int n, kpt, count;
+    int *d_order;
+  };
+  std::vector<Group> groups;
+};
+
+extern "C" {
+
+void gato_default_params(gato_params *p) {
+  if (!p) return;
+  p->sqp_iters = 10;
+  p->pcg_tol = 1e-5;
+  p->pcg_max_iter = 0;
+  p->mu = 10.0;
+  p->beta = 2.0;
+  p->n_alpha = 8;
+  p->rho = 0.0;
+  p->schur_fp64 = 1;
+  p->warm_lambda = 1;
+}
+
+const char *gato_last_error(void) { return g_err.c_str(); }
+
+static int check_params(const gato_params *p) {
+  if (p->sqp_iters < 0) return fail(GATO_EINVAL, "sqp_iters must be >= 0");
+  if (!pos_finite(p->pcg_tol)) return fail(GATO_EINVAL, "pcg_tol must be positive and finite");
+  if (p->pcg_max_iter < 0) return fail(GATO_EINVAL, "pcg_max_iter must be >= 0");
+  if (!(std::isfinite(p->mu) && p->mu >= 0.0)) return fail(GATO_EINVAL, "mu must be >= 0");
+  if (!(std::isfinite(p->beta) && p->beta > 1.0)) return fail(GATO_EINVAL, "beta must be > 1");
+  if (p->n_alpha < 1 || p->n_alpha > GATO_MAX_ALPHA) return fail(GATO_EINVAL, "n_alpha must be in 1..16");
+  if (!(std::isfinite(p->rho) && p->rho >= 0.0)) return fail(GATO_EINVAL, "rho must be >= 0");
+  if (p->schur_fp64 != 0 && p->schur_fp64 != 1) return fail(GATO_EINVAL, "schur_fp64 must be 0 or 1");
+  return GATO_OK;
+}
+
+size_t gato_workspace_bytes(int n_dof, int N, const gato_params *p) {
+  if (!dof_supported(n_dof) || N < 2 || N > GATO_MAX_KNOTS) return 0;
+  if (p && p->n_alpha > GATO_MAX_ALPHA) return 0;
+  return layout_for(n_dof, N).total + (size_t)N * 2 * n_dof * sizeof(double) + sizeof(SolveDesc) +
+         64 * sizeof(gato_solve_stats);
+}
+
+int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs, const gato_params *p,
+                      void *hip_stream, gato_batch **out) {
+  if (!out) return fail(GATO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (M < 1) return fail(GATO_EINVAL, "M must be >= 1");
+  if (!robots || !probs) return fail(GATO_EINVAL, "robots and probs must not be NULL");
+  gato_params prm;
+  gato_default_params(&prm);
+  if (p) prm = *p;
+  int rc = check_params(&prm);
+  if (rc != GATO_OK) return rc;
+
+  std::vector<SolveDesc> desc(M);
+  int n_max = 0, N_max = 0;
+  for (int i = 0; i < M; ++i) {
+    const gato_robot &r = robots[i];
+    const gato_problem &q = probs[i];
+    const std::string who = "solve " + std::to_string(i) + ": ";
+    if (r.model != GATO_MODEL_SERIAL_CHAIN && r.model != GATO_MODEL_DOUBLE_INTEGRATOR)
+      return fail(GATO_EINVAL, who + "unknown robot model");
+    if (r.n_dof < 1 || r.n_dof > GATO_MAX_DOF) return fail(GATO_EINVAL, who + "n_dof must be in 1..7");
+    if (!dof_supported(r.n_dof))
+      return fail(GATO_EUNSUPPORTED, who + "n_dof " + std::to_string(r.n_dof) + " has no compiled kernel (3, 6, 7)");
+    if (q.N < 2 || q.N > GATO_MAX_KNOTS) return fail(GATO_EINVAL, who + "N must be in 2..128");
+    if (!pos_finite(q.dt)) return fail(GATO_EINVAL, who + "dt must be positive");
+    if (!q.Q_diag || !q.R_diag || !q.QN_diag) return fail(GATO_EINVAL, who + "cost weights must not be NULL");
+    const int n = r.n_dof, nx = 2 * n;
+    for (int j = 0; j < nx; ++j)
+      if (!pos_finite(q.Q_diag[j]) || !pos_finite(q.QN_diag[j]))
+        return fail(GATO_EINVAL, who + "Q and Q_N must be positive");
+    for (int j = 0; j < n; ++j)
+      if (!pos_finite(q.R_diag[j])) return fail(GATO_EINVAL, who + "R must be positive");
+    SolveDesc &d = desc[i];
+    std::memset(&d, 0, sizeof(d));
+    d.chain.n = n;
+    d.chain.model = r.model;
+    d.chain.g = (float)r.gravity;
+    d.chain.ks = (float)r.spring_k;
+    if (r.model == GATO_MODEL_SERIAL_CHAIN) {
+      if (!r.link) return fail(GATO_EINVAL, who + "link parameters must not be NULL");
+      if (!std::isfinite(r.gravity)) return fail(GATO_EINVAL, who + "gravity must be finite");
+      for (int j = 0; j < n; ++j) {
+        const double *l = r.link + 5 * j;
+        if (!(std::isfinite(l[0]) && l[0] >= 0.0) || !pos_finite(l[1]) || !pos_finite(l[2]) ||
+            !pos_finite(l[3]) || !pos_finite(l[4]))
+          return fail(GATO_EINVAL, who + "link length must be >= 0 and mass/inertias > 0");
+        const double cz = 0.5 * l[0];
+        d.chain.Lp[j] = j > 0 ? (float)r.link[5 * (j - 1)] : 0.f;
+        d.chain.m[j] = (float)l[1];
+        d.chain.cz[j] = (float)cz;
+        d.chain.Io[j][0] = (float)(l[2] + l[1] * cz * cz);
+        d.chain.Io[j][1] = (float)(l[3] + l[1] * cz * cz);
+        d.chain.Io[j][2] = (float)l[4];
+      }
+    } else if (!std::isfinite(r.spring_k)) {
+      return fail(GATO_EINVAL, who + "spring_k must be finite");
+    }
+    d.n = n;
+    d.N = q.N;
+    d.kpt = gato::kpt_for(n, q.N);
+    d.dt = (float)q.dt;
+    for (int j = 0; j < nx; ++j) {
+      d.Wq[j] = (float)q.Q_diag[j];
+      d.Wn[j] = (float)q.QN_diag[j];
+      d.Qi[j] = 1.0 / (q.Q_diag[j] + prm.rho);
+      d.Qni[j] = 1.0 / (q.QN_diag[j] + prm.rho);
+    }
+    for (int j = 0; j < n; ++j) {
+      d.Wr[j] = (float)q.R_diag[j];
+      d.Ri[j] = 1.0 / q.R_diag[j];
+    }
+    n_max = std::max(n_max, n);
+    N_max = std::max(N_max, q.N);
+  }
+
+  gato_batch *b = new gato_batch();
+  b->M = M;
+  b->n_max = n_max;
+  b->N_max = N_max;
+  b->p = prm;
+  b->stream = (hipStream_t)hip_stream;
+  size_t off = 0;
+  for (int i = 0; i < M; ++i) {
+    const Layout l = layout_for(desc[i].n, desc[i].N);
+    desc[i].ws_off = (int64_t)off;
+    desc[i].offA = (int64_t)l.offA;
+    desc[i].offB = (int64_t)l.offB;
+    desc[i].offD = (int64_t)l.offD;
+    off += l.total;
+  }
+  b->ws_bytes = off;
+  b->desc = desc;
+
+  // Group solves by kernel shape; longest horizon first inside a group.
+  std::vector<std::vector<int>> members(64);
+  for (int i = 0; i < M; ++i) members[desc[i].n * 8 + desc[i].kpt].push_back(i);
+  hipError_t e;
+  for (int key = 0; key < 64; ++key) {
+    auto &v = members[key];
+    if (v.empty()) continue;
+    std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return desc[x].N > desc[y].N; });
+    gato_batch::Group g{key / 8, key % 8, (int)v.size(), nullptr};
+    e = hipMalloc((void **)&g.d_order, v.size() * sizeof(int));
+    if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(order)"); }
+    e = hipMemcpy(g.d_order, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { b->groups.push_back(g); gato_batch_destroy(b); return hip_fail(e, "hipMemcpy(order)"); }
+    b->groups.push_back(g);
+  }
+
+  e = hipMalloc((void **)&b->d_desc, M * sizeof(SolveDesc));
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(desc)"); }
+  e = hipMemcpy(b->d_desc, desc.data(), M * sizeof(SolveDesc), hipMemcpyHostToDevice);
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemcpy(desc)"); }
+  e = hipMalloc((void **)&b->d_ws, b->ws_bytes);
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(workspace)"); }
+  e = hipMemset(b->d_ws, 0, b->ws_bytes);
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemset(workspace)"); }
+  b->lam_bytes = (size_t)M * N_max * 2 * n_max * sizeof(double);
+  e = hipMalloc((void **)&b->d_lam, b->lam_bytes);
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(lambda)"); }
+  e = hipMemset(b->d_lam, 0, b->lam_bytes);
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemset(lambda)"); }
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipDeviceSynchronize"); }
+  *out = b;
+  return GATO_OK;
+}
+
+void gato_batch_destroy(gato_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  else (void)hipDeviceSynchronize();
+  for (auto &g : b->groups)
+    if (g.d_order) (void)hipFree(g.d_order);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->d_ws) (void)hipFree(b->d_ws);
+  if (b->d_lam) (void)hipFree(b->d_lam);
+  if (b->d_stats) (void)hipFree(b->d_stats);
+  delete b;
+}
+
+int gato_batch_shape(const gato_batch *b, int *M, int *n_max, int *N_max) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (M) *M = b->M;
+  if (n_max) *n_max = b->n_max;
+  if (N_max) *N_max = b->N_max;
+  return GATO_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+gato::KArgs base_args(gato_batch *b) {
+  gato::KArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.desc = b->d_desc;
+  a.ws = b->d_ws;
+  a.lam = b->d_lam;
+  a.nx_max = 2 * b->n_max;
+  a.nu_max = b->n_max;
+  a.N_max = b->N_max;
+  a.pcg_tol = b->p.pcg_tol;
+  a.pcg_max_iter = b->p.pcg_max_iter;
+  a.mu = (float)b->p.mu;
+  a.beta = (float)b->p.beta;
+  a.n_alpha = b->p.n_alpha;
+  a.warm = b->p.warm_lambda;
+  return a;
+}
+
+// One launch per shape group, solves mapped through the group's order.
+int launch_groups(gato_batch *b, gato::KArgs a) {
+  const bool f64 = b->p.schur_fp64 != 0;
+  for (const auto &g : b->groups) {
+    a.order = g.d_order;
+    hipError_t e = gato::launch_sqp(g.n, g.kpt, f64, g.count, a, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  return GATO_OK;
+}
+
+int check_io(gato_batch *b, const void *xs, const void *goal, const void *X, const void *U) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (!xs || !goal || !X || !U) return fail(GATO_EINVAL, "device buffers must not be NULL");
+  return GATO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gato_step(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U, int n_iters,
+              gato_solve_stats *d_stats) {
+  int rc = check_io(b, d_xs, d_goal, d_X, d_U);
+  if (rc) return rc;
+  if (n_iters < 0) return fail(GATO_EINVAL, "n_iters must be >= 0");
+  if (n_iters == 0) return GATO_OK;
+  gato::KArgs a = base_args(b);
+  a.xs = d_xs;
+  a.goal = d_goal;
+  a.X = d_X;
+  a.U = d_U;
+  a.iters = n_iters;
+  a.stats = d_stats;
+  a.stats_stride = n_iters;
+  a.mode = gato::kModeSqp;
+  return launch_groups(b, a);
+}
+
+int gato_step_plain(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U, int n_iters,
+                    gato_solve_stats *d_stats) {
+  int rc = check_io(b, d_xs, d_goal, d_X, d_U);
+  if (rc) return rc;
+  if (n_iters < 0) return fail(GATO_EINVAL, "n_iters must be >= 0");
+  if (n_iters == 0) return GATO_OK;
+  gato::KArgs a = base_args(b);
+  a.xs = d_xs;
+  a.goal = d_goal;
+  a.X = d_X;
+  a.U = d_U;
+  a.iters = n_iters;
+  a.stats = d_stats;
+  a.stats_stride = n_iters;
+  a.mode = gato::kModeSqp;
+  a.order = nullptr;
+  const bool f64 = b->p.schur_fp64 != 0;
+  for (int i = 0; i < b->M; ++i) {
+    a.sid_base = i;
+    hipError_t e = gato::launch_sqp(b->desc[i].n, b->desc[i].kpt, f64, 1, a, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  }
+  return GATO_OK;
+}
+
+int gato_solve(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U,
+               gato_solve_stats *h_stats) {
+  int rc = check_io(b, d_xs, d_goal, d_X, d_U);
+  if (rc) return rc;
+  const int iters = b->p.sqp_iters;
+  if (iters == 0) return GATO_OK;
+  gato_solve_stats *ds = nullptr;
+  if (h_stats) {
+    const size_t need = (size_t)b->M * iters;
+    if (b->stats_cap < need) {
+      if (b->d_stats) (void)hipFree(b->d_stats);
+      b->d_stats = nullptr;
+      b->stats_cap = 0;
+      hipError_t e = hipMalloc((void **)&b->d_stats, need * sizeof(gato_solve_stats));
+      if (e != hipSuccess) return hip_fail(e, "hipMalloc(stats)");
+      b->stats_cap = need;
+    }
+    ds = b->d_stats;
+  }
+  rc = gato_step(b, d_xs, d_goal, d_X, d_U, iters, ds);
+  if (rc) return rc;
+  if (h_stats) {
+    const size_t need = (size_t)b->M * iters;
+    hipError_t e = hipMemcpyAsync(h_stats, ds, need * sizeof(gato_solve_stats), hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(stats)");
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (size_t i = 0; i < need; ++i)
+      if (h_stats[i].status) return 1;
+  }
+  return GATO_OK;
+}
+
+int gato_debug_lq(gato_batch *b, const float *d_xs, const float *d_goal, const float *d_X, const float *d_U,
+                  float *d_A, float *d_B, float *d_e) {
+  int rc = check_io(b, d_xs, d_goal, d_X, d_U);
+  if (rc) return rc;
+  if (!d_A || !d_B || !d_e) return fail(GATO_EINVAL, "output buffers must not be NULL");
+  gato::KArgs a = base_args(b);
+  a.xs = d_xs;
+  a.goal = d_goal;
+  a.X = const_cast<float *>(d_X);
+  a.U = const_cast<float *>(d_U);
+  a.iters = 1;
+  a.mode = gato::kModeLq;
+  a.outA = d_A;
+  a.outB = d_B;
+  a.oute = d_e;
+  return launch_groups(b, a);
+}
+
+int gato_debug_kkt(gato_batch *b, const float *d_A, const float *d_B, const float *d_e, const float *d_q,
+                   const float *d_r, const float *d_c0, float *d_dX, float *d_dU, double *d_lambda,
+                   int *d_pcg_iters) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (!d_A || !d_B || !d_e || !d_q || !d_r || !d_c0 || !d_dX || !d_dU || !d_lambda)
+    return fail(GATO_EINVAL, "buffers must not be NULL");
+  gato::KArgs a = base_args(b);
+  a.iters = 1;
+  a.mode = gato::kModeKkt;
+  a.warm = 0;
+  a.inA = d_A;
+  a.inB = d_B;
+  a.ine = d_e;
+  a.inq = d_q;
+  a.inr = d_r;
+  a.inc0 = d_c0;
+  a.outdX = d_dX;
+  a.outdU = d_dU;
+  a.outlam = d_lambda;
+  a.outits = d_pcg_iters;
+  return launch_groups(b, a);
+}
+
+int gato_reset_warm_start(gato_batch *b) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  hipError_t e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(lambda)");
+  return GATO_OK;
+}
+}  // extern "C"

@@ -1,0 +1,63 @@
+// Descriptors shared by the host library and the kernels (internal, not ABI).
+#pragma once
+
+#include <stdint.h>
+
+#include "../../include/gato.h"
+#include "gato_rbd.hpp"
+
+namespace gato {
+
+constexpr int kBlock = 512;        // threads per workgroup (one solve per workgroup)
+constexpr int kMaxAlpha = GATO_MAX_ALPHA;
+
+// Per-solve constants, built on the host at create time.
+struct SolveDesc {
+  Chain chain;
+  int n;              // DoF
+  int N;              // knot points
+  int kpt;            // knots per lane group held in registers by the PCG phase
+  int pad0;
+  float dt;
+  float Wq[16];       // stage state weights (diagonal of Q)
+  float Wn[16];       // terminal weights (diagonal of Q_N)
+  float Wr[8];        // control weights (diagonal of R)
+  double Qi[16];      // 1 / (Q + rho)
+  double Qni[16];     // 1 / (Q_N + rho)
+  double Ri[8];       // 1 / R
+  int64_t ws_off;     // byte offset of this solve's workspace
+  int64_t offA, offB, offD;  // byte offsets inside it: A, B (float), Dinv (Real)
+};
+
+enum KernelMode { kModeSqp = 0, kModeLq = 1, kModeKkt = 2 };
+
+struct KArgs {
+  const SolveDesc *desc;
+  char *ws;
+  double *lam;               // [M][N_max][nx_max] warm-start multipliers
+  const float *xs;
+  const float *goal;
+  float *X;
+  float *U;
+  int nx_max, nu_max, N_max;
+  int iters;
+  gato_solve_stats *stats;   // [M][iters] device, or null
+  int stats_stride;
+  double pcg_tol;
+  int pcg_max_iter;
+  float mu;
+  float beta;
+  int n_alpha;
+  int warm;
+  int mode;
+  int sid_base;              // solve index of blockIdx.x == 0
+  const int *order;          // optional block -> solve map (longest first), or null
+  // Stage entry points.
+  const float *inA, *inB, *ine, *inq, *inr, *inc0;
+  float *outA, *outB, *oute;
+  float *outdX, *outdU;
+  double *outlam;
+  int *outits;
+};
+
+}  // namespace gato

@@ -1,0 +1,26 @@
+// Kernel instantiation table shared by the host library and the translation
+// units that instantiate the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gato_internal.hpp"
+
+namespace gato {
+
+// Launches the fused SQP kernel for n = nd, knots-per-group kpt, precision f64
+// on `grid` workgroups. Returns hipErrorInvalidValue for shapes that were not
+// compiled.
+hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
+
+// Register-resident PCG rows: knots per lane group for a solve of n DoF and
+// N knots (0 if N is too large).
+inline int kpt_for(int n, int N) {
+  const int G = (2 * n > 8) ? 16 : 8;
+  const int slots = kBlock / G;
+  for (int k = 1; k <= 4; k *= 2)
+    if (N <= k * slots) return k;
+  return 0;
+}
+
+}  // namespace gato

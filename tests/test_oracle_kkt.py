@@ -264,3 +264,17 @@ def test_schur_pcg_mode_tracks_dense_mode(oracle_lib):
     scale = np.abs(a.X).max()
     assert np.abs(a.X - b.X).max() < 1e-6 * scale
     assert all(L["pcg_iters"] > 0 for L in b.logs[:2])
+
+
+@pytest.mark.parametrize("n,N", [(3, 128), (7, 64)])
+def test_riccati_is_stable_on_long_horizons(oracle_lib, n, N):
+    # Open-loop-unstable chains over long horizons: the Riccati mode must still
+    # agree with a LAPACK solve of the assembled KKT system.
+    s = w.chain_solve(12, 0, n=n, N=N)
+    dZ_ref, lam_ref, _ = _dense_kkt(s, s.X0, s.U0)
+    dX_ref, dU_ref = oracle.split_dz(s, dZ_ref)
+    dX, dU, lam, _, res = oracle.qp_step(s, s.X0, s.U0, mode=2)
+    np.testing.assert_allclose(dX, dX_ref, atol=1e-8 * np.abs(dX_ref).max())
+    np.testing.assert_allclose(dU, dU_ref, atol=1e-8 * np.abs(dU_ref).max())
+    np.testing.assert_allclose(lam.ravel(), lam_ref, atol=1e-8 * np.abs(lam_ref).max())
+    assert res < 1e-9
