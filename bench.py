@@ -1,0 +1,250 @@
+"""Benchmark of the batched SQP hot path on one MI355X.
+
+Workload (the headline configuration): seeded 7-DoF revolute chains, N = 32
+knot points, dt = 0.01 s, diagonal tracking weights Q = 1, R = 1e-3,
+Q_N = 100, 10 SQP iterations per solve, PCG tolerance 1e-5, a batch of
+M = 256 solves with one solve per workgroup. A step is one batched call that
+runs the 10 SQP iterations of all M solves, starting from the same initial
+guess every time (iterate restored and PCG warm start cleared inside the
+timed loop). Inputs are synthetic and resident in HBM before timing starts.
+
+Also measured: the batch-size sweep M in {1, 16, 32, 64, 128, 256} for the
+batched launch and for the plain form (M one-solve launches in order), per-call
+latency p50/p99 from HIP events, the trajectory error against the FP64 oracle
+on sampled solves, the roofline position of the fused kernel and the oracle's
+CPU throughput on a bounded sample.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_ALU = 78.6e12       # FP64 (and unpacked FP32) vector FLOP/s: 256 CU x 64 FMA lanes x 2 x 2.4 GHz
+SWEEP = (1, 16, 32, 64, 128, 256)
+
+
+def _pcts(ms):
+    a = np.asarray(ms, dtype=np.float64)
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def run_batched(g, torch, M, steps, warmup, params, seed=0):
+    import workload as w
+    solves = w.chain_batch(seed, M)
+    b = g.Batch.from_solves(solves, params)
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    X, U = X0.clone(), U0.clone()
+    it = params.sqp_iters
+    st = b.stats_buffer(it)
+    for _ in range(warmup):
+        X.copy_(X0)
+        U.copy_(U0)
+        b.reset_warm_start()
+        b.step(xs, goal, X, U, it, st)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        X.copy_(X0)
+        U.copy_(U0)
+        b.reset_warm_start()
+        ev[k][0].record()
+        b.step(xs, goal, X, U, it, st)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [a.elapsed_time(c) for a, c in ev]
+    stats = g.Batch.decode_stats(st, M, it)
+    out = dict(M=M, wall_s=wall, kernel_ms=kern_ms, stats=stats, X=X.cpu().numpy(), U=U.cpu().numpy(),
+               solves=solves)
+    b.close()
+    return out
+
+
+def run_plain(g, torch, M, reps, params, seed=0):
+    import workload as w
+    solves = w.chain_batch(seed, M)
+    b = g.Batch.from_solves(solves, params)
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    X, U = X0.clone(), U0.clone()
+    it = params.sqp_iters
+    b.step(xs, goal, X, U, it, plain=True)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        X.copy_(X0)
+        U.copy_(U0)
+        b.reset_warm_start()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.step(xs, goal, X, U, it, plain=True)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    b.close()
+    return ms
+
+
+def end_to_end_ms(g, torch, M, reps, params, seed=0):
+    """Host-timed calls including the H2D of start states/goals and the D2H of X*, U*."""
+    import workload as w
+    solves = w.chain_batch(seed, M)
+    b = g.Batch.from_solves(solves, params)
+    xs_h, goal_h, X0, U0 = (t.cpu().pin_memory() for t in g.pack_inputs(solves))
+    xs = torch.empty_like(xs_h, device="cuda")
+    goal = torch.empty_like(goal_h, device="cuda")
+    X = torch.empty_like(X0, device="cuda")
+    U = torch.empty_like(U0, device="cuda")
+    Xo = torch.empty_like(X0).pin_memory()
+    Uo = torch.empty_like(U0).pin_memory()
+    ms = []
+    for r in range(reps + 2):
+        b.reset_warm_start()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs.copy_(xs_h, non_blocking=True)
+        goal.copy_(goal_h, non_blocking=True)
+        X.copy_(X0, non_blocking=True)
+        U.copy_(U0, non_blocking=True)
+        b.step(xs, goal, X, U, params.sqp_iters)
+        Xo.copy_(X, non_blocking=True)
+        Uo.copy_(U, non_blocking=True)
+        torch.cuda.synchronize()
+        if r >= 2:
+            ms.append((time.perf_counter() - t0) * 1e3)
+    b.close()
+    return ms
+
+
+def accuracy(g, res, params, sample=4):
+    """Max relative trajectory error of sampled solves against the FP64 oracle
+    (dense KKT), the oracle replaying the GPU's accepted steps."""
+    import oracle
+    errs = []
+    idx = np.linspace(0, res["M"] - 1, min(sample, res["M"])).astype(int)
+    for i in idx:
+        s = res["solves"][i]
+        ref = oracle.sqp(s, oracle.Params(sqp_iters=params.sqp_iters, kkt_mode=0),
+                         alpha_replay=res["stats"][i]["alpha"].astype(np.float64))
+        ex = np.abs(res["X"][i] - ref.X).max() / np.abs(ref.X).max()
+        eu = np.abs(res["U"][i] - ref.U).max() / np.abs(ref.U).max()
+        errs.append(max(ex, eu))
+    return dict(max_rel_traj_err_vs_fp64_oracle=float(max(errs)), solves_checked=[int(i) for i in idx])
+
+
+def cpu_baseline(n_solves=32, threads=None):
+    """The FP64 oracle (dense KKT LU per SQP iteration) on a bounded sample."""
+    import oracle
+    import workload as w
+    oracle.lib()
+    threads = threads or len(os.sched_getaffinity(0))
+    solves = w.chain_batch(0, n_solves)
+    t0 = time.perf_counter()
+    oracle.sqp_batch(solves, oracle.Params(sqp_iters=10, kkt_mode=0), threads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=n_solves / dt, unit="solves/s", cores=int(threads), kind="oracle",
+                sample=f"{n_solves} solves of the same workload (7-DoF, N=32, 10 SQP iterations, dense FP64 "
+                       f"KKT LU), one solve per thread, {dt:.1f} s wall")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--M", type=int, default=256)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pcg-tol", type=float, default=1e-5)
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only the timed batched steps (no sweep, end-to-end, accuracy or CPU legs)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (for HBM counter scaling)")
+    args = ap.parse_args()
+    if args.profile_run:
+        args.no_sweep = args.no_cpu = True
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; solves shard across GPUs without any exchange, "
+                                   "so a multi-GPU run is M/G independent copies of the 1-GPU run",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2510_07625_amd as g
+
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    params = g.Params(sqp_iters=10, pcg_tol=args.pcg_tol)
+    main_res = run_batched(g, torch, args.M, args.steps, args.warmup, params)
+    M, K = args.M, args.steps
+    value = M * K / main_res["wall_s"]
+    kern = np.asarray(main_res["kernel_ms"])
+    p50, p99 = _pcts(kern)
+    pcg = main_res["stats"]["pcg_iters"]
+    flops_launch = sum(g.sqp_iteration_flops(7, 32, params.n_alpha, pcg[i]) for i in range(M))
+    achieved = flops_launch / (kern.mean() * 1e-3)
+    roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_ALU / 1e12, unit="TFLOP/s",
+                frac=achieved / PEAK_ALU, traffic=None,
+                kernel="gato::sqp_kernel<7, 1, double>",
+                flops_per_launch=flops_launch, avg_kernel_ms=float(kern.mean()),
+                pcg_iters_per_solve=float(pcg.sum(axis=1).mean()))
+    sweep, plain = [], []
+    if not args.no_sweep:
+        for m in SWEEP:
+            r = main_res if m == M else run_batched(g, torch, m, 10, 2, params)
+            km = np.asarray(r["kernel_ms"])
+            a, b = _pcts(km)
+            sweep.append(dict(M=m, solves_per_s=m / (km.mean() * 1e-3), p50_ms=a, p99_ms=b))
+        for m in SWEEP:
+            ms = run_plain(g, torch, m, 3 if m >= 64 else 5, params)
+            a, b = _pcts(ms)
+            plain.append(dict(M=m, solves_per_s=m / (np.mean(ms) * 1e-3), p50_ms=a, p99_ms=b))
+    e2e = [float("nan")] if args.profile_run else end_to_end_ms(g, torch, M, 10, params)
+    acc = None if args.profile_run else accuracy(g, main_res, params)
+    out = {
+        "metric": "SQP solves/s + p99 latency, 7-DoF N=32 batch 1-256, batched vs plain",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["wall_s"] * 1e3 / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"7-DoF revolute chain, N=32 knots, dt=0.01, 10 SQP iterations, PCG tol "
+                               f"{args.pcg_tol:g}, batch M={M}, one solve per workgroup",
+                   "M": M, "N": 32, "n_dof": 7, "sqp_iters": 10, "pcg_tol": args.pcg_tol},
+        "p50_ms": p50,
+        "p99_ms": p99,
+        "end_to_end_ms": dict(zip(("p50", "p99"), _pcts(e2e))),
+        "sweep_batched": sweep,
+        "sweep_plain": plain,
+        "accuracy": acc,
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -196,6 +196,16 @@ int gato_debug_kkt(gato_batch *b, const float *d_A, const float *d_B, const floa
 /* Resets the PCG warm-start multipliers of every solve to zero (stream-ordered). */
 int gato_reset_warm_start(gato_batch *b);
 
+/*
+ * Arithmetic operation counts of the per-knot rigid-body routines the kernels
+ * run, for algorithmic FLOP accounting (host only, no GPU needed):
+ * out[0] forward dynamics (inertia matrix, bias forces, Cholesky, solve),
+ * out[1] one column of the forward-dynamics Jacobian (dual-number inverse
+ * dynamics + solve), out[2] one Cholesky solve. A fused multiply-add counts 2,
+ * sin and cos count 1 each. Errors: GATO_EINVAL for n_dof outside 1..7.
+ */
+int gato_rbd_flops(int n_dof, double *out);
+
 /* Thread-local message describing the last non-OK return (never NULL). */
 const char *gato_last_error(void);
 

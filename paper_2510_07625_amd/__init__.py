@@ -57,7 +57,7 @@ STATS_DTYPE = np.dtype([("merit0", np.float32), ("merit", np.float32), ("alpha",
 # Entry points declared in include/gato.h.
 EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "gato_batch_destroy",
            "gato_batch_shape", "gato_solve", "gato_step", "gato_step_plain", "gato_debug_lq",
-           "gato_debug_kkt", "gato_reset_warm_start", "gato_last_error")
+           "gato_debug_kkt", "gato_reset_warm_start", "gato_rbd_flops", "gato_last_error")
 
 _lib = None
 
@@ -86,6 +86,7 @@ def lib() -> C.CDLL:
         L.gato_debug_lq.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.gato_debug_kkt.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.gato_reset_warm_start.argtypes = [vp]
+        L.gato_rbd_flops.argtypes = [ip, C.POINTER(C.c_double)]
         L.gato_last_error.argtypes = []
         L.gato_last_error.restype = C.c_char_p
         _lib = L
@@ -133,6 +134,43 @@ class Problem:
     Q_diag: np.ndarray
     R_diag: np.ndarray
     QN_diag: np.ndarray
+
+
+def rbd_flops(n_dof: int):
+    """(forward dynamics, one Jacobian column, one Cholesky solve) operation counts."""
+    out = (C.c_double * 3)()
+    _check(lib().gato_rbd_flops(int(n_dof), out))
+    return tuple(out)
+
+
+def sqp_iteration_flops(n: int, N: int, n_alpha: int, pcg_iters) -> float:
+    """Algorithmic FLOPs of one SQP iteration of one solve, counted once per knot.
+
+    pcg_iters may be an array (one entry per SQP iteration); the result is the
+    sum over those iterations. Per knot: dynamics + 2n Jacobian columns + n
+    inverse-inertia columns (LQ), the Schur row products, the diagonal-block
+    inverse (2 nx^3), the two preconditioner off-diagonal blocks (4 nx^3 each);
+    per PCG iteration two block-tridiagonal matrix-vector products (6 nx FLOPs
+    per row each) plus vector updates and dot products (12 per row); step
+    recovery; and per line-search candidate and knot one forward dynamics plus
+    trial point, defect and cost.
+    """
+    import numpy as _np
+    f_fd, f_col, f_sol = rbd_flops(n)
+    nx, nu = 2 * n, n
+    k = N - 1
+    lq = k * (f_fd + 2 * n * f_col + n * f_sol + 7 * nx + 3 * nu)
+    schur = k * (nx * nx * (nx + nu) * 2 + nx * (nx + nu) + nx + nx * (2 * (nx + nu) + 3))
+    inv = k * (2 * nx ** 3 + nx)
+    precond = N * (8 * nx ** 3 + 2 * nx * nx)
+    rows = N * nx
+    pcg_init = rows * (6 * nx + 2) + rows + 2 * rows * 6 * nx + 4 * rows
+    pcg_iter = rows * (12 * nx + 14)
+    step = rows * (2 * nx + 3) + k * nu * (2 * nx + 2)
+    ls = n_alpha * k * (f_fd + 2 * (2 * nx + nu) + 4 * nx + 3 * nx + 3 * nu) + n_alpha * (7 * nx + N)
+    fixed = lq + schur + inv + precond + pcg_init + step + ls
+    its = _np.atleast_1d(_np.asarray(pcg_iters, dtype=_np.float64))
+    return float(its.size * fixed + pcg_iter * its.sum())
 
 
 def workspace_bytes(n_dof: int, N: int, params: Params | None = None) -> int:

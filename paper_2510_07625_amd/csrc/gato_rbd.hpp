@@ -41,34 +41,42 @@ struct Chain {
 };
 
 // ---------------------------------------------------------------------------
-// Forward-mode dual number: value + one tangent.
+// Forward-mode dual number over a base scalar S: value + one tangent.
 // ---------------------------------------------------------------------------
-struct df {
-  float v, d;
+template <class S>
+struct dual {
+  S v, d;
 };
-__host__ __device__ inline df operator+(df a, df b) { return {a.v + b.v, a.d + b.d}; }
-__host__ __device__ inline df operator-(df a, df b) { return {a.v - b.v, a.d - b.d}; }
-__host__ __device__ inline df operator-(df a) { return {-a.v, -a.d}; }
-__host__ __device__ inline df operator*(df a, df b) { return {a.v * b.v, fmaf(a.d, b.v, a.v * b.d)}; }
-__host__ __device__ inline df operator*(float s, df a) { return {s * a.v, s * a.d}; }
-__host__ __device__ inline df &operator+=(df &a, df b) { a = a + b; return a; }
-__host__ __device__ inline df &operator-=(df &a, df b) { a = a - b; return a; }
+template <class S> __host__ __device__ inline dual<S> operator+(dual<S> a, dual<S> b) { return {a.v + b.v, a.d + b.d}; }
+template <class S> __host__ __device__ inline dual<S> operator-(dual<S> a, dual<S> b) { return {a.v - b.v, a.d - b.d}; }
+template <class S> __host__ __device__ inline dual<S> operator-(dual<S> a) { return {-a.v, -a.d}; }
+template <class S> __host__ __device__ inline dual<S> operator*(dual<S> a, dual<S> b) {
+  return {a.v * b.v, a.d * b.v + a.v * b.d};
+}
+template <class S> __host__ __device__ inline dual<S> operator*(float s, dual<S> a) { return {s * a.v, s * a.d}; }
+using df = dual<float>;
 
-__host__ __device__ inline float value_of(float x) { return x; }
-__host__ __device__ inline float value_of(df x) { return x.v; }
-template <class T> __host__ __device__ inline T cst(float x);
-template <> __host__ __device__ inline float cst<float>(float x) { return x; }
-template <> __host__ __device__ inline df cst<df>(float x) { return {x, 0.0f}; }
+template <class T> struct base_of { using type = T; };
+template <class S> struct base_of<dual<S>> { using type = S; };
+
+template <class T> struct cst_impl {
+  __host__ __device__ static T make(float x) { return T(x); }
+};
+template <class S> struct cst_impl<dual<S>> {
+  __host__ __device__ static dual<S> make(float x) { return {S(x), S(0.f)}; }
+};
+template <class T> __host__ __device__ inline T cst(float x) { return cst_impl<T>::make(x); }
 
 __host__ __device__ inline void sin_cos(float x, float *s, float *c) {
   *s = sinf(x);
   *c = cosf(x);
 }
-__host__ __device__ inline void sin_cos(df x, df *s, df *c) {
-  float sv, cv;
+template <class S>
+__host__ __device__ inline void sin_cos(dual<S> x, dual<S> *s, dual<S> *c) {
+  S sv, cv;
   sin_cos(x.v, &sv, &cv);
   *s = {sv, x.d * cv};
-  *c = {cv, -x.d * sv};
+  *c = {cv, -(x.d * sv)};
 }
 
 // ---------------------------------------------------------------------------
@@ -204,93 +212,90 @@ __host__ __device__ inline void rnea(const Chain &ch, const T *q, const T *qd, c
 // stored xx yy zz xy xz yz) in its own frame. Only the lower triangle is used
 // by the Cholesky below, but the full matrix is written.
 // ---------------------------------------------------------------------------
-template <bool Y>
-__host__ __device__ inline void rotate_inertia(float c, float s, float *I) {
-  // I <- R I R^T for R the rotation about the joint axis.
-  float Rm[3][3];
+template <bool Y, class S>
+__host__ __device__ inline void rotate_inertia(S c, S s, S *I) {
+  // I <- R I R^T for R the rotation about the joint axis. Only the entries
+  // that the rotation mixes are touched.
   if (Y) {
-    Rm[0][0] = c;  Rm[0][1] = 0.f; Rm[0][2] = s;
-    Rm[1][0] = 0.f; Rm[1][1] = 1.f; Rm[1][2] = 0.f;
-    Rm[2][0] = -s; Rm[2][1] = 0.f; Rm[2][2] = c;
+    // R = [[c, 0, s], [0, 1, 0], [-s, 0, c]]
+    const S xx = I[0], yy = I[1], zz = I[2], xy = I[3], xz = I[4], yz = I[5];
+    const S cc = c * c, ss = s * s, cs = c * s;
+    I[0] = cc * xx + ss * zz + 2.f * (cs * xz);
+    I[2] = ss * xx + cc * zz - 2.f * (cs * xz);
+    I[4] = cs * (zz - xx) + (cc - ss) * xz;
+    I[3] = c * xy + s * yz;
+    I[5] = c * yz - s * xy;
+    (void)yy;
   } else {
-    Rm[0][0] = c;  Rm[0][1] = -s; Rm[0][2] = 0.f;
-    Rm[1][0] = s;  Rm[1][1] = c;  Rm[1][2] = 0.f;
-    Rm[2][0] = 0.f; Rm[2][1] = 0.f; Rm[2][2] = 1.f;
+    // R = [[c, -s, 0], [s, c, 0], [0, 0, 1]]
+    const S xx = I[0], yy = I[1], xy = I[3], xz = I[4], yz = I[5];
+    const S cc = c * c, ss = s * s, cs = c * s;
+    I[0] = cc * xx + ss * yy - 2.f * (cs * xy);
+    I[1] = ss * xx + cc * yy + 2.f * (cs * xy);
+    I[3] = cs * (xx - yy) + (cc - ss) * xy;
+    I[4] = c * xz - s * yz;
+    I[5] = s * xz + c * yz;
   }
-  const float A[3][3] = {{I[0], I[3], I[4]}, {I[3], I[1], I[5]}, {I[4], I[5], I[2]}};
-  float T[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) T[i][j] = Rm[i][0] * A[0][j] + Rm[i][1] * A[1][j] + Rm[i][2] * A[2][j];
-  float B[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = 0; j < 3; ++j) B[i][j] = T[i][0] * Rm[j][0] + T[i][1] * Rm[j][1] + T[i][2] * Rm[j][2];
-  I[0] = B[0][0]; I[1] = B[1][1]; I[2] = B[2][2];
-  I[3] = 0.5f * (B[0][1] + B[1][0]);
-  I[4] = 0.5f * (B[0][2] + B[2][0]);
-  I[5] = 0.5f * (B[1][2] + B[2][1]);
 }
 
-template <int ND>
-__host__ __device__ inline void crba(const Chain &ch, const float *cq, const float *sq, float (*M)[ND]) {
+template <int ND, class S>
+__host__ __device__ inline void crba(const Chain &ch, const S *cq, const S *sq, S (*M)[ND]) {
   if (ch.model == 1) {
 #pragma unroll
     for (int i = 0; i < ND; ++i)
 #pragma unroll
-      for (int j = 0; j < ND; ++j) M[i][j] = (i == j) ? 1.f : 0.f;
+      for (int j = 0; j < ND; ++j) M[i][j] = S((i == j) ? 1.f : 0.f);
     return;
   }
-  float cm[ND], ch3[ND][3], cI[ND][6];
+  S cm[ND], ch3[ND][3], cI[ND][6];
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
-    cm[i] = ch.m[i];
-    ch3[i][0] = 0.f; ch3[i][1] = 0.f; ch3[i][2] = ch.m[i] * ch.cz[i];
-    cI[i][0] = ch.Io[i][0]; cI[i][1] = ch.Io[i][1]; cI[i][2] = ch.Io[i][2];
-    cI[i][3] = 0.f; cI[i][4] = 0.f; cI[i][5] = 0.f;
+    cm[i] = S(ch.m[i]);
+    ch3[i][0] = S(0.f); ch3[i][1] = S(0.f); ch3[i][2] = S(ch.m[i] * ch.cz[i]);
+    cI[i][0] = S(ch.Io[i][0]); cI[i][1] = S(ch.Io[i][1]); cI[i][2] = S(ch.Io[i][2]);
+    cI[i][3] = S(0.f); cI[i][4] = S(0.f); cI[i][5] = S(0.f);
   }
   // Accumulate composites towards the base.
 #pragma unroll
   for (int i = ND - 1; i >= 1; --i) {
-    float h[3] = {ch3[i][0], ch3[i][1], ch3[i][2]};
-    float I[6] = {cI[i][0], cI[i][1], cI[i][2], cI[i][3], cI[i][4], cI[i][5]};
+    S h[3] = {ch3[i][0], ch3[i][1], ch3[i][2]};
+    S I[6] = {cI[i][0], cI[i][1], cI[i][2], cI[i][3], cI[i][4], cI[i][5]};
     if (i & 1) { rot_R<true>(cq[i], sq[i], h[0], h[1], h[2]); rotate_inertia<true>(cq[i], sq[i], I); }
     else { rot_R<false>(cq[i], sq[i], h[0], h[1], h[2]); rotate_inertia<false>(cq[i], sq[i], I); }
     // Shift from the child joint to the parent joint, r = (0, 0, L):
     // I += -m [r]^2 - [h][r] - [r][h], h += m r.
-    const float L = ch.Lp[i], m = cm[i];
-    const float t = 2.f * h[2] * L + m * L * L;
-    I[0] += t;
-    I[1] += t;
-    I[4] -= h[0] * L;
-    I[5] -= h[1] * L;
-    h[2] += m * L;
-    cm[i - 1] += m;
+    const float L = ch.Lp[i];
+    const S m = cm[i];
+    const S t = (2.f * L) * h[2] + (L * L) * m;
+    I[0] = I[0] + t;
+    I[1] = I[1] + t;
+    I[4] = I[4] - L * h[0];
+    I[5] = I[5] - L * h[1];
+    h[2] = h[2] + L * m;
+    cm[i - 1] = cm[i - 1] + m;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) ch3[i - 1][a] += h[a];
+    for (int a = 0; a < 3; ++a) ch3[i - 1][a] = ch3[i - 1][a] + h[a];
 #pragma unroll
-    for (int a = 0; a < 6; ++a) cI[i - 1][a] += I[a];
+    for (int a = 0; a < 6; ++a) cI[i - 1][a] = cI[i - 1][a] + I[a];
   }
   // Column i: force of unit motion about joint i, carried towards the base.
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
-    float n[3], f[3];
+    S n[3], f[3];
     if (i & 1) {  // e = e_y: n = I e_y, f = e_y x h
       n[0] = cI[i][3]; n[1] = cI[i][1]; n[2] = cI[i][5];
-      f[0] = ch3[i][2]; f[1] = 0.f; f[2] = -ch3[i][0];
+      f[0] = ch3[i][2]; f[1] = S(0.f); f[2] = -ch3[i][0];
       M[i][i] = n[1];
     } else {      // e = e_z
       n[0] = cI[i][4]; n[1] = cI[i][5]; n[2] = cI[i][2];
-      f[0] = -ch3[i][1]; f[1] = ch3[i][0]; f[2] = 0.f;
+      f[0] = -ch3[i][1]; f[1] = ch3[i][0]; f[2] = S(0.f);
       M[i][i] = n[2];
     }
 #pragma unroll
     for (int j = i; j >= 1; --j) {
       if (j & 1) force_to_parent<true>(cq[j], sq[j], ch.Lp[j], n, f);
       else force_to_parent<false>(cq[j], sq[j], ch.Lp[j], n, f);
-      const float mij = ((j - 1) & 1) ? n[1] : n[2];
+      const S mij = ((j - 1) & 1) ? n[1] : n[2];
       M[i][j - 1] = mij;
       M[j - 1][i] = mij;
     }
@@ -299,83 +304,86 @@ __host__ __device__ inline void crba(const Chain &ch, const float *cq, const flo
 
 // In-place Cholesky of an SPD ND x ND matrix (lower triangle); returns false if
 // a pivot is not positive.
-template <int ND>
-__host__ __device__ inline bool cholesky(float (*A)[ND]) {
+__host__ __device__ inline bool positive(float x) { return x > 0.f; }
+__host__ __device__ inline float sqrt_pos(float x) { return sqrtf(fmaxf(x, 1e-30f)); }
+
+template <int ND, class S>
+__host__ __device__ inline bool cholesky(S (*A)[ND]) {
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < ND; ++j) {
-    float s = A[j][j];
+    S s = A[j][j];
 #pragma unroll
-    for (int k = 0; k < j; ++k) s -= A[j][k] * A[j][k];
-    ok = ok && (s > 0.f);
-    const float d = sqrtf(fmaxf(s, 1e-30f));
-    const float inv = 1.f / d;
+    for (int k = 0; k < j; ++k) s = s - A[j][k] * A[j][k];
+    ok = ok && positive(s);
+    const S d = sqrt_pos(s);
+    const S inv = 1.f / d;
     A[j][j] = d;
 #pragma unroll
     for (int i = j + 1; i < ND; ++i) {
-      float t = A[i][j];
+      S t = A[i][j];
 #pragma unroll
-      for (int k = 0; k < j; ++k) t -= A[i][k] * A[j][k];
+      for (int k = 0; k < j; ++k) t = t - A[i][k] * A[j][k];
       A[i][j] = t * inv;
     }
   }
   return ok;
 }
 
-template <int ND>
-__host__ __device__ inline void chol_solve(const float (*L)[ND], float *b) {
+template <int ND, class S>
+__host__ __device__ inline void chol_solve(const S (*L)[ND], S *b) {
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
-    float s = b[i];
+    S s = b[i];
 #pragma unroll
-    for (int k = 0; k < i; ++k) s -= L[i][k] * b[k];
+    for (int k = 0; k < i; ++k) s = s - L[i][k] * b[k];
     b[i] = s / L[i][i];
   }
 #pragma unroll
   for (int i = ND - 1; i >= 0; --i) {
-    float s = b[i];
+    S s = b[i];
 #pragma unroll
-    for (int k = i + 1; k < ND; ++k) s -= L[k][i] * b[k];
+    for (int k = i + 1; k < ND; ++k) s = s - L[k][i] * b[k];
     b[i] = s / L[i][i];
   }
 }
 
 // Forward dynamics qdd = M(q)^-1 (tau - b(q, qd)). Leaves the Cholesky factor
 // of M in L for later solves. Returns false if M is not positive definite.
-template <int ND>
-__host__ __device__ inline bool forward_dynamics(const Chain &ch, const float *q, const float *qd,
-                                                 const float *tau, float *qdd, float (*L)[ND]) {
-  float cq[ND], sq[ND];
+template <int ND, class S>
+__host__ __device__ inline bool forward_dynamics(const Chain &ch, const S *q, const S *qd, const S *tau, S *qdd,
+                                                 S (*L)[ND]) {
+  S cq[ND], sq[ND];
 #pragma unroll
   for (int i = 0; i < ND; ++i) sin_cos(q[i], &sq[i], &cq[i]);
-  crba<ND>(ch, cq, sq, L);
-  float zero[ND], b[ND];
+  crba<ND, S>(ch, cq, sq, L);
+  S zero[ND], b[ND];
 #pragma unroll
-  for (int i = 0; i < ND; ++i) zero[i] = 0.f;
-  rnea<ND, float>(ch, q, qd, zero, true, b);
-  const bool ok = cholesky<ND>(L);
+  for (int i = 0; i < ND; ++i) zero[i] = S(0.f);
+  rnea<ND, S>(ch, q, qd, zero, true, b);
+  const bool ok = cholesky<ND, S>(L);
 #pragma unroll
   for (int i = 0; i < ND; ++i) qdd[i] = tau[i] - b[i];
-  chol_solve<ND>(L, qdd);
+  chol_solve<ND, S>(L, qdd);
   return ok;
 }
 
 // One column of the Jacobian of forward dynamics: direction dir < ND is q_dir,
 // dir >= ND is qd_(dir-ND). Uses the factor L and qdd from forward_dynamics.
-template <int ND>
-__host__ __device__ inline void fd_jacobian_column(const Chain &ch, const float *q, const float *qd,
-                                                   const float *qdd, const float (*L)[ND], int dir, float *col) {
-  df Q[ND], QD[ND], QDD[ND], TAU[ND];
+template <int ND, class S>
+__host__ __device__ inline void fd_jacobian_column(const Chain &ch, const S *q, const S *qd, const S *qdd,
+                                                   const S (*L)[ND], int dir, S *col) {
+  dual<S> Q[ND], QD[ND], QDD[ND], TAU[ND];
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
-    Q[i] = {q[i], (dir == i) ? 1.f : 0.f};
-    QD[i] = {qd[i], (dir == ND + i) ? 1.f : 0.f};
-    QDD[i] = {qdd[i], 0.f};
+    Q[i] = {q[i], S((dir == i) ? 1.f : 0.f)};
+    QD[i] = {qd[i], S((dir == ND + i) ? 1.f : 0.f)};
+    QDD[i] = {qdd[i], S(0.f)};
   }
-  rnea<ND, df>(ch, Q, QD, QDD, true, TAU);
+  rnea<ND, dual<S>>(ch, Q, QD, QDD, true, TAU);
 #pragma unroll
   for (int i = 0; i < ND; ++i) col[i] = -TAU[i].d;
-  chol_solve<ND>(L, col);
+  chol_solve<ND, S>(L, col);
 }
 
 }  // namespace gato
