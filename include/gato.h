@@ -171,6 +171,17 @@ int gato_step_plain(gato_batch *b, const float *d_xs, const float *d_goal, float
                     int n_iters, gato_solve_stats *d_stats);
 
 /*
+ * gato_step with per-phase timing, for profiling: thread 0 of each solve's
+ * workgroup writes, per SQP iteration, 8 unsigned 64-bit values to d_clk
+ * (device, [M][n_iters][8]): the constant-rate device wall clock at the start
+ * of the iteration and after the dynamics, Schur complement, preconditioner,
+ * PCG, step-recovery and line-search phases (7 values), then the shader clock
+ * cycles of the whole iteration. Results equal gato_step's. Errors as gato_step.
+ */
+int gato_profile_phases(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U,
+                        int n_iters, unsigned long long *d_clk);
+
+/*
  * Stage entry point: the QP data of Eq. (1) at (X, U) for every solve, as the
  * kernel forms it in the first phase of an SQP iteration (dynamics,
  * derivatives and Euler discretisation). Outputs are device buffers:
@@ -192,6 +203,34 @@ int gato_debug_lq(gato_batch *b, const float *d_xs, const float *d_goal, const f
 int gato_debug_kkt(gato_batch *b, const float *d_A, const float *d_B, const float *d_e, const float *d_q,
                    const float *d_r, const float *d_c0, float *d_dX, float *d_dU, double *d_lambda,
                    int *d_pcg_iters);
+
+/*
+ * Serving (MPC re-solves, warm-started from the previous control step as in
+ * the experiments of Sec. IV). The batch keeps one device-resident trajectory
+ * per solve slot, [M][N_max][nx_max] and [M][N_max-1][nu_max].
+ * gato_set_trajectories / gato_get_trajectories copy all slots in or out
+ * (device-to-device, stream-ordered on the batch stream).
+ */
+int gato_set_trajectories(gato_batch *b, const float *d_X, const float *d_U);
+int gato_get_trajectories(gato_batch *b, float *d_X, float *d_U);
+
+/*
+ * One serving step over n_req requests: request r re-solves slot d_slots[r]
+ * (device int array; the slots of one call must be distinct, and a slot must
+ * not be in two calls that overlap in time) from start state d_xs[r] and goal
+ * d_goal[r] ([n_req][nx_max], [n_req][nu_max], device). With shift = 1 the
+ * slot's resident trajectory and PCG multipliers are first shifted one knot
+ * (the last knot repeated); shift = 0 re-solves from them as they are. Runs
+ * n_iters SQP iterations (1 for a real-time iteration), updates the resident
+ * trajectories and, if non-NULL, writes them per request to d_Xout / d_Uout
+ * ([n_req][N_max][nx_max], [n_req][N_max-1][nu_max]) and statistics to
+ * d_stats ([n_req][n_iters]). Launched on hip_stream (NULL: the batch stream)
+ * so that several steps on disjoint slots can overlap. Errors: GATO_EINVAL;
+ * GATO_EUNSUPPORTED for batches that mix shapes.
+ */
+int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d_xs, const float *d_goal,
+                    int n_iters, int shift, float *d_Xout, float *d_Uout, gato_solve_stats *d_stats,
+                    void *hip_stream);
 
 /* Resets the PCG warm-start multipliers of every solve to zero (stream-ordered). */
 int gato_reset_warm_start(gato_batch *b);

@@ -57,7 +57,8 @@ STATS_DTYPE = np.dtype([("merit0", np.float32), ("merit", np.float32), ("alpha",
 # Entry points declared in include/gato.h.
 EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "gato_batch_destroy",
            "gato_batch_shape", "gato_solve", "gato_step", "gato_step_plain", "gato_debug_lq",
-           "gato_debug_kkt", "gato_reset_warm_start", "gato_rbd_flops", "gato_last_error")
+           "gato_debug_kkt", "gato_reset_warm_start", "gato_rbd_flops", "gato_profile_phases",
+           "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_last_error")
 
 _lib = None
 
@@ -87,6 +88,10 @@ def lib() -> C.CDLL:
         L.gato_debug_kkt.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.gato_reset_warm_start.argtypes = [vp]
         L.gato_rbd_flops.argtypes = [ip, C.POINTER(C.c_double)]
+        L.gato_profile_phases.argtypes = [vp, vp, vp, vp, vp, ip, vp]
+        L.gato_set_trajectories.argtypes = [vp, vp, vp]
+        L.gato_get_trajectories.argtypes = [vp, vp, vp]
+        L.gato_serve_step.argtypes = [vp, ip, vp, vp, vp, ip, ip, vp, vp, vp, vp]
         L.gato_last_error.argtypes = []
         L.gato_last_error.restype = C.c_char_p
         _lib = L
@@ -273,6 +278,23 @@ class Batch:
         fn = lib().gato_step_plain if plain else lib().gato_step
         _check(fn(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), int(n_iters), _dptr(d_stats)))
 
+    PHASES = ("dynamics", "schur", "precond", "pcg", "step", "line_search")
+
+    def profile_phases(self, xs, goal, X, U, n_iters: int):
+        """Runs n_iters iterations recording per-phase device timestamps.
+
+        Returns (wall-clock ticks per phase [M, n_iters, 6], shader cycles per
+        iteration [M, n_iters]). The wall clock runs at a constant rate
+        (see torch/HIP device properties for its frequency).
+        """
+        import torch
+        self._io(xs, goal, X, U)
+        clk = torch.zeros((self.M, n_iters, 8), dtype=torch.int64, device="cuda")
+        _check(lib().gato_profile_phases(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), int(n_iters),
+                                         _dptr(clk)))
+        c = clk.cpu().numpy()
+        return np.diff(c[:, :, :7], axis=2), c[:, :, 7]
+
     def stats_buffer(self, n_iters: int):
         import torch
         return torch.zeros(self.M * n_iters * STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
@@ -308,6 +330,35 @@ class Batch:
         _check(lib().gato_debug_kkt(self._h, _dptr(A), _dptr(B), _dptr(e), _dptr(q), _dptr(r), _dptr(c0),
                                     _dptr(dX), _dptr(dU), _dptr(lam), _dptr(its)))
         return dX, dU, lam, its
+
+    # ---- serving --------------------------------------------------------------
+    def set_trajectories(self, X, U):
+        self._chk(X, (self.M, self.N_max, self.nx_max))
+        self._chk(U, (self.M, self.N_max - 1, self.nu_max))
+        _check(lib().gato_set_trajectories(self._h, _dptr(X), _dptr(U)))
+
+    def get_trajectories(self):
+        import torch
+        X = torch.empty((self.M, self.N_max, self.nx_max), dtype=torch.float32, device="cuda")
+        U = torch.empty((self.M, self.N_max - 1, self.nu_max), dtype=torch.float32, device="cuda")
+        _check(lib().gato_get_trajectories(self._h, _dptr(X), _dptr(U)))
+        return X, U
+
+    def serve_step(self, slots, xs, goal, n_iters: int = 1, shift: int = 1, Xout=None, Uout=None, d_stats=None,
+                   stream=None):
+        """gato_serve_step: slots (int32 cuda tensor [R]), xs [R, nx_max], goal [R, nu_max]."""
+        import torch
+        R = int(slots.shape[0])
+        self._chk(slots, (R,), torch.int32)
+        self._chk(xs, (R, self.nx_max))
+        self._chk(goal, (R, self.nu_max))
+        if Xout is not None:
+            self._chk(Xout, (R, self.N_max, self.nx_max))
+        if Uout is not None:
+            self._chk(Uout, (R, self.N_max - 1, self.nu_max))
+        st = stream.cuda_stream if stream is not None else None
+        _check(lib().gato_serve_step(self._h, R, _dptr(slots), _dptr(xs), _dptr(goal), int(n_iters), int(shift),
+                                     _dptr(Xout), _dptr(Uout), _dptr(d_stats), C.c_void_p(st) if st else None))
 
     def reset_warm_start(self):
         _check(lib().gato_reset_warm_start(self._h))

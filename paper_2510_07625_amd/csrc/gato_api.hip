@@ -49,7 +49,7 @@ bool dof_supported(int n) { return n == 3 || n == 6 || n == 7; }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t offA, offB, offD, total;
+  size_t offA, offB, offD, offP, total;
 };
 
 Layout layout_for(int n, int N) {
@@ -58,7 +58,8 @@ Layout layout_for(int n, int N) {
   l.offA = 0;
   l.offB = align256(l.offA + (size_t)(N - 1) * nx * nx * sizeof(float));
   l.offD = align256(l.offB + (size_t)(N - 1) * nx * nu * sizeof(float));
-  l.total = align256(l.offD + (size_t)N * nx * nx * sizeof(double));
+  l.offP = align256(l.offD + (size_t)N * nx * nx * sizeof(float));
+  l.total = align256(l.offP + (size_t)N * nx * nx * sizeof(float));
   return l;
 }
 
@@ -76,6 +77,9 @@ struct gato_batch {
   size_t ws_bytes = 0;
   double *d_lam = nullptr;   // [M][N_max][nx_max]
   size_t lam_bytes = 0;
+  float *d_Xres = nullptr;   // device-resident trajectories for serving, [M][N_max][nx_max]
+  float *d_Ures = nullptr;   // [M][N_max-1][nu_max]
+  size_t xres_bytes = 0, ures_bytes = 0;
   gato_solve_stats *d_stats = nullptr;
   size_t stats_cap = 0;
   // Launch groups: solves of one (n, kpt) shape, longest horizon first.
@@ -210,6 +214,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     desc[i].offA = (int64_t)l.offA;
     desc[i].offB = (int64_t)l.offB;
     desc[i].offD = (int64_t)l.offD;
+    desc[i].offP = (int64_t)l.offP;
     off += l.total;
   }
   b->ws_bytes = off;
@@ -244,6 +249,15 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(lambda)"); }
   e = hipMemset(b->d_lam, 0, b->lam_bytes);
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemset(lambda)"); }
+  b->xres_bytes = (size_t)M * N_max * 2 * n_max * sizeof(float);
+  b->ures_bytes = (size_t)M * (N_max - 1) * n_max * sizeof(float);
+  e = hipMalloc((void **)&b->d_Xres, b->xres_bytes);
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(resident X)"); }
+  e = hipMalloc((void **)&b->d_Ures, b->ures_bytes);
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(resident U)"); }
+  e = hipMemset(b->d_Xres, 0, b->xres_bytes);
+  if (e == hipSuccess) e = hipMemset(b->d_Ures, 0, b->ures_bytes);
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemset(resident X, U)"); }
   e = hipDeviceSynchronize();
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipDeviceSynchronize"); }
   *out = b;
@@ -259,6 +273,8 @@ void gato_batch_destroy(gato_batch *b) {
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_lam) (void)hipFree(b->d_lam);
+  if (b->d_Xres) (void)hipFree(b->d_Xres);
+  if (b->d_Ures) (void)hipFree(b->d_Ures);
   if (b->d_stats) (void)hipFree(b->d_stats);
   delete b;
 }
@@ -390,6 +406,22 @@ int gato_solve(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X
   return GATO_OK;
 }
 
+int gato_profile_phases(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U,
+                        int n_iters, unsigned long long *d_clk) {
+  int rc = check_io(b, d_xs, d_goal, d_X, d_U);
+  if (rc) return rc;
+  if (n_iters < 1 || !d_clk) return fail(GATO_EINVAL, "n_iters must be >= 1 and d_clk non-NULL");
+  gato::KArgs a = base_args(b);
+  a.xs = d_xs;
+  a.goal = d_goal;
+  a.X = d_X;
+  a.U = d_U;
+  a.iters = n_iters;
+  a.mode = gato::kModeSqp;
+  a.clk = d_clk;
+  return launch_groups(b, a);
+}
+
 int gato_debug_lq(gato_batch *b, const float *d_xs, const float *d_goal, const float *d_X, const float *d_U,
                   float *d_A, float *d_B, float *d_e) {
   int rc = check_io(b, d_xs, d_goal, d_X, d_U);
@@ -429,6 +461,53 @@ int gato_debug_kkt(gato_batch *b, const float *d_A, const float *d_B, const floa
   a.outlam = d_lambda;
   a.outits = d_pcg_iters;
   return launch_groups(b, a);
+}
+
+int gato_set_trajectories(gato_batch *b, const float *d_X, const float *d_U) {
+  if (!b || !d_X || !d_U) return fail(GATO_EINVAL, "batch and buffers must not be NULL");
+  hipError_t e = hipMemcpyAsync(b->d_Xres, d_X, b->xres_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_Ures, d_U, b->ures_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(trajectories in)");
+  return GATO_OK;
+}
+
+int gato_get_trajectories(gato_batch *b, float *d_X, float *d_U) {
+  if (!b || !d_X || !d_U) return fail(GATO_EINVAL, "batch and buffers must not be NULL");
+  hipError_t e = hipMemcpyAsync(d_X, b->d_Xres, b->xres_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_U, b->d_Ures, b->ures_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(trajectories out)");
+  return GATO_OK;
+}
+
+int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d_xs, const float *d_goal,
+                    int n_iters, int shift, float *d_Xout, float *d_Uout, gato_solve_stats *d_stats,
+                    void *hip_stream) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (n_req < 1 || n_req > b->M) return fail(GATO_EINVAL, "n_req must be in 1..M");
+  if (!d_slots || !d_xs || !d_goal) return fail(GATO_EINVAL, "slots, xs and goal must not be NULL");
+  if (n_iters < 1) return fail(GATO_EINVAL, "n_iters must be >= 1");
+  if (shift < 0 || shift > 1) return fail(GATO_EINVAL, "shift must be 0 or 1");
+  if (b->groups.size() != 1)
+    return fail(GATO_EUNSUPPORTED, "serving needs a batch of one shape (same DoF and knots-per-group)");
+  const auto &g = b->groups[0];
+  gato::KArgs a = base_args(b);
+  a.xs = d_xs;
+  a.goal = d_goal;
+  a.X = b->d_Xres;
+  a.U = b->d_Ures;
+  a.iters = n_iters;
+  a.stats = d_stats;
+  a.stats_stride = n_iters;
+  a.mode = gato::kModeSqp;
+  a.order = d_slots;
+  a.by_block = 1;
+  a.shift = shift;
+  a.Xout = d_Xout;
+  a.Uout = d_Uout;
+  hipStream_t st = hip_stream ? (hipStream_t)hip_stream : b->stream;
+  hipError_t e = gato::launch_sqp(g.n, g.kpt, b->p.schur_fp64 != 0, n_req, a, st);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return GATO_OK;
 }
 
 int gato_reset_warm_start(gato_batch *b) {

@@ -26,7 +26,8 @@ struct SolveDesc {
   double Qni[16];     // 1 / (Q_N + rho)
   double Ri[8];       // 1 / R
   int64_t ws_off;     // byte offset of this solve's workspace
-  int64_t offA, offB, offD;  // byte offsets inside it: A, B (float), Dinv (Real)
+  int64_t offA, offB, offD, offP;  // byte offsets inside it: A_k, B_k, inverse diagonal
+                                   // blocks and preconditioner off-diagonal blocks (float)
 };
 
 enum KernelMode { kModeSqp = 0, kModeLq = 1, kModeKkt = 2 };
@@ -58,6 +59,13 @@ struct KArgs {
   float *outdX, *outdU;
   double *outlam;
   int *outits;
+  unsigned long long *clk;    // optional [M][iters][8] phase timestamps (profiling)
+  // Serving: xs, goal and stats indexed by workgroup (request) instead of
+  // solve; the warm start is shifted by `shift` knots when it is loaded; the
+  // final trajectories are also gathered per request into Xout / Uout.
+  int by_block;
+  int shift;
+  float *Xout, *Uout;
 };
 
 }  // namespace gato

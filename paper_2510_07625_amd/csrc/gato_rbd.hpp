@@ -129,9 +129,11 @@ __host__ __device__ inline void force_to_parent(T c, T s, float L, T *n, T *f) {
 // Inverse dynamics (recursive Newton-Euler). Gravity is an upward acceleration
 // of the base. ch.model == 1 gives tau = qdd + ks T q (T = tridiag(-1, 2, -1)).
 // ---------------------------------------------------------------------------
+// cq, sq: cos and sin of the joint angles (precomputed so that the
+// trigonometric routines run before the recursion, with few values live).
 template <int ND, class T>
-__host__ __device__ inline void rnea(const Chain &ch, const T *q, const T *qd, const T *qdd, bool gravity,
-                                     T *tau) {
+__host__ __device__ inline void rnea(const Chain &ch, const T *q, const T *cq, const T *sq, const T *qd,
+                                     const T *qdd, bool gravity, T *tau) {
   if (ch.model == 1) {
 #pragma unroll
     for (int i = 0; i < ND; ++i) {
@@ -142,7 +144,6 @@ __host__ __device__ inline void rnea(const Chain &ch, const T *q, const T *qd, c
     }
     return;
   }
-  T cq[ND], sq[ND];
   T fn[ND][3], ff[ND][3];
   T w[3] = {cst<T>(0.f), cst<T>(0.f), cst<T>(0.f)};
   T v[3] = {cst<T>(0.f), cst<T>(0.f), cst<T>(0.f)};
@@ -150,7 +151,6 @@ __host__ __device__ inline void rnea(const Chain &ch, const T *q, const T *qd, c
   T av[3] = {cst<T>(0.f), cst<T>(0.f), cst<T>(gravity ? ch.g : 0.f)};
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
-    sin_cos(q[i], &sq[i], &cq[i]);
     const float L = ch.Lp[i];
     if (i & 1) {
       motion_to_child<true>(cq[i], sq[i], L, w, v);
@@ -360,7 +360,7 @@ __host__ __device__ inline bool forward_dynamics(const Chain &ch, const S *q, co
   S zero[ND], b[ND];
 #pragma unroll
   for (int i = 0; i < ND; ++i) zero[i] = S(0.f);
-  rnea<ND, S>(ch, q, qd, zero, true, b);
+  rnea<ND, S>(ch, q, cq, sq, qd, zero, true, b);
   const bool ok = cholesky<ND, S>(L);
 #pragma unroll
   for (int i = 0; i < ND; ++i) qdd[i] = tau[i] - b[i];
@@ -368,21 +368,36 @@ __host__ __device__ inline bool forward_dynamics(const Chain &ch, const S *q, co
   return ok;
 }
 
-// One column of the Jacobian of forward dynamics: direction dir < ND is q_dir,
-// dir >= ND is qd_(dir-ND). Uses the factor L and qdd from forward_dynamics.
+// -dID/dx_dir at fixed qdd, by one dual-number RNEA pass: direction dir < ND
+// is q_dir, dir >= ND is qd_(dir-ND).
 template <int ND, class S>
-__host__ __device__ inline void fd_jacobian_column(const Chain &ch, const S *q, const S *qd, const S *qdd,
-                                                   const S (*L)[ND], int dir, S *col) {
-  dual<S> Q[ND], QD[ND], QDD[ND], TAU[ND];
+__host__ __device__ inline void id_tangent(const Chain &ch, const S *q, const S *qd, const S *qdd, int dir,
+                                           S *col) {
+  S cv[ND], sv[ND];
+#pragma unroll
+  for (int i = 0; i < ND; ++i) sin_cos(q[i], &sv[i], &cv[i]);
+  // Only joint `dir` carries an angle tangent: d sin = cos, d cos = -sin.
+  dual<S> Q[ND], CQ[ND], SQ[ND], QD[ND], QDD[ND], TAU[ND];
 #pragma unroll
   for (int i = 0; i < ND; ++i) {
-    Q[i] = {q[i], S((dir == i) ? 1.f : 0.f)};
+    const bool on = (dir == i);
+    Q[i] = {q[i], S(on ? 1.f : 0.f)};
+    CQ[i] = {cv[i], on ? -sv[i] : S(0.f)};
+    SQ[i] = {sv[i], on ? cv[i] : S(0.f)};
     QD[i] = {qd[i], S((dir == ND + i) ? 1.f : 0.f)};
     QDD[i] = {qdd[i], S(0.f)};
   }
-  rnea<ND, dual<S>>(ch, Q, QD, QDD, true, TAU);
+  rnea<ND, dual<S>>(ch, Q, CQ, SQ, QD, QDD, true, TAU);
 #pragma unroll
   for (int i = 0; i < ND; ++i) col[i] = -TAU[i].d;
+}
+
+// One column of the Jacobian of forward dynamics, dqdd/dx_dir = -M^-1 dID/dx_dir,
+// using the Cholesky factor L and qdd from forward_dynamics.
+template <int ND, class S>
+__host__ __device__ inline void fd_jacobian_column(const Chain &ch, const S *q, const S *qd, const S *qdd,
+                                                   const S (*L)[ND], int dir, S *col) {
+  id_tangent<ND, S>(ch, q, qd, qdd, dir, col);
   chol_solve<ND, S>(L, col);
 }
 

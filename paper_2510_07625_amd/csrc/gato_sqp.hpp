@@ -1,26 +1,31 @@
 // The fused SQP iteration for one trajectory-optimisation solve per workgroup.
 //
 // One workgroup of kBlock threads owns one solve and runs whole SQP iterations
-// (Algorithm 1) without returning to the host:
-//   1. LQ:     rigid-body dynamics + derivatives at every knot (Sec. III-A,
-//              Eq. (1)); lane (knot, direction) runs one dual-number RNEA.
-//   2. Schur:  lane (knot, row) forms its row of theta_k, phi_k and gamma~
-//              (Eqs. (5)-(6)) and, inside the knot's lane group, the inverse of
-//              the diagonal block by Gauss-Jordan elimination.
-//   3. Precon: its row of the stair preconditioner (Eq. (6)), which needs the
-//              neighbouring knots' inverses (the paper's single grid-wide
-//              synchronisation becomes a workgroup barrier here).
-//   4. PCG:    (Sec. II-B, III-B) with the rows of S~ and P held in registers,
-//              vectors exchanged through LDS and dot products reduced across
-//              the wavefronts of the workgroup.
-//   5. Step:   dZ = -G^-1 (g - C^T lambda) (Eq. (4)).
-//   6. Line search: lane (alpha, knot) evaluates one trial knot (forward
-//              dynamics + stage cost + defect), a fixed-order reduction gives
-//              the merit of Eq. (3) per alpha and the argmin of Eq. (7) picks
-//              the step.
-// The S~ rows, gamma~, PCG vectors and dot products use Real (double by
-// default; float for the all-FP32 variant); the dynamics, line search and the
-// preconditioner application use float.
+// (Algorithm 1) without returning to the host. Knot k of the solve is handled
+// by a group of G lanes (G = 16 for 5..7 DoF, 8 for fewer), so a wavefront
+// holds 64/G knots. Per iteration:
+//   1. LQ (Sec. III-A, Eq. (1)): the group's first lane evaluates forward
+//      dynamics and the Cholesky factor of the inertia matrix and shares them
+//      through LDS; lane d then forms column d of the dynamics Jacobian with one
+//      dual-number RNEA pass. Defects, gradients and the current merit follow.
+//   2. Schur complement (Eqs. (5)-(6)): lane j forms row j of theta_{k-1} and
+//      entry j of gamma~ in FP64, then the group inverts the diagonal block by
+//      Gauss-Jordan elimination (SPD, no pivoting).
+//   3. Stair preconditioner (Eq. (6)): the lanes of knot k+1 form the
+//      off-diagonal block -D_{k+1}^-1 phi_k D_k^-1 once; knot k reads its
+//      transpose. The paper's single grid-wide synchronisation becomes a
+//      workgroup barrier.
+//   4. PCG on S~ lambda = gamma~ (Sec. II-B, III-B) in the pipelined
+//      arrangement: the inner products of an iteration are reduced together
+//      and share a barrier with the vector exchange, so an iteration needs two
+//      workgroup barriers. Rows of S~ and P stay in registers; vectors are
+//      exchanged through LDS.
+//   5. Step dZ = -G^-1 (g - C^T lambda) (Eq. (4)).
+//   6. Line search (Eqs. (3), (7)): lane (alpha, knot) evaluates one trial
+//      knot; a fixed-order reduction gives each candidate's merit.
+// The Schur rows, gamma~, the block inverses, the PCG vectors and its inner
+// products use Real (double; float for the all-FP32 variant). Dynamics, line
+// search and the preconditioner blocks use float.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,13 +40,24 @@ struct Shape {
   static constexpr int NU = ND;
   static constexpr int G = (2 * ND > 8) ? 16 : 8;  // lanes per knot (power of two >= NX)
   static constexpr int SLOTS = kBlock / G;          // knots handled at once
+  static constexpr int NL = ND * (ND + 1) / 2;      // packed Cholesky factor
+};
+
+// QP blocks live in LDS when one knot per lane group suffices (KPT == 1) and
+// in the solve's global workspace otherwise.
+template <int ND, int KPT>
+struct BlockStore {
+  static constexpr bool kLds = (KPT == 1);
+  static constexpr int LB = kLds ? Shape<ND>::SLOTS : 1;
 };
 
 template <int ND, int KPT, class Real>
 struct Smem {
   using Sh = Shape<ND>;
   static constexpr int G = Sh::G;
+  static constexpr int NX = Sh::NX, NU = Sh::NU;
   static constexpr int KN = KPT * Sh::SLOTS;
+  static constexpr int LB = BlockStore<ND, KPT>::LB;
   float X[KN][G];          // iterate
   float U[KN][8];
   float dX[KN][G];         // step
@@ -49,17 +65,23 @@ struct Smem {
   float e[KN][G];          // defects e_k = f(x_k, u_k) - x_{k+1}
   float qg[KN][G];         // state gradients q_k
   float rg[KN][8];         // control gradients r_k
-  float rv[KN][G];         // PCG residual, shared for the preconditioner
-  float gv[KN][G];         // gamma~, shared for the reference norm
-  Real pv[KN][G];          // PCG direction / multipliers, shared
+  Real rv[KN][G];          // PCG residual, shared for the preconditioner
+  Real gv[KN][G];          // gamma~, shared for the reference norm
+  float qdd[KN][8];        // forward dynamics at the knot
+  float Lf[KN][Sh::NL];    // packed Cholesky factor of the inertia matrix
+  Real pv[KN][G];          // vector shared for the S~ product
   Real sv[KN][G];          // Q_k^-1 times pv
   Real piv[Sh::SLOTS][G];  // Gauss-Jordan pivot rows, one per lane group
-  Real red[2][2][kBlock / 64];
+  Real red[2][3][kBlock / 64];
   double mp[kMaxAlpha + 1][KN];  // per-knot merit terms; row n_alpha: current point
   double merit[kMaxAlpha + 1];
   float alpha[kMaxAlpha];
   float xs[G], xg[G], c0[G];
-  int bad[2];  // per-iteration flag, indexed by iteration parity
+  int bad[2];              // per-iteration flag, indexed by iteration parity
+  float A[LB][NX * NX];    // A_k
+  float B[LB][NX * NU];    // B_k
+  float Dinv[LB][NX * NX]; // inverse diagonal blocks of S~
+  float Poff[LB][NX * NX]; // P_{k+1,k}
 };
 
 __device__ __forceinline__ void wave_sync() {
@@ -68,84 +90,123 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ---- Cross-lane sums. Every lane ends with the bit-identical total.
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float swz16(float v) {  // lane ^ 16 inside each half-wave
+  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+}
+__device__ __forceinline__ double swz16(double v) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_val(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_val(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+
+// Sum over the wavefront (all 64 lanes must be active).
 template <class R>
 __device__ __forceinline__ R wave_sum(R v) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-  return v;
+  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp<0x141>(v);  // row_half_mirror
+  v += dpp<0x140>(v);  // row_mirror
+  v += swz16(v);
+  return lane_val(v, 0) + lane_val(v, 32);
 }
 
-// Sum over the workgroup of two values; every thread gets bit-identical
-// results (butterfly inside the wavefront, fixed order across wavefronts).
-template <class Real>
-__device__ __forceinline__ void block_sum2(Real (*red)[2][kBlock / 64], int &buf, Real &a, Real &b) {
-  a = wave_sum(a);
-  b = wave_sum(b);
+// Sum over the workgroup of NV values: butterfly inside each wavefront, then a
+// fixed-order sum of the per-wavefront partials.
+template <int NV, class Real>
+__device__ __forceinline__ void block_sum(Real (*red)[3][kBlock / 64], int &buf, Real *v) {
   const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   if ((threadIdx.x & 63) == 0) {
-    red[buf][0][wave] = a;
-    red[buf][1][wave] = b;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[buf][i][wave] = v[i];
   }
   __syncthreads();
-  Real sa = 0, sb = 0;
 #pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) {
-    sa += red[buf][0][w];
-    sb += red[buf][1][w];
+  for (int i = 0; i < NV; ++i) {
+    Real s = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) s += red[buf][i][w];
+    v[i] = s;
   }
   buf ^= 1;
-  a = sa;
-  b = sb;
-}
-
-template <class Real>
-__device__ __forceinline__ Real block_sum(Real (*red)[2][kBlock / 64], int &buf, Real a) {
-  a = wave_sum(a);
-  const int wave = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) red[buf][0][wave] = a;
-  __syncthreads();
-  Real s = 0;
-#pragma unroll
-  for (int w = 0; w < kBlock / 64; ++w) s += red[buf][0][w];
-  buf ^= 1;
-  return s;
 }
 
 template <int ND, int KPT, class Real>
 __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
   using Sh = Shape<ND>;
   constexpr int NX = Sh::NX, NU = Sh::NU, G = Sh::G, SLOTS = Sh::SLOTS;
+  constexpr bool kLds = BlockStore<ND, KPT>::kLds;
   using SM = Smem<ND, KPT, Real>;
   SM &sm = *reinterpret_cast<SM *>(smem_raw);
   const SolveDesc &D = a.desc[sid];
   const Chain &ch = D.chain;
   const int tid = threadIdx.x;
-  const int lane = tid % G;
-  const int slot = tid / G;
+  const int lane0 = tid % G;
+  const int slot0 = tid / G;
   const int N = D.N;
   const float h = D.dt;
   const int n_alpha = a.n_alpha;
   char *ws = a.ws + D.ws_off;
-  float *gA = reinterpret_cast<float *>(ws + D.offA);    // [N-1][NX][NX]
-  float *gB = reinterpret_cast<float *>(ws + D.offB);    // [N-1][NX][NU]
-  Real *gD = reinterpret_cast<Real *>(ws + D.offD);      // [N][NX][NX]
   const size_t xoff = (size_t)sid * a.N_max * a.nx_max;
-  double *gL = a.lam + xoff;                             // [N][nx_max]
   const size_t uoff = (size_t)sid * (a.N_max - 1) * a.nu_max;
+  double *gL = a.lam + xoff;  // [N][nx_max]
+  const int rid = a.by_block ? (int)blockIdx.x : sid;  // index of xs, goal, stats
+  const int sh = a.shift;
+
+  // Block accessors (LDS or the solve's workspace).
+  auto Ablk = [&](int k) -> float * {
+    if constexpr (kLds) return sm.A[k];
+    else return reinterpret_cast<float *>(ws + D.offA) + (size_t)k * NX * NX;
+  };
+  auto Bblk = [&](int k) -> float * {
+    if constexpr (kLds) return sm.B[k];
+    else return reinterpret_cast<float *>(ws + D.offB) + (size_t)k * NX * NU;
+  };
+  auto Dblk = [&](int k) -> float * {
+    if constexpr (kLds) return sm.Dinv[k];
+    else return reinterpret_cast<float *>(ws + D.offD) + (size_t)k * NX * NX;
+  };
+  auto Pblk = [&](int k) -> float * {
+    if constexpr (kLds) return sm.Poff[k];
+    else return reinterpret_cast<float *>(ws + D.offP) + (size_t)k * NX * NX;
+  };
 
   // ---- Stage the iterate and the solve constants in LDS.
+  // (With a warm-start shift, knot k starts from the previous knot k + shift,
+  // the last knot repeated.)
   for (int t = tid; t < N * G; t += kBlock) {
     const int k = t / G, j = t % G;
-    sm.X[k][j] = (j < NX && a.mode != kModeKkt) ? a.X[xoff + (size_t)k * a.nx_max + j] : 0.f;
+    const int ks = min(k + sh, N - 1);
+    sm.X[k][j] = (j < NX && a.mode != kModeKkt) ? a.X[xoff + (size_t)ks * a.nx_max + j] : 0.f;
   }
   for (int t = tid; t < (N - 1) * 8; t += kBlock) {
     const int k = t / 8, j = t % 8;
-    sm.U[k][j] = (j < NU && a.mode != kModeKkt) ? a.U[uoff + (size_t)k * a.nu_max + j] : 0.f;
+    const int ks = min(k + sh, N - 2);
+    sm.U[k][j] = (j < NU && a.mode != kModeKkt) ? a.U[uoff + (size_t)ks * a.nu_max + j] : 0.f;
   }
   if (tid < G) {
     const bool in = tid < NX && a.mode != kModeKkt;
-    sm.xs[tid] = in ? a.xs[(size_t)sid * a.nx_max + tid] : 0.f;
-    sm.xg[tid] = (in && tid < ND) ? a.goal[(size_t)sid * a.nu_max + tid] : 0.f;
+    sm.xs[tid] = in ? a.xs[(size_t)rid * a.nx_max + tid] : 0.f;
+    sm.xg[tid] = (in && tid < ND) ? a.goal[(size_t)rid * a.nu_max + tid] : 0.f;
   }
   if (tid == 0) {
     sm.bad[0] = 0;
@@ -161,48 +222,44 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
   Real lam[KPT];
 #pragma unroll
   for (int p = 0; p < KPT; ++p) {
-    const int k = slot + p * SLOTS;
-    lam[p] = (a.warm && a.mode == kModeSqp && k < N && lane < NX) ? (Real)gL[k * a.nx_max + lane] : (Real)0;
+    const int k = slot0 + p * SLOTS;
+    lam[p] = (a.warm && a.mode == kModeSqp && k < N && lane0 < NX)
+                 ? (Real)gL[min(k + sh, N - 1) * a.nx_max + lane0] : (Real)0;
   }
   int redbuf = 0;
   __syncthreads();
 
   for (int it = 0; it < a.iters; ++it) {
+    // Opaque per-iteration copies: keeps the compiler from hoisting the many
+    // lane-dependent selects of the phases below out of the iteration loop,
+    // where they would stay live across every phase and spill.
+    int lane = lane0, slot = slot0;
+    asm volatile("" : "+v"(lane), "+v"(slot));
     int &bad_flag = sm.bad[it & 1];
+    unsigned long long *clk = (a.clk && tid == 0) ? a.clk + ((size_t)sid * a.iters + it) * 8 : nullptr;
+    unsigned long long cyc0 = 0;
+    if (clk) {
+      clk[0] = wall_clock64();
+      cyc0 = clock64();
+    }
     // ================= 1. LQ: dynamics, derivatives, defects, gradients.
     if (a.mode != kModeKkt) {
       for (int k = slot; k < N - 1; k += SLOTS) {
-        float q[ND], qd[ND], u[ND], qdd[ND], L[ND][ND];
-#pragma unroll
-        for (int i = 0; i < ND; ++i) {
-          q[i] = sm.X[k][i];
-          qd[i] = sm.X[k][ND + i];
-          u[i] = sm.U[k][i];
-        }
-        const bool ok = forward_dynamics<ND>(ch, q, qd, u, qdd, L);
-        if (lane < NX) {
-          float col[ND];
-          fd_jacobian_column<ND>(ch, q, qd, qdd, L, lane, col);
-          float *Ak = gA + (size_t)k * NX * NX;
+        if (lane == 0) {
+          float q[ND], qd[ND], u[ND], qdd[ND], L[ND][ND];
 #pragma unroll
           for (int i = 0; i < ND; ++i) {
-            Ak[i * NX + lane] = (i == lane ? 1.f : 0.f) + (lane == ND + i ? h : 0.f);
-            Ak[(ND + i) * NX + lane] = h * col[i] + (lane == ND + i ? 1.f : 0.f);
+            q[i] = sm.X[k][i];
+            qd[i] = sm.X[k][ND + i];
+            u[i] = sm.U[k][i];
           }
-          if (lane < ND) {
-            float mi[ND];
+          const bool ok = forward_dynamics<ND>(ch, q, qd, u, qdd, L);
 #pragma unroll
-            for (int i = 0; i < ND; ++i) mi[i] = (i == lane) ? 1.f : 0.f;
-            chol_solve<ND>(L, mi);
-            float *Bk = gB + (size_t)k * NX * NU;
+          for (int i = 0; i < ND; ++i) sm.qdd[k][i] = qdd[i];
 #pragma unroll
-            for (int i = 0; i < ND; ++i) {
-              Bk[i * NU + lane] = 0.f;
-              Bk[(ND + i) * NU + lane] = h * mi[i];
-            }
-          }
-        }
-        if (lane == 0) {
+          for (int i = 0; i < ND; ++i)
+#pragma unroll
+            for (int j = 0; j <= i; ++j) sm.Lf[k][i * (i + 1) / 2 + j] = L[i][j];
           float viol = 0.f, cost = 0.f;
 #pragma unroll
           for (int i = 0; i < ND; ++i) {
@@ -221,6 +278,41 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
           for (int i = 0; i < NU; ++i) cost += 0.5f * D.Wr[i] * u[i] * u[i];
           sm.mp[n_alpha][k] = (double)cost + (double)a.mu * (double)viol;
           if (!ok || !isfinite(viol) || !isfinite(cost)) bad_flag = 1;
+        }
+        wave_sync();
+        if (lane < NX) {
+          float q[ND], qd[ND], qdd[ND], col[ND];
+#pragma unroll
+          for (int i = 0; i < ND; ++i) {
+            q[i] = sm.X[k][i];
+            qd[i] = sm.X[k][ND + i];
+            qdd[i] = sm.qdd[k][i];
+          }
+          id_tangent<ND>(ch, q, qd, qdd, lane, col);
+          float L[ND][ND];
+#pragma unroll
+          for (int i = 0; i < ND; ++i)
+#pragma unroll
+            for (int j = 0; j < ND; ++j) L[i][j] = (j <= i) ? sm.Lf[k][i * (i + 1) / 2 + j] : 0.f;
+          chol_solve<ND>(L, col);
+          float *Ak = Ablk(k);
+#pragma unroll
+          for (int i = 0; i < ND; ++i) {
+            Ak[i * NX + lane] = (i == lane ? 1.f : 0.f) + (lane == ND + i ? h : 0.f);
+            Ak[(ND + i) * NX + lane] = h * col[i] + (lane == ND + i ? 1.f : 0.f);
+          }
+          if (lane < ND) {
+            float mi[ND];
+#pragma unroll
+            for (int i = 0; i < ND; ++i) mi[i] = (i == lane) ? 1.f : 0.f;
+            chol_solve<ND>(L, mi);
+            float *Bk = Bblk(k);
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+              Bk[i * NU + lane] = 0.f;
+              Bk[(ND + i) * NU + lane] = h * mi[i];
+            }
+          }
         }
       }
       for (int t = tid; t < N * G; t += kBlock) {
@@ -246,11 +338,11 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
         const size_t eo = (size_t)sid * (a.N_max - 1) * a.nx_max;
         for (int t = tid; t < (N - 1) * NX * NX; t += kBlock) {
           const int k = t / (NX * NX), r = (t / NX) % NX, c = t % NX;
-          a.outA[ao + ((size_t)k * a.nx_max + r) * a.nx_max + c] = gA[t];
+          a.outA[ao + ((size_t)k * a.nx_max + r) * a.nx_max + c] = Ablk(k)[r * NX + c];
         }
         for (int t = tid; t < (N - 1) * NX * NU; t += kBlock) {
           const int k = t / (NX * NU), r = (t / NU) % NX, c = t % NU;
-          a.outB[bo + ((size_t)k * a.nx_max + r) * a.nu_max + c] = gB[t];
+          a.outB[bo + ((size_t)k * a.nx_max + r) * a.nu_max + c] = Bblk(k)[r * NU + c];
         }
         for (int t = tid; t < (N - 1) * NX; t += kBlock) {
           const int k = t / NX, r = t % NX;
@@ -264,11 +356,11 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
       const size_t bo = (size_t)sid * (a.N_max - 1) * a.nx_max * a.nu_max;
       for (int t = tid; t < (N - 1) * NX * NX; t += kBlock) {
         const int k = t / (NX * NX), r = (t / NX) % NX, c = t % NX;
-        gA[t] = a.inA[ao + ((size_t)k * a.nx_max + r) * a.nx_max + c];
+        Ablk(k)[r * NX + c] = a.inA[ao + ((size_t)k * a.nx_max + r) * a.nx_max + c];
       }
       for (int t = tid; t < (N - 1) * NX * NU; t += kBlock) {
         const int k = t / (NX * NU), r = (t / NU) % NX, c = t % NU;
-        gB[t] = a.inB[bo + ((size_t)k * a.nx_max + r) * a.nu_max + c];
+        Bblk(k)[r * NU + c] = a.inB[bo + ((size_t)k * a.nx_max + r) * a.nu_max + c];
       }
       for (int t = tid; t < N * G; t += kBlock) {
         const int k = t / G, j = t % G;
@@ -284,14 +376,17 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
     // The other parity's flag was last read before the previous iteration's
     // closing barrier; clear it for the next iteration.
     if (tid == 0) sm.bad[(it + 1) & 1] = 0;
+    if (clk) clk[1] = wall_clock64();
 
     // ================= 2. Schur complement rows and diagonal-block inverses.
     Real th[KPT][NX];     // row of the diagonal block theta_{k-1} (Q_0^-1 for k = 0)
+    // A entries are exact in FP32 and are kept so (converted to Real at use),
+    // which halves their register footprint.
     float Am[KPT][NX];    // row `lane` of A_{k-1}: S~_{k,k-1} = -A_{k-1} Q_{k-1}^-1
     float Ac[KPT][NX];    // column `lane` of A_k: S~_{k,k+1} = -Q_k^-1 A_k^T
     Real gam[KPT];
     Real qown[KPT];       // Q_k^-1 at (lane, lane)
-    Real dinv[KPT][NX];   // row of the inverse of the diagonal block
+    Real Pd[KPT][NX];     // row of the inverse diagonal block (preconditioner)
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {
       const int k = slot + p * SLOTS;
@@ -301,7 +396,7 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
         th[p][m] = 0;
         Am[p][m] = 0.f;
         Ac[p][m] = 0.f;
-        dinv[p][m] = 0;
+        Pd[p][m] = 0;
       }
       gam[p] = 0;
       qown[p] = 0;
@@ -314,18 +409,16 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
           gam[p] = (Real)sm.c0[lane] + (Real)D.Qi[lane] * (Real)sm.qg[0][lane];
         } else {
           const int km = k - 1;
-          const float *A = gA + (size_t)km * NX * NX;
-          const float *B = gB + (size_t)km * NX * NU;
-          float Ar[NX], Br[NU];
-#pragma unroll
-          for (int m = 0; m < NX; ++m) Ar[m] = A[lane * NX + m];
-#pragma unroll
-          for (int m = 0; m < NU; ++m) Br[m] = B[lane * NU + m];
+          const float *A = Ablk(km);
+          const float *B = Bblk(km);
           Real ArQ[NX], BrR[NU];
 #pragma unroll
-          for (int m = 0; m < NX; ++m) ArQ[m] = (Real)Ar[m] * (Real)D.Qi[m];
+          for (int m = 0; m < NX; ++m) {
+            Am[p][m] = A[lane * NX + m];
+            ArQ[m] = (Real)Am[p][m] * (Real)D.Qi[m];
+          }
 #pragma unroll
-          for (int m = 0; m < NU; ++m) BrR[m] = (Real)Br[m] * (Real)D.Ri[m];
+          for (int m = 0; m < NU; ++m) BrR[m] = (Real)B[lane * NU + m] * (Real)D.Ri[m];
 #pragma unroll
           for (int c = 0; c < NX; ++c) {
             Real t = (c == lane) ? (Real)Qik[lane] : (Real)0;
@@ -341,11 +434,9 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
 #pragma unroll
           for (int m = 0; m < NU; ++m) z -= BrR[m] * (Real)sm.rg[km][m];
           gam[p] = z;
-#pragma unroll
-          for (int m = 0; m < NX; ++m) Am[p][m] = Ar[m];
         }
         if (k < N - 1) {
-          const float *A = gA + (size_t)k * NX * NX;
+          const float *A = Ablk(k);
 #pragma unroll
           for (int m = 0; m < NX; ++m) Ac[p][m] = A[m * NX + lane];
         }
@@ -356,7 +447,7 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
         if (k == 0) {
           const Real d0 = lane < NX ? (Real)1 / (Real)D.Qi[lane] : (Real)0;
 #pragma unroll
-          for (int m = 0; m < NX; ++m) dinv[p][m] = (m == lane) ? d0 : (Real)0;
+          for (int m = 0; m < NX; ++m) Pd[p][m] = (m == lane) ? d0 : (Real)0;
         } else {
           Real row[NX];
 #pragma unroll
@@ -383,73 +474,81 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
             }
           }
 #pragma unroll
-          for (int c = 0; c < NX; ++c) dinv[p][c] = row[c];
+          for (int c = 0; c < NX; ++c) Pd[p][c] = row[c];
         }
         if (lane < NX) {
-          Real *Dk = gD + (size_t)k * NX * NX + lane * NX;
+          float *Dk = Dblk(k) + lane * NX;
 #pragma unroll
-          for (int c = 0; c < NX; ++c) Dk[c] = dinv[p][c];
+          for (int c = 0; c < NX; ++c) Dk[c] = (float)Pd[p][c];
         }
       }
     }
     __syncthreads();
+    if (clk) clk[2] = wall_clock64();
 
-    // ================= 3. Rows of the stair preconditioner P = -Phi^-1.
-    float Pd[KPT][NX], Pm[KPT][NX], Pp[KPT][NX];
+    // ================= 3. Off-diagonal blocks of the stair preconditioner.
+    // The lanes of knot k (k >= 1) form row `lane` of
+    //   P_{k,k-1} = -D_k^-1 phi_{k-1} D_{k-1}^-1,  phi_{k-1} = -A_{k-1} Q_{k-1}^-1,
+    // keep it, and publish it so that knot k-1 can read its column.
+    // Preconditioner blocks are stored in FP32 and applied in Real arithmetic:
+    // a fixed linear operator, as the pipelined recurrences require.
+    float Pm[KPT][NX], Pp[KPT][NX], Pdf[KPT][NX];
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {
       const int k = slot + p * SLOTS;
       const bool valid = k < N && lane < NX;
 #pragma unroll
       for (int m = 0; m < NX; ++m) {
-        Pd[p][m] = (float)dinv[p][m];
         Pm[p][m] = 0.f;
         Pp[p][m] = 0.f;
+        Pdf[p][m] = (float)Pd[p][m];
       }
       if (valid && k >= 1) {
-        // row of -D_k^-1 phi_{k-1} D_{k-1}^-1, phi_{k-1} = -A_{k-1} Q_{k-1}^-1
-        const float *A = gA + (size_t)(k - 1) * NX * NX;
-        const Real *Dm = gD + (size_t)(k - 1) * NX * NX;
-        Real t[NX];
+        const float *A = Ablk(k - 1);
+        const float *Dm = Dblk(k - 1);
+        float t[NX];
 #pragma unroll
         for (int c = 0; c < NX; ++c) {
-          Real s = 0;
+          float s = 0.f;
 #pragma unroll
-          for (int m = 0; m < NX; ++m) s += dinv[p][m] * (Real)A[m * NX + c];
-          t[c] = s * (Real)D.Qi[c];   // = -(D_k^-1 phi_{k-1})[lane][c]
+          for (int m = 0; m < NX; ++m) s += (float)Pd[p][m] * A[m * NX + c];
+          t[c] = s * (float)D.Qi[c];   // = -(D_k^-1 phi_{k-1})[lane][c]
         }
+        float *Po = Pblk(k - 1) + lane * NX;
 #pragma unroll
         for (int c2 = 0; c2 < NX; ++c2) {
-          Real s = 0;
+          float s = 0.f;
 #pragma unroll
           for (int c = 0; c < NX; ++c) s += t[c] * Dm[c * NX + c2];
-          Pm[p][c2] = (float)s;
-        }
-      }
-      if (valid && k <= N - 2) {
-        // row of (-D_{k+1}^-1 phi_k D_k^-1)^T = column of the block below.
-        const float *A = gA + (size_t)k * NX * NX;
-        const Real *Dp = gD + (size_t)(k + 1) * NX * NX;
-        Real v[NX];
-#pragma unroll
-        for (int m = 0; m < NX; ++m) {
-          Real s = 0;
-#pragma unroll
-          for (int c = 0; c < NX; ++c) s += (Real)A[m * NX + c] * ((Real)D.Qi[c] * dinv[p][c]);
-          v[m] = s;   // = -(phi_k D_k^-1 e_lane)[m]
-        }
-#pragma unroll
-        for (int m2 = 0; m2 < NX; ++m2) {
-          Real s = 0;
-#pragma unroll
-          for (int m = 0; m < NX; ++m) s += Dp[m2 * NX + m] * v[m];
-          Pp[p][m2] = (float)s;
+          Pm[p][c2] = s;
+          Po[c2] = s;
         }
       }
     }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < KPT; ++p) {
+      const int k = slot + p * SLOTS;
+      if (k < N - 1 && lane < NX) {
+        const float *Po = Pblk(k);
+#pragma unroll
+        for (int m = 0; m < NX; ++m) Pp[p][m] = Po[m * NX + lane];   // P_{k,k+1} = P_{k+1,k}^T
+      }
+    }
 
-    // ================= 4. PCG on S~ lambda = gamma~.
-    auto share_p = [&](const Real *vals) {
+    if (clk) clk[3] = wall_clock64();
+    // ================= 4. PCG on S~ lambda = gamma~, pipelined arrangement.
+    // Per iteration, with u = P r, w = S~ u kept by recurrence:
+    //   gamma = (r, u), delta = (w, u)         [partials published with w]
+    //   m = P w, n = S~ m
+    //   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
+    //   z = n + beta z, q = m + beta q, s = w + beta s, p = u + beta p
+    //   lambda += alpha p, r -= alpha s, u -= alpha q, w -= alpha z
+    // In exact arithmetic this is the standard PCG iteration; the reduction of
+    // an iteration shares a workgroup barrier with the vector exchange, so an
+    // iteration needs two barriers and the scalar divisions overlap the
+    // matrix-vector products.
+    auto share_S = [&](const Real *vals) {   // operand of S~: vals and Q^-1 vals
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
         const int k = slot + p * SLOTS;
@@ -458,6 +557,13 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
           sm.pv[k][lane] = valid ? vals[p] : (Real)0;
           sm.sv[k][lane] = valid ? qown[p] * vals[p] : (Real)0;
         }
+      }
+    };
+    auto share_P = [&](const Real *vals, Real (*buf)[G]) {
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) {
+        const int k = slot + p * SLOTS;
+        if (k < N) buf[k][lane] = (lane < NX) ? vals[p] : (Real)0;
       }
     };
     auto apply_S = [&](int p) -> Real {
@@ -477,106 +583,178 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
       }
       return acc;
     };
-    auto apply_P = [&](int p, float (*buf)[G]) -> float {
+    auto apply_P = [&](int p, Real (*buf)[G]) -> Real {
       const int k = slot + p * SLOTS;
-      float acc = 0.f;
+      Real acc = 0;
 #pragma unroll
-      for (int m = 0; m < NX; ++m) acc += Pd[p][m] * buf[k][m];
+      for (int m = 0; m < NX; ++m) acc += (Real)Pdf[p][m] * buf[k][m];
       if (k > 0) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) acc += Pm[p][m] * buf[k - 1][m];
+        for (int m = 0; m < NX; ++m) acc += (Real)Pm[p][m] * buf[k - 1][m];
       }
       if (k < N - 1) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) acc += Pp[p][m] * buf[k + 1][m];
+        for (int m = 0; m < NX; ++m) acc += (Real)Pp[p][m] * buf[k + 1][m];
       }
       return acc;
     };
+    auto row_valid = [&](int p) { return (slot + p * SLOTS) < N && lane < NX; };
 
-    Real r[KPT], z[KPT], pd[KPT];
-    share_p(lam);
+    // r = gamma~ - S~ lambda, u = P r, w = S~ u; eta_ref = gamma~^T P gamma~.
+    Real r[KPT], u[KPT], w[KPT], vm[KPT], vn[KPT], vz[KPT], vq[KPT], vs[KPT], vp[KPT];
+    share_S(lam);
     __syncthreads();
 #pragma unroll
-    for (int p = 0; p < KPT; ++p) {
-      const int k = slot + p * SLOTS;
-      const bool valid = k < N && lane < NX;
-      r[p] = valid ? gam[p] - apply_S(p) : (Real)0;
-      if (k < N) {
-        sm.rv[k][lane] = valid ? (float)r[p] : 0.f;
-        sm.gv[k][lane] = valid ? (float)gam[p] : 0.f;
-      }
-    }
+    for (int p = 0; p < KPT; ++p) r[p] = row_valid(p) ? gam[p] - apply_S(p) : (Real)0;
+    share_P(r, sm.rv);
+    share_P(gam, sm.gv);
     __syncthreads();
-    Real eta = 0, eta_ref = 0;
+    Real eta_ref = 0;
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {
-      const int k = slot + p * SLOTS;
-      const bool valid = k < N && lane < NX;
-      z[p] = valid ? (Real)apply_P(p, sm.rv) : (Real)0;
-      const Real pg = valid ? (Real)apply_P(p, sm.gv) : (Real)0;
-      pd[p] = z[p];
-      eta += r[p] * z[p];
-      eta_ref += gam[p] * pg;
+      u[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
+      eta_ref += row_valid(p) ? gam[p] * apply_P(p, sm.gv) : (Real)0;
     }
-    block_sum2(sm.red, redbuf, eta, eta_ref);
-    const Real stop = (Real)a.pcg_tol * (Real)a.pcg_tol * eta_ref;
     const int max_it = a.pcg_max_iter > 0 ? a.pcg_max_iter : N * NX;
+    Real gma = 0, stop = 0;
     int its = 0;
-    while (eta > stop && its < max_it) {
-      share_p(pd);
+    if constexpr (sizeof(Real) == 4) {
+      // All-FP32 variant: the standard (Hestenes-Stiefel) arrangement, whose
+      // directly computed p^T S~ p tolerates the rounding of FP32 vectors.
+      Real sums[3] = {0, 0, eta_ref};
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) {
+        sums[0] += r[p] * u[p];
+        vp[p] = u[p];
+      }
+      block_sum<3>(sm.red, redbuf, sums);
+      gma = sums[0];
+      stop = (Real)a.pcg_tol * (Real)a.pcg_tol * sums[2];
+      while (gma > stop && its < max_it) {
+        share_S(vp);
+        __syncthreads();
+        Real pw[1] = {0};
+#pragma unroll
+        for (int p = 0; p < KPT; ++p) {
+          w[p] = row_valid(p) ? apply_S(p) : (Real)0;
+          pw[0] += vp[p] * w[p];
+        }
+        block_sum<1>(sm.red, redbuf, pw);
+        const Real alpha = gma / pw[0];
+#pragma unroll
+        for (int p = 0; p < KPT; ++p) {
+          lam[p] += alpha * vp[p];
+          r[p] -= alpha * w[p];
+        }
+        share_P(r, sm.rv);
+        __syncthreads();
+        Real rz[1] = {0};
+#pragma unroll
+        for (int p = 0; p < KPT; ++p) {
+          u[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
+          rz[0] += r[p] * u[p];
+        }
+        block_sum<1>(sm.red, redbuf, rz);
+        const Real beta = rz[0] / gma;
+        gma = rz[0];
+#pragma unroll
+        for (int p = 0; p < KPT; ++p) vp[p] = u[p] + beta * vp[p];
+        ++its;
+      }
+    } else {
+      share_S(u);
       __syncthreads();
-      Real pw = 0, w[KPT];
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
-        const int k = slot + p * SLOTS;
-        const bool valid = k < N && lane < NX;
-        w[p] = valid ? apply_S(p) : (Real)0;
-        pw += pd[p] * w[p];
+        w[p] = row_valid(p) ? apply_S(p) : (Real)0;
+        vz[p] = vq[p] = vs[p] = vp[p] = 0;
       }
-      pw = block_sum(sm.red, redbuf, pw);
-      const Real alpha = eta / pw;
+      eta_ref = wave_sum(eta_ref);
+      const int wave = tid >> 6;
+      if ((tid & 63) == 0) sm.red[redbuf][2][wave] = eta_ref;
+      Real gma_prev = 1, alpha_prev = 1;
+      for (;;) {
+        // Keep the FP32 matrix rows as FP32 across iterations (stops the
+        // compiler from hoisting their conversions and doubling their registers).
 #pragma unroll
-      for (int p = 0; p < KPT; ++p) {
-        const int k = slot + p * SLOTS;
-        lam[p] += alpha * pd[p];
-        r[p] -= alpha * w[p];
-        if (k < N) sm.rv[k][lane] = (float)r[p];
+        for (int p = 0; p < KPT; ++p)
+#pragma unroll
+          for (int m = 0; m < NX; ++m)
+            asm volatile("" : "+v"(Am[p][m]), "+v"(Ac[p][m]), "+v"(Pm[p][m]), "+v"(Pp[p][m]), "+v"(Pdf[p][m]));
+        // Publish w for m = P w together with the partial inner products.
+        Real pr = 0, pwu = 0;
+#pragma unroll
+        for (int p = 0; p < KPT; ++p) {
+          pr += r[p] * u[p];
+          pwu += w[p] * u[p];
+        }
+        pr = wave_sum(pr);
+        pwu = wave_sum(pwu);
+        if ((tid & 63) == 0) {
+          sm.red[redbuf][0][wave] = pr;
+          sm.red[redbuf][1][wave] = pwu;
+        }
+        share_P(w, sm.rv);
+        __syncthreads();
+        Real g4[4], d4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {   // pairwise tree over the eight partials
+          g4[q] = sm.red[redbuf][0][2 * q] + sm.red[redbuf][0][2 * q + 1];
+          d4[q] = sm.red[redbuf][1][2 * q] + sm.red[redbuf][1][2 * q + 1];
+        }
+        gma = (g4[0] + g4[1]) + (g4[2] + g4[3]);
+        const Real dlt = (d4[0] + d4[1]) + (d4[2] + d4[3]);
+        if (its == 0) {
+          Real e4[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) e4[q] = sm.red[redbuf][2][2 * q] + sm.red[redbuf][2][2 * q + 1];
+          stop = (Real)a.pcg_tol * (Real)a.pcg_tol * ((e4[0] + e4[1]) + (e4[2] + e4[3]));
+        }
+        redbuf ^= 1;
+        if (!(gma > stop) || its >= max_it) break;
+#pragma unroll
+        for (int p = 0; p < KPT; ++p) vm[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
+        share_S(vm);
+        const Real beta = (its == 0) ? (Real)0 : gma / gma_prev;
+        const Real alpha = (its == 0) ? gma / dlt : gma / (dlt - beta * gma / alpha_prev);
+        __syncthreads();
+#pragma unroll
+        for (int p = 0; p < KPT; ++p) {
+          vn[p] = row_valid(p) ? apply_S(p) : (Real)0;
+          vz[p] = vn[p] + beta * vz[p];
+          vq[p] = vm[p] + beta * vq[p];
+          vs[p] = w[p] + beta * vs[p];
+          vp[p] = u[p] + beta * vp[p];
+          lam[p] += alpha * vp[p];
+          r[p] -= alpha * vs[p];
+          u[p] -= alpha * vq[p];
+          w[p] -= alpha * vz[p];
+        }
+        gma_prev = gma;
+        alpha_prev = alpha;
+        ++its;
       }
-      __syncthreads();
-      Real eta_new = 0;
-#pragma unroll
-      for (int p = 0; p < KPT; ++p) {
-        const int k = slot + p * SLOTS;
-        const bool valid = k < N && lane < NX;
-        z[p] = valid ? (Real)apply_P(p, sm.rv) : (Real)0;
-        eta_new += r[p] * z[p];
-      }
-      eta_new = block_sum(sm.red, redbuf, eta_new);
-      const Real beta = eta_new / eta;
-      eta = eta_new;
-#pragma unroll
-      for (int p = 0; p < KPT; ++p) pd[p] = z[p] + beta * pd[p];
-      ++its;
     }
-    unsigned status = (eta > stop) ? GATO_ST_PCG_MAXITER : 0u;
+    unsigned status = (gma > stop) ? GATO_ST_PCG_MAXITER : 0u;
+    if (clk) clk[4] = wall_clock64();
 
     // ================= 5. Step recovery dZ = -G^-1 (g - C^T lambda).
-    share_p(lam);
+    share_S(lam);
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {
       const int k = slot + p * SLOTS;
       if (k < N && lane < NX) {
-        Real s = (Real)sm.qg[k][lane] - lam[p];
+        Real sx = (Real)sm.qg[k][lane] - lam[p];
         if (k < N - 1) {
 #pragma unroll
-          for (int m = 0; m < NX; ++m) s += (Real)Ac[p][m] * sm.pv[k + 1][m];
+          for (int m = 0; m < NX; ++m) sx += (Real)Ac[p][m] * sm.pv[k + 1][m];
         }
-        const float dx = (float)(-qown[p] * s);
+        const float dx = (float)(-qown[p] * sx);
         sm.dX[k][lane] = dx;
         if (!isfinite(dx)) bad_flag = 1;
         if (lane < NU && k < N - 1) {
-          const float *B = gB + (size_t)k * NX * NU;
+          const float *B = Bblk(k);
           Real su = (Real)sm.rg[k][lane];
 #pragma unroll
           for (int m = 0; m < NX; ++m) su += (Real)B[m * NU + lane] * sm.pv[k + 1][m];
@@ -601,28 +779,29 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
       return;
     }
     __syncthreads();
+    if (clk) clk[5] = wall_clock64();
 
     // ================= 6. Line search over alpha_i = beta^-i (Eqs. (3), (7)).
     const int ntask = n_alpha * (N - 1);
     for (int t = tid; t < ntask; t += kBlock) {
       const int i = t / (N - 1), k = t - i * (N - 1);
       const float al = sm.alpha[i];
-      float q[ND], qd[ND], u[ND], qdd[ND], L[ND][ND], xn[NX];
+      float q[ND], qd[ND], uu[ND], qdd[ND], L[ND][ND], xn[NX];
 #pragma unroll
       for (int j = 0; j < ND; ++j) {
         q[j] = sm.X[k][j] + al * sm.dX[k][j];
         qd[j] = sm.X[k][ND + j] + al * sm.dX[k][ND + j];
-        u[j] = sm.U[k][j] + al * sm.dU[k][j];
+        uu[j] = sm.U[k][j] + al * sm.dU[k][j];
       }
 #pragma unroll
       for (int j = 0; j < NX; ++j) xn[j] = sm.X[k + 1][j] + al * sm.dX[k + 1][j];
-      forward_dynamics<ND>(ch, q, qd, u, qdd, L);
+      forward_dynamics<ND>(ch, q, qd, uu, qdd, L);
       float viol = 0.f, cost = 0.f;
 #pragma unroll
       for (int j = 0; j < ND; ++j) {
         viol += fabsf((q[j] + h * qd[j]) - xn[j]) + fabsf((qd[j] + h * qdd[j]) - xn[ND + j]);
         const float d0 = q[j] - sm.xg[j], d1 = qd[j] - sm.xg[ND + j];
-        cost += 0.5f * D.Wq[j] * d0 * d0 + 0.5f * D.Wq[ND + j] * d1 * d1 + 0.5f * D.Wr[j] * u[j] * u[j];
+        cost += 0.5f * D.Wq[j] * d0 * d0 + 0.5f * D.Wq[ND + j] * d1 * d1 + 0.5f * D.Wr[j] * uu[j] * uu[j];
       }
       sm.mp[i][k] = (double)cost + (double)a.mu * (double)viol;
     }
@@ -638,9 +817,9 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
     }
     __syncthreads();
     if (tid <= n_alpha) {
-      double s = 0.0;
-      for (int k = 0; k < N; ++k) s += sm.mp[tid][k];
-      sm.merit[tid] = s;
+      double sum = 0.0;
+      for (int k = 0; k < N; ++k) sum += sm.mp[tid][k];
+      sm.merit[tid] = sum;
     }
     __syncthreads();
     int best = -1;
@@ -666,17 +845,30 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
       st.alpha = al;
       st.pcg_iters = its;
       st.status = status;
-      a.stats[(size_t)sid * a.stats_stride + it] = st;
+      a.stats[(size_t)rid * a.stats_stride + it] = st;
     }
     __syncthreads();
+    if (clk) {
+      clk[6] = wall_clock64();
+      clk[7] = clock64() - cyc0;
+    }
   }
 
   // ---- Write back the iterate and the warm-start multipliers.
+  const int lane = lane0, slot = slot0;
   if (a.mode == kModeSqp) {
+    const size_t rxo = (size_t)blockIdx.x * a.N_max * a.nx_max;
+    const size_t ruo = (size_t)blockIdx.x * (a.N_max - 1) * a.nu_max;
     for (int t = tid; t < N * G; t += kBlock) {
       const int k = t / G, j = t % G;
-      if (j < NX) a.X[xoff + (size_t)k * a.nx_max + j] = sm.X[k][j];
-      if (k < N - 1 && j < NU) a.U[uoff + (size_t)k * a.nu_max + j] = sm.U[k][j];
+      if (j < NX) {
+        a.X[xoff + (size_t)k * a.nx_max + j] = sm.X[k][j];
+        if (a.Xout) a.Xout[rxo + (size_t)k * a.nx_max + j] = sm.X[k][j];
+      }
+      if (k < N - 1 && j < NU) {
+        a.U[uoff + (size_t)k * a.nu_max + j] = sm.U[k][j];
+        if (a.Uout) a.Uout[ruo + (size_t)k * a.nu_max + j] = sm.U[k][j];
+      }
     }
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {

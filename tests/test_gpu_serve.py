@@ -1,0 +1,106 @@
+"""Serving path on the GPU: warm-start shift, batch invariance and a served run."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workload as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2510_07625_amd as g  # noqa: E402
+from paper_2510_07625_amd.serve import GpuExecutor, Request, Scheduler  # noqa: E402
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _pool(P, seed=0, **kw):
+    solves = w.chain_batch(seed, P)
+    b = g.Batch.from_solves(solves, g.Params(**kw))
+    xs, goal, X, U = g.pack_inputs(solves)
+    return solves, b, xs, goal, X, U
+
+
+def test_shifted_serve_step_equals_step_on_shifted_trajectory():
+    _say("serve shift")
+    solves, b, xs, goal, X, U = _pool(4, seed=1, sqp_iters=2, warm_lambda=0)
+    b.step(xs, goal, X, U, 2)                   # some non-trivial trajectories
+    b.set_trajectories(X, U)
+    slots = torch.tensor([2, 0], dtype=torch.int32, device="cuda")
+    Xo = torch.zeros((2,) + tuple(X.shape[1:]), device="cuda")
+    Uo = torch.zeros((2,) + tuple(U.shape[1:]), device="cuda")
+    b.serve_step(slots, xs[[2, 0]].contiguous(), goal[[2, 0]].contiguous(), n_iters=1, shift=1, Xout=Xo, Uout=Uo)
+    Xs = torch.cat([X[:, 1:], X[:, -1:]], dim=1).contiguous()
+    Us = torch.cat([U[:, 1:], U[:, -1:]], dim=1).contiguous()
+    b.step(xs, goal, Xs, Us, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(Xo[0], Xs[2]) and torch.equal(Xo[1], Xs[0])
+    assert torch.equal(Uo[0], Us[2]) and torch.equal(Uo[1], Us[0])
+    Xr, Ur = b.get_trajectories()
+    assert torch.equal(Xr[2], Xs[2]) and torch.equal(Xr[1], X[1])   # untouched slots keep their state
+    b.close()
+
+
+def test_result_is_the_same_alone_and_in_the_mix():
+    _say("serve batch invariance")
+    solves, b, xs, goal, X, U = _pool(8, seed=2)
+    b.set_trajectories(X, U)
+    outs = []
+    for slots in ([5], [1, 5, 7, 3]):
+        b.set_trajectories(X, U)
+        b.reset_warm_start()
+        sl = torch.tensor(slots, dtype=torch.int32, device="cuda")
+        Xo = torch.zeros((len(slots),) + tuple(X.shape[1:]), device="cuda")
+        b.serve_step(sl, xs[slots].contiguous(), goal[slots].contiguous(), n_iters=2, shift=1, Xout=Xo)
+        torch.cuda.synchronize()
+        outs.append(Xo[slots.index(5)].clone())
+    assert torch.equal(outs[0], outs[1])
+    b.close()
+
+
+def test_served_resolve_matches_the_oracle():
+    _say("serve parity")
+    solves, b, xs, goal, X, U = _pool(3, seed=3, pcg_tol=1e-7)
+    b.set_trajectories(X, U)
+    sl = torch.tensor([0, 1, 2], dtype=torch.int32, device="cuda")
+    st = torch.zeros(3 * 3 * g.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    Xo = torch.zeros_like(X)
+    Uo = torch.zeros_like(U)
+    b.serve_step(sl, xs, goal, n_iters=3, shift=0, Xout=Xo, Uout=Uo, d_stats=st)
+    stats = g.Batch.decode_stats(st, 3, 3)
+    Xg, Ug = Xo.cpu().numpy(), Uo.cpu().numpy()
+    for i, s in enumerate(solves):
+        ref = oracle.sqp(s, oracle.Params(sqp_iters=3, kkt_mode=0), alpha_replay=stats[i]["alpha"].astype(float))
+        assert np.abs(Xg[i] - ref.X).max() <= 1e-4 * np.abs(ref.X).max()
+        assert np.abs(Ug[i] - ref.U).max() <= 1e-4 * np.abs(ref.U).max()
+    b.close()
+
+
+def test_short_served_run():
+    _say("served run")
+    P = 32
+    solves, b, xs, goal, X, U = _pool(P, seed=4)
+    b.set_trajectories(X, U)
+    ex = GpuExecutor(b, slots=3, n_iters=1)
+    g_ = np.random.default_rng(0)
+    reqs = []
+    t = 0.0
+    for i in range(300):
+        t += g_.exponential(1 / 5000)
+        inst = int(g_.integers(P))
+        reqs.append(Request(i, inst, t, solves[inst].qgoal + g_.normal(0, 0.05, 7)))
+    sch = Scheduler(ex, np.stack([s.xs for s in solves]), deadline_s=1e-3)
+    rep = sch.run(reqs)
+    s = rep.summary()
+    print("served:", s)
+    assert s["completed"] == 300 and s["rejected"] == 0
+    assert all((c.status & g.ST_NONFINITE) == 0 for c in rep.completions)
+    b.close()
