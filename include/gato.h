@@ -91,7 +91,16 @@ typedef struct {
  * Solver settings. The paper defers its values to its code; the defaults set
  * by gato_default_params are: sqp_iters 10, pcg_tol 1e-5, pcg_max_iter 0
  * (= N nx), mu 10, beta 2, n_alpha 8 (alpha_i = beta^-i, i = 0..7), rho 0,
- * schur_fp64 1, warm_lambda 1.
+ * schur_fp64 1, warm_lambda 1, fp64_block_inv 0, fp64_dot 0.
+ *
+ * Precision: with schur_fp64 = 1 the Schur rows, gamma~, the diagonal-block
+ * inverses, the PCG vectors and inner products are FP64 (preconditioner blocks
+ * stored in FP32, applied in FP64; dynamics, line search and trajectories in
+ * FP32). With schur_fp64 = 0 all of it is FP32, and two toggles move single
+ * pieces to FP64: fp64_block_inv (the Gauss-Jordan inversion of the diagonal
+ * blocks; the blocks themselves are formed in FP32) and fp64_dot (the
+ * accumulation of the PCG inner products). The toggles are ignored when
+ * schur_fp64 = 1.
  */
 typedef struct {
   int sqp_iters;       /* SQP iterations per gato_solve */
@@ -102,8 +111,10 @@ typedef struct {
   int n_alpha;         /* candidate steps, 1..GATO_MAX_ALPHA */
   double rho;          /* added to the diagonal of every Q_k (incl. Q_N) */
   int schur_fp64;      /* 1: Schur complement, PCG vectors and dot products in
-                          FP64 (preconditioner applied in FP32); 0: all FP32 */
+                          FP64; 0: all FP32 (see the toggles below) */
   int warm_lambda;     /* 1: PCG starts from the solve's previous multipliers */
+  int fp64_block_inv;  /* schur_fp64 = 0 only: FP64 diagonal-block inversion */
+  int fp64_dot;        /* schur_fp64 = 0 only: FP64 PCG inner-product accumulation */
 } gato_params;
 
 /* Per solve and SQP iteration. */
@@ -225,8 +236,8 @@ int gato_get_trajectories(gato_batch *b, float *d_X, float *d_U);
  * trajectories and, if non-NULL, writes them per request to d_Xout / d_Uout
  * ([n_req][N_max][nx_max], [n_req][N_max-1][nu_max]) and statistics to
  * d_stats ([n_req][n_iters]). Launched on hip_stream (NULL: the batch stream)
- * so that several steps on disjoint slots can overlap. Errors: GATO_EINVAL;
- * GATO_EUNSUPPORTED for batches that mix shapes.
+ * so that several steps on disjoint slots can overlap. Batches that mix shapes
+ * run through the mixed-shape kernel. Errors: GATO_EINVAL.
  */
 int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d_xs, const float *d_goal,
                     int n_iters, int shift, float *d_Xout, float *d_Uout, gato_solve_stats *d_stats,
@@ -234,6 +245,65 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
 
 /* Resets the PCG warm-start multipliers of every solve to zero (stream-ordered). */
 int gato_reset_warm_start(gato_batch *b);
+
+/*
+ * Dispatch of a batch whose solves differ in DoF or horizon (the uneven batch).
+ * A solve's kernel shape is (n_dof, kpt), kpt = knots per 16- (8-) lane group
+ * held in registers by the PCG (1, 2 or 4, at most 2 for 3 DoF; at least
+ * ceil(N / slots), slots = 32 lane groups of 16 for 6-7 DoF, 64 of 8 for 3). The
+ * solves run either as one launch per shape (GATO_DISPATCH_GROUPED) or as
+ * one launch of the mixed-shape kernel, whose workgroups each pick their
+ * solve's specialisation (GATO_DISPATCH_MIXED). AUTO (the default) takes
+ * MIXED when the batch has more than one shape. In both, solves are ordered
+ * by decreasing work so that the longest start first. Algorithm 1 runs each
+ * phase as its own launch over all solves; here a whole SQP step of every
+ * solve is one launch.
+ */
+enum { GATO_DISPATCH_AUTO = 0, GATO_DISPATCH_GROUPED = 1, GATO_DISPATCH_MIXED = 2 };
+int gato_set_dispatch(gato_batch *b, int mode);
+
+/* One (n_dof, N) bucket of a batch and the mapping its solves use. */
+typedef struct {
+  int n_dof;
+  int N;
+  int count;      /* solves in the bucket */
+  int kpt;        /* knots per lane group */
+  float tuned_ms; /* time of the winning candidate in the last gato_autotune, 0 if never tuned */
+} gato_bucket;
+
+/*
+ * Writes up to cap buckets (ordered by n_dof, then N) to out, and their number
+ * to *n_out. Errors: GATO_EINVAL.
+ */
+int gato_buckets(const gato_batch *b, gato_bucket *out, int cap, int *n_out);
+
+/*
+ * Sets the knots-per-group mapping of one bucket by hand. kpt must be 1, 2 or
+ * 4 (at most 2 for 3 DoF) and at least the minimum for N. Errors: GATO_EINVAL (no such bucket, or
+ * kpt not allowed).
+ */
+int gato_set_mapping(gato_batch *b, int n_dof, int N, int kpt);
+
+/*
+ * Autotuner: for every (n_dof, N) bucket, times each allowed kpt on the
+ * bucket's own solves (mixed-shape kernel, n_iters SQP iterations from d_X,
+ * d_U, reps timed runs after one warm-up, HIP events, the median kept) and
+ * keeps the fastest. d_X and d_U are read only (the runs use copies); the PCG
+ * warm start is cleared afterwards. Synchronous; allocates temporary device
+ * memory. Errors: GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE.
+ */
+int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const float *d_X, const float *d_U,
+                  int n_iters, int reps);
+
+/*
+ * gato_step through a HIP graph: the first call with a given argument tuple
+ * (and dispatch mapping) captures the step's launch(es) into a graph and
+ * instantiates it; later calls with the same tuple replay it with one graph
+ * launch on the batch stream. A new tuple or mapping recaptures. Same
+ * semantics, errors and stream ordering as gato_step.
+ */
+int gato_step_graph(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U, int n_iters,
+                    gato_solve_stats *d_stats);
 
 /*
  * Arithmetic operation counts of the per-knot rigid-body routines the kernels

@@ -22,6 +22,7 @@ GATO_OK, GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE, GATO_EUNSUPPORTED = 0, -1, -2, 
 ST_PCG_MAXITER, ST_NONFINITE, ST_NO_DESCENT = 1, 2, 4
 MODEL_SERIAL_CHAIN, MODEL_DOUBLE_INTEGRATOR = 0, 1
 MAX_DOF, MAX_KNOTS, MAX_ALPHA = 7, 128, 16
+DISPATCH_AUTO, DISPATCH_GROUPED, DISPATCH_MIXED = 0, 1, 2
 
 
 class GatoError(RuntimeError):
@@ -43,12 +44,18 @@ class _Problem(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("sqp_iters", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int),
                 ("mu", C.c_double), ("beta", C.c_double), ("n_alpha", C.c_int), ("rho", C.c_double),
-                ("schur_fp64", C.c_int), ("warm_lambda", C.c_int)]
+                ("schur_fp64", C.c_int), ("warm_lambda", C.c_int), ("fp64_block_inv", C.c_int),
+                ("fp64_dot", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("merit0", C.c_float), ("merit", C.c_float), ("alpha", C.c_float), ("pcg_iters", C.c_int),
                 ("status", C.c_uint)]
+
+
+class Bucket(C.Structure):
+    _fields_ = [("n_dof", C.c_int), ("N", C.c_int), ("count", C.c_int), ("kpt", C.c_int),
+                ("tuned_ms", C.c_float)]
 
 
 STATS_DTYPE = np.dtype([("merit0", np.float32), ("merit", np.float32), ("alpha", np.float32),
@@ -58,7 +65,8 @@ STATS_DTYPE = np.dtype([("merit0", np.float32), ("merit", np.float32), ("alpha",
 EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "gato_batch_destroy",
            "gato_batch_shape", "gato_solve", "gato_step", "gato_step_plain", "gato_debug_lq",
            "gato_debug_kkt", "gato_reset_warm_start", "gato_rbd_flops", "gato_profile_phases",
-           "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_last_error")
+           "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_set_dispatch",
+           "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_last_error")
 
 _lib = None
 
@@ -92,6 +100,11 @@ def lib() -> C.CDLL:
         L.gato_set_trajectories.argtypes = [vp, vp, vp]
         L.gato_get_trajectories.argtypes = [vp, vp, vp]
         L.gato_serve_step.argtypes = [vp, ip, vp, vp, vp, ip, ip, vp, vp, vp, vp]
+        L.gato_set_dispatch.argtypes = [vp, ip]
+        L.gato_buckets.argtypes = [vp, C.POINTER(Bucket), ip, C.POINTER(ip)]
+        L.gato_set_mapping.argtypes = [vp, ip, ip, ip]
+        L.gato_autotune.argtypes = [vp, vp, vp, vp, vp, ip, ip]
+        L.gato_step_graph.argtypes = [vp, vp, vp, vp, vp, ip, vp]
         L.gato_last_error.argtypes = []
         L.gato_last_error.restype = C.c_char_p
         _lib = L
@@ -117,10 +130,19 @@ class Params:
     rho: float = 0.0
     schur_fp64: int = 1
     warm_lambda: int = 1
+    fp64_block_inv: int = 0
+    fp64_dot: int = 0
 
     def c(self) -> _Params:
         return _Params(self.sqp_iters, self.pcg_tol, self.pcg_max_iter, self.mu, self.beta, self.n_alpha,
-                       self.rho, self.schur_fp64, self.warm_lambda)
+                       self.rho, self.schur_fp64, self.warm_lambda, self.fp64_block_inv, self.fp64_dot)
+
+    def precision(self) -> str:
+        """Short name of the precision configuration."""
+        if self.schur_fp64:
+            return "fp64-schur"
+        parts = ["fp32"] + (["fp64-inv"] if self.fp64_block_inv else []) + (["fp64-dot"] if self.fp64_dot else [])
+        return "+".join(parts)
 
 
 @dataclass
@@ -272,11 +294,34 @@ class Batch:
         _check(lib().gato_solve(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), None))
         return None
 
-    def step(self, xs, goal, X, U, n_iters: int, d_stats=None, plain: bool = False):
-        """gato_step / gato_step_plain: asynchronous, device-side stats (uint8 tensor or None)."""
+    def step(self, xs, goal, X, U, n_iters: int, d_stats=None, plain: bool = False, graph: bool = False):
+        """gato_step / gato_step_plain / gato_step_graph: asynchronous, device-side stats (uint8 tensor or None)."""
         self._io(xs, goal, X, U)
-        fn = lib().gato_step_plain if plain else lib().gato_step
+        if plain and graph:
+            raise ValueError("plain and graph are exclusive")
+        fn = lib().gato_step_plain if plain else (lib().gato_step_graph if graph else lib().gato_step)
         _check(fn(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), int(n_iters), _dptr(d_stats)))
+
+    def set_dispatch(self, mode: int):
+        """gato_set_dispatch: DISPATCH_AUTO, DISPATCH_GROUPED or DISPATCH_MIXED."""
+        _check(lib().gato_set_dispatch(self._h, int(mode)))
+
+    def buckets(self) -> list:
+        """gato_buckets: [(n_dof, N, count, kpt, tuned_ms)] per (n_dof, N) bucket."""
+        n = C.c_int()
+        _check(lib().gato_buckets(self._h, None, 0, C.byref(n)))
+        arr = (Bucket * max(n.value, 1))()
+        _check(lib().gato_buckets(self._h, arr, n.value, C.byref(n)))
+        return [dict(n_dof=b.n_dof, N=b.N, count=b.count, kpt=b.kpt, tuned_ms=b.tuned_ms) for b in arr[:n.value]]
+
+    def set_mapping(self, n_dof: int, N: int, kpt: int):
+        _check(lib().gato_set_mapping(self._h, int(n_dof), int(N), int(kpt)))
+
+    def autotune(self, xs, goal, X, U, n_iters: int = 2, reps: int = 3) -> list:
+        """gato_autotune: picks the fastest knots-per-group mapping per bucket; returns buckets()."""
+        self._io(xs, goal, X, U)
+        _check(lib().gato_autotune(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), int(n_iters), int(reps)))
+        return self.buckets()
 
     PHASES = ("dynamics", "schur", "precond", "pcg", "step", "line_search")
 

@@ -17,6 +17,8 @@ namespace gato {
 hipError_t launch_sqp_n3(int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
 hipError_t launch_sqp_n6(int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
 hipError_t launch_sqp_n7(int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_mixed_f32(int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_mixed_f64(int grid, const KArgs &a, hipStream_t s);
 
 hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s) {
   switch (nd) {
@@ -65,6 +67,19 @@ Layout layout_for(int n, int N) {
 
 bool pos_finite(double x) { return std::isfinite(x) && x > 0.0; }
 
+// Knots-per-group choices allowed for a solve of n DoF and N knots.
+bool kpt_allowed(int n, int N, int kpt) {
+  const int lo = gato::kpt_for(n, N);
+  return lo > 0 && (kpt == 1 || kpt == 2 || kpt == 4) && kpt >= lo && kpt <= gato::kpt_max(n);
+}
+
+}  // namespace
+
+struct gato_batch;
+static int rebuild_dispatch(gato_batch *b);
+
+namespace {
+
 }  // namespace
 
 struct gato_batch {
@@ -88,7 +103,50 @@ struct gato_batch {
     int *d_order;
   };
   std::vector<Group> groups;
+  int *d_order_all = nullptr;  // every solve, decreasing work (mixed-shape launch)
+  int dispatch = GATO_DISPATCH_AUTO;
+  std::vector<float> tuned_ms;  // per solve: the tuned time of its bucket (0 if never tuned)
+  // Captured step (gato_step_graph).
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  std::vector<uintptr_t> graph_key;
+  unsigned mapping_gen = 0;
 };
+
+// Uploads the descriptors and rebuilds the launch groups and the decreasing-work
+// order from b->desc (after create and after every mapping change).
+static int rebuild_dispatch(gato_batch *b) {
+  const int M = b->M;
+  const auto &desc = b->desc;
+  hipError_t e = hipMemcpy(b->d_desc, desc.data(), M * sizeof(SolveDesc), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(desc)");
+  for (auto &g : b->groups)
+    if (g.d_order) (void)hipFree(g.d_order);
+  b->groups.clear();
+  auto longer = [&](int x, int y) {
+    const long wx = (long)desc[x].N * desc[x].n, wy = (long)desc[y].N * desc[y].n;
+    return wx != wy ? wx > wy : desc[x].N > desc[y].N;
+  };
+  std::vector<int> all(M);
+  for (int i = 0; i < M; ++i) all[i] = i;
+  std::stable_sort(all.begin(), all.end(), longer);
+  e = hipMemcpy(b->d_order_all, all.data(), M * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(order)");
+  std::vector<std::vector<int>> members(64);
+  for (int i : all) members[desc[i].n * 8 + desc[i].kpt].push_back(i);
+  for (int key = 0; key < 64; ++key) {
+    auto &v = members[key];
+    if (v.empty()) continue;
+    gato_batch::Group g{key / 8, key % 8, (int)v.size(), nullptr};
+    e = hipMalloc((void **)&g.d_order, v.size() * sizeof(int));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(order)");
+    b->groups.push_back(g);
+    e = hipMemcpy(g.d_order, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy(order)");
+  }
+  ++b->mapping_gen;
+  return GATO_OK;
+}
 
 extern "C" {
 
@@ -103,6 +161,8 @@ void gato_default_params(gato_params *p) {
   p->rho = 0.0;
   p->schur_fp64 = 1;
   p->warm_lambda = 1;
+  p->fp64_block_inv = 0;
+  p->fp64_dot = 0;
 }
 
 const char *gato_last_error(void) { return g_err.c_str(); }
@@ -116,6 +176,9 @@ static int check_params(const gato_params *p) {
   if (p->n_alpha < 1 || p->n_alpha > GATO_MAX_ALPHA) return fail(GATO_EINVAL, "n_alpha must be in 1..16");
   if (!(std::isfinite(p->rho) && p->rho >= 0.0)) return fail(GATO_EINVAL, "rho must be >= 0");
   if (p->schur_fp64 != 0 && p->schur_fp64 != 1) return fail(GATO_EINVAL, "schur_fp64 must be 0 or 1");
+  if (p->warm_lambda != 0 && p->warm_lambda != 1) return fail(GATO_EINVAL, "warm_lambda must be 0 or 1");
+  if (p->fp64_block_inv != 0 && p->fp64_block_inv != 1) return fail(GATO_EINVAL, "fp64_block_inv must be 0 or 1");
+  if (p->fp64_dot != 0 && p->fp64_dot != 1) return fail(GATO_EINVAL, "fp64_dot must be 0 or 1");
   return GATO_OK;
 }
 
@@ -220,26 +283,14 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
   b->ws_bytes = off;
   b->desc = desc;
 
-  // Group solves by kernel shape; longest horizon first inside a group.
-  std::vector<std::vector<int>> members(64);
-  for (int i = 0; i < M; ++i) members[desc[i].n * 8 + desc[i].kpt].push_back(i);
   hipError_t e;
-  for (int key = 0; key < 64; ++key) {
-    auto &v = members[key];
-    if (v.empty()) continue;
-    std::stable_sort(v.begin(), v.end(), [&](int x, int y) { return desc[x].N > desc[y].N; });
-    gato_batch::Group g{key / 8, key % 8, (int)v.size(), nullptr};
-    e = hipMalloc((void **)&g.d_order, v.size() * sizeof(int));
-    if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(order)"); }
-    e = hipMemcpy(g.d_order, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
-    if (e != hipSuccess) { b->groups.push_back(g); gato_batch_destroy(b); return hip_fail(e, "hipMemcpy(order)"); }
-    b->groups.push_back(g);
-  }
-
+  b->tuned_ms.assign(M, 0.f);
   e = hipMalloc((void **)&b->d_desc, M * sizeof(SolveDesc));
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(desc)"); }
-  e = hipMemcpy(b->d_desc, desc.data(), M * sizeof(SolveDesc), hipMemcpyHostToDevice);
-  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemcpy(desc)"); }
+  e = hipMalloc((void **)&b->d_order_all, M * sizeof(int));
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(order)"); }
+  rc = rebuild_dispatch(b);
+  if (rc != GATO_OK) { gato_batch_destroy(b); return rc; }
   e = hipMalloc((void **)&b->d_ws, b->ws_bytes);
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(workspace)"); }
   e = hipMemset(b->d_ws, 0, b->ws_bytes);
@@ -270,6 +321,9 @@ void gato_batch_destroy(gato_batch *b) {
   else (void)hipDeviceSynchronize();
   for (auto &g : b->groups)
     if (g.d_order) (void)hipFree(g.d_order);
+  if (b->d_order_all) (void)hipFree(b->d_order_all);
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_lam) (void)hipFree(b->d_lam);
@@ -306,19 +360,37 @@ gato::KArgs base_args(gato_batch *b) {
   a.beta = (float)b->p.beta;
   a.n_alpha = b->p.n_alpha;
   a.warm = b->p.warm_lambda;
+  a.fp64_inv = b->p.fp64_block_inv;
+  a.fp64_dot = b->p.fp64_dot;
   return a;
 }
 
-// One launch per shape group, solves mapped through the group's order.
-int launch_groups(gato_batch *b, gato::KArgs a) {
+bool use_mixed(const gato_batch *b) {
+  return b->dispatch == GATO_DISPATCH_MIXED || (b->dispatch == GATO_DISPATCH_AUTO && b->groups.size() > 1);
+}
+
+hipError_t launch_mixed(const gato_batch *b, int grid, const gato::KArgs &a, hipStream_t s) {
+  return b->p.schur_fp64 ? gato::launch_sqp_mixed_f64(grid, a, s) : gato::launch_sqp_mixed_f32(grid, a, s);
+}
+
+// All solves of the batch: one mixed-shape launch over the decreasing-work
+// order, or one launch per shape group.
+int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s) {
+  if (use_mixed(b)) {
+    a.order = b->d_order_all;
+    hipError_t e = launch_mixed(b, b->M, a, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    return GATO_OK;
+  }
   const bool f64 = b->p.schur_fp64 != 0;
   for (const auto &g : b->groups) {
     a.order = g.d_order;
-    hipError_t e = gato::launch_sqp(g.n, g.kpt, f64, g.count, a, b->stream);
+    hipError_t e = gato::launch_sqp(g.n, g.kpt, f64, g.count, a, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
   }
   return GATO_OK;
 }
+int launch_groups(gato_batch *b, const gato::KArgs &a) { return launch_groups(b, a, b->stream); }
 
 int check_io(gato_batch *b, const void *xs, const void *goal, const void *X, const void *U) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
@@ -487,9 +559,6 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
   if (!d_slots || !d_xs || !d_goal) return fail(GATO_EINVAL, "slots, xs and goal must not be NULL");
   if (n_iters < 1) return fail(GATO_EINVAL, "n_iters must be >= 1");
   if (shift < 0 || shift > 1) return fail(GATO_EINVAL, "shift must be 0 or 1");
-  if (b->groups.size() != 1)
-    return fail(GATO_EUNSUPPORTED, "serving needs a batch of one shape (same DoF and knots-per-group)");
-  const auto &g = b->groups[0];
   gato::KArgs a = base_args(b);
   a.xs = d_xs;
   a.goal = d_goal;
@@ -505,7 +574,9 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
   a.Xout = d_Xout;
   a.Uout = d_Uout;
   hipStream_t st = hip_stream ? (hipStream_t)hip_stream : b->stream;
-  hipError_t e = gato::launch_sqp(g.n, g.kpt, b->p.schur_fp64 != 0, n_req, a, st);
+  hipError_t e = b->groups.size() == 1
+                     ? gato::launch_sqp(b->groups[0].n, b->groups[0].kpt, b->p.schur_fp64 != 0, n_req, a, st)
+                     : launch_mixed(b, n_req, a, st);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   return GATO_OK;
 }
@@ -514,6 +585,190 @@ int gato_reset_warm_start(gato_batch *b) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   hipError_t e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, b->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(lambda)");
+  return GATO_OK;
+}
+
+int gato_set_dispatch(gato_batch *b, int mode) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (mode != GATO_DISPATCH_AUTO && mode != GATO_DISPATCH_GROUPED && mode != GATO_DISPATCH_MIXED)
+    return fail(GATO_EINVAL, "unknown dispatch mode");
+  b->dispatch = mode;
+  ++b->mapping_gen;
+  return GATO_OK;
+}
+
+int gato_buckets(const gato_batch *b, gato_bucket *out, int cap, int *n_out) {
+  if (!b || !n_out || (cap > 0 && !out)) return fail(GATO_EINVAL, "batch, n_out or out is NULL");
+  std::vector<gato_bucket> v;
+  for (int i = 0; i < b->M; ++i) {
+    const SolveDesc &d = b->desc[i];
+    auto it = std::find_if(v.begin(), v.end(), [&](const gato_bucket &x) { return x.n_dof == d.n && x.N == d.N; });
+    if (it == v.end()) v.push_back(gato_bucket{d.n, d.N, 1, d.kpt, b->tuned_ms[i]});
+    else ++it->count;
+  }
+  std::sort(v.begin(), v.end(), [](const gato_bucket &x, const gato_bucket &y) {
+    return x.n_dof != y.n_dof ? x.n_dof < y.n_dof : x.N < y.N;
+  });
+  *n_out = (int)v.size();
+  for (int i = 0; i < (int)v.size() && i < cap; ++i) out[i] = v[i];
+  return GATO_OK;
+}
+
+int gato_set_mapping(gato_batch *b, int n_dof, int N, int kpt) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (!kpt_allowed(n_dof, N, kpt)) return fail(GATO_EINVAL, "kpt must be 1, 2 or 4 and cover N");
+  bool any = false;
+  for (auto &d : b->desc)
+    if (d.n == n_dof && d.N == N) {
+      d.kpt = kpt;
+      any = true;
+    }
+  if (!any) return fail(GATO_EINVAL, "no solve of this (n_dof, N) in the batch");
+  hipError_t e = b->stream ? hipStreamSynchronize(b->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  return rebuild_dispatch(b);
+}
+
+int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const float *d_X, const float *d_U,
+                  int n_iters, int reps) {
+  int rc = check_io(b, d_xs, d_goal, d_X, d_U);
+  if (rc) return rc;
+  if (n_iters < 1 || reps < 1) return fail(GATO_EINVAL, "n_iters and reps must be >= 1");
+  hipStream_t s = b->stream;
+  hipError_t e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  // Buckets of (n, N) and their members.
+  std::vector<std::pair<int, int>> keys;
+  std::vector<std::vector<int>> mem;
+  for (int i = 0; i < b->M; ++i) {
+    const auto key = std::make_pair(b->desc[i].n, b->desc[i].N);
+    auto it = std::find(keys.begin(), keys.end(), key);
+    if (it == keys.end()) {
+      keys.push_back(key);
+      mem.push_back({i});
+    } else {
+      mem[it - keys.begin()].push_back(i);
+    }
+  }
+  float *X = nullptr, *U = nullptr;
+  int *order = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    if (X) (void)hipFree(X);
+    if (U) (void)hipFree(U);
+    if (order) (void)hipFree(order);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  e = hipMalloc((void **)&X, b->xres_bytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&U, b->ures_bytes);
+  if (e == hipSuccess) e = hipMalloc((void **)&order, b->M * sizeof(int));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) { cleanup(); return hip_fail(e, "autotune set-up"); }
+  gato::KArgs a = base_args(b);
+  a.xs = d_xs;
+  a.goal = d_goal;
+  a.X = X;
+  a.U = U;
+  a.iters = n_iters;
+  a.mode = gato::kModeSqp;
+  a.order = order;
+  for (size_t k = 0; k < keys.size(); ++k) {
+    const int n = keys[k].first, N = keys[k].second;
+    auto &v = mem[k];
+    std::stable_sort(v.begin(), v.end());
+    e = hipMemcpy(order, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipMemcpy(order)"); }
+    int best = 0;
+    float best_ms = 0.f;
+    for (int kpt : {1, 2, 4}) {
+      if (!kpt_allowed(n, N, kpt)) continue;
+      for (int i : v) b->desc[i].kpt = kpt;
+      e = hipMemcpy(b->d_desc, b->desc.data(), b->M * sizeof(SolveDesc), hipMemcpyHostToDevice);
+      if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipMemcpy(desc)"); }
+      std::vector<float> ms;
+      for (int r = 0; r <= reps; ++r) {
+        e = hipMemcpyAsync(X, d_X, b->xres_bytes, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(U, d_U, b->ures_bytes, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = launch_mixed(b, (int)v.size(), a, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) { cleanup(); return hip_fail(e, "autotune run"); }
+        if (r > 0) ms.push_back(t);
+      }
+      std::sort(ms.begin(), ms.end());
+      const float med = ms[ms.size() / 2];
+      if (best == 0 || med < best_ms) {
+        best = kpt;
+        best_ms = med;
+      }
+    }
+    for (int i : v) {
+      b->desc[i].kpt = best;
+      b->tuned_ms[i] = best_ms;
+    }
+  }
+  cleanup();
+  e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, s);
+  if (e == hipSuccess) e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "autotune clean-up");
+  return rebuild_dispatch(b);
+}
+
+int gato_step_graph(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U, int n_iters,
+                    gato_solve_stats *d_stats) {
+  int rc = check_io(b, d_xs, d_goal, d_X, d_U);
+  if (rc) return rc;
+  if (n_iters < 0) return fail(GATO_EINVAL, "n_iters must be >= 0");
+  if (n_iters == 0) return GATO_OK;
+  const std::vector<uintptr_t> key = {(uintptr_t)d_xs, (uintptr_t)d_goal, (uintptr_t)d_X, (uintptr_t)d_U,
+                                      (uintptr_t)n_iters, (uintptr_t)d_stats, (uintptr_t)b->mapping_gen};
+  hipError_t e;
+  if (!b->graph || key != b->graph_key) {
+    if (b->graph) {
+      e = b->stream ? hipStreamSynchronize(b->stream) : hipDeviceSynchronize();
+      if (e != hipSuccess) return hip_fail(e, "synchronize");
+      (void)hipGraphExecDestroy(b->graph);
+      b->graph = nullptr;
+    }
+    if (!b->cap_stream) {
+      e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    gato::KArgs a = base_args(b);
+    a.xs = d_xs;
+    a.goal = d_goal;
+    a.X = d_X;
+    a.U = d_U;
+    a.iters = n_iters;
+    a.stats = d_stats;
+    a.stats_stride = n_iters;
+    a.mode = gato::kModeSqp;
+    e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    rc = launch_groups(b, a, b->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(b->cap_stream, &g);
+    if (rc != GATO_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      b->graph = nullptr;
+      return hip_fail(e, "hipGraphInstantiate");
+    }
+    b->graph_key = key;
+  }
+  e = hipGraphLaunch(b->graph, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return GATO_OK;
 }
 }  // extern "C"

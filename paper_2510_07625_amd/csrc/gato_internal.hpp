@@ -50,6 +50,8 @@ struct KArgs {
   float beta;
   int n_alpha;
   int warm;
+  int fp64_inv;              // all-FP32 variant: FP64 Gauss-Jordan for the diagonal-block inverses
+  int fp64_dot;              // all-FP32 variant: FP64 accumulation of the PCG inner products
   int mode;
   int sid_base;              // solve index of blockIdx.x == 0
   const int *order;          // optional block -> solve map (longest first), or null

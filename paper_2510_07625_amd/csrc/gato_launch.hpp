@@ -13,12 +13,16 @@ namespace gato {
 // compiled.
 hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
 
-// Register-resident PCG rows: knots per lane group for a solve of n DoF and
-// N knots (0 if N is too large).
+// Largest compiled knots-per-group value for n DoF (3 DoF: 64 lane groups
+// of 8, so 2 knots per group reach the maximum horizon).
+inline int kpt_max(int n) { return 2 * n > 8 ? 4 : 2; }
+
+// Register-resident PCG rows: the smallest knots per lane group for a solve
+// of n DoF and N knots (0 if N is too large).
 inline int kpt_for(int n, int N) {
   const int G = (2 * n > 8) ? 16 : 8;
   const int slots = kBlock / G;
-  for (int k = 1; k <= 4; k *= 2)
+  for (int k = 1; k <= kpt_max(n); k *= 2)
     if (N <= k * slots) return k;
   return 0;
 }

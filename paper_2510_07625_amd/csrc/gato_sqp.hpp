@@ -71,8 +71,8 @@ struct Smem {
   float Lf[KN][Sh::NL];    // packed Cholesky factor of the inertia matrix
   Real pv[KN][G];          // vector shared for the S~ product
   Real sv[KN][G];          // Q_k^-1 times pv
-  Real piv[Sh::SLOTS][G];  // Gauss-Jordan pivot rows, one per lane group
-  Real red[2][3][kBlock / 64];
+  double piv[Sh::SLOTS][G];  // Gauss-Jordan pivot rows, one per lane group
+  double red[2][3][kBlock / 64];  // per-wavefront partial sums
   double mp[kMaxAlpha + 1][KN];  // per-knot merit terms; row n_alpha: current point
   double merit[kMaxAlpha + 1];
   float alpha[kMaxAlpha];
@@ -130,28 +130,29 @@ __device__ __forceinline__ R wave_sum(R v) {
 
 // Sum over the workgroup of NV values: butterfly inside each wavefront, then a
 // fixed-order sum of the per-wavefront partials.
-template <int NV, class Real>
-__device__ __forceinline__ void block_sum(Real (*red)[3][kBlock / 64], int &buf, Real *v) {
+// The partials travel through LDS as double (exact for float values).
+template <int NV, class V>
+__device__ __forceinline__ void block_sum(double (*red)[3][kBlock / 64], int &buf, V *v) {
   const int wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) red[buf][i][wave] = v[i];
+    for (int i = 0; i < NV; ++i) red[buf][i][wave] = (double)v[i];
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    Real s = 0;
+    V s = 0;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) s += red[buf][i][w];
+    for (int w = 0; w < kBlock / 64; ++w) s += (V)red[buf][i][w];
     v[i] = s;
   }
   buf ^= 1;
 }
 
 template <int ND, int KPT, class Real>
-__device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
+__device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
   using Sh = Shape<ND>;
   constexpr int NX = Sh::NX, NU = Sh::NU, G = Sh::G, SLOTS = Sh::SLOTS;
   constexpr bool kLds = BlockStore<ND, KPT>::kLds;
@@ -449,32 +450,39 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
 #pragma unroll
           for (int m = 0; m < NX; ++m) Pd[p][m] = (m == lane) ? d0 : (Real)0;
         } else {
-          Real row[NX];
+          // T: the arithmetic of the elimination (Real, or double when the
+          // all-FP32 variant is asked for an FP64 block inverse).
+          auto gauss_jordan = [&](auto tag) {
+            using T = decltype(tag);
+            T row[NX];
 #pragma unroll
-          for (int c = 0; c < NX; ++c) row[c] = th[p][c];
+            for (int c = 0; c < NX; ++c) row[c] = (T)th[p][c];
 #pragma unroll
-          for (int pv = 0; pv < NX; ++pv) {
-            if (lane == pv) {
+            for (int pv = 0; pv < NX; ++pv) {
+              if (lane == pv) {
 #pragma unroll
-              for (int c = 0; c < NX; ++c) sm.piv[slot][c] = row[c];
+                for (int c = 0; c < NX; ++c) sm.piv[slot][c] = (double)row[c];
+              }
+              wave_sync();
+              T prow[NX];
+#pragma unroll
+              for (int c = 0; c < NX; ++c) prow[c] = (T)sm.piv[slot][c];
+              wave_sync();
+              const T pinv = (T)1 / prow[pv];
+              if (lane == pv) {
+#pragma unroll
+                for (int c = 0; c < NX; ++c) row[c] = (c == pv) ? pinv : row[c] * pinv;
+              } else {
+                const T f = row[pv] * pinv;
+#pragma unroll
+                for (int c = 0; c < NX; ++c) row[c] = (c == pv) ? -f : row[c] - f * prow[c];
+              }
             }
-            wave_sync();
-            Real prow[NX];
 #pragma unroll
-            for (int c = 0; c < NX; ++c) prow[c] = sm.piv[slot][c];
-            wave_sync();
-            const Real pinv = (Real)1 / prow[pv];
-            if (lane == pv) {
-#pragma unroll
-              for (int c = 0; c < NX; ++c) row[c] = (c == pv) ? pinv : row[c] * pinv;
-            } else {
-              const Real f = row[pv] * pinv;
-#pragma unroll
-              for (int c = 0; c < NX; ++c) row[c] = (c == pv) ? -f : row[c] - f * prow[c];
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < NX; ++c) Pd[p][c] = row[c];
+            for (int c = 0; c < NX; ++c) Pd[p][c] = (Real)row[c];
+          };
+          if (sizeof(Real) == 4 && a.fp64_inv) gauss_jordan(double{});
+          else gauss_jordan(Real{});
         }
         if (lane < NX) {
           float *Dk = Dblk(k) + lane * NX;
@@ -621,46 +629,57 @@ __device__ void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
     if constexpr (sizeof(Real) == 4) {
       // All-FP32 variant: the standard (Hestenes-Stiefel) arrangement, whose
       // directly computed p^T S~ p tolerates the rounding of FP32 vectors.
-      Real sums[3] = {0, 0, eta_ref};
-#pragma unroll
-      for (int p = 0; p < KPT; ++p) {
-        sums[0] += r[p] * u[p];
-        vp[p] = u[p];
-      }
-      block_sum<3>(sm.red, redbuf, sums);
-      gma = sums[0];
-      stop = (Real)a.pcg_tol * (Real)a.pcg_tol * sums[2];
-      while (gma > stop && its < max_it) {
-        share_S(vp);
-        __syncthreads();
-        Real pw[1] = {0};
+      // Acc: the accumulation type of the inner products (double when FP64
+      // accumulation is asked for; vectors and updates stay FP32).
+      auto run = [&](auto tag) {
+        using Acc = decltype(tag);
+        Acc sums[3] = {0, 0, 0};
 #pragma unroll
         for (int p = 0; p < KPT; ++p) {
-          w[p] = row_valid(p) ? apply_S(p) : (Real)0;
-          pw[0] += vp[p] * w[p];
+          sums[0] += (Acc)r[p] * (Acc)u[p];
+          sums[2] += row_valid(p) ? (Acc)gam[p] * (Acc)apply_P(p, sm.gv) : (Acc)0;
+          vp[p] = u[p];
         }
-        block_sum<1>(sm.red, redbuf, pw);
-        const Real alpha = gma / pw[0];
+        block_sum<3>(sm.red, redbuf, sums);
+        Acc g = sums[0];
+        const Acc stop_a = (Acc)a.pcg_tol * (Acc)a.pcg_tol * sums[2];
+        while (g > stop_a && its < max_it) {
+          share_S(vp);
+          __syncthreads();
+          Acc pw[1] = {0};
 #pragma unroll
-        for (int p = 0; p < KPT; ++p) {
-          lam[p] += alpha * vp[p];
-          r[p] -= alpha * w[p];
+          for (int p = 0; p < KPT; ++p) {
+            w[p] = row_valid(p) ? apply_S(p) : (Real)0;
+            pw[0] += (Acc)vp[p] * (Acc)w[p];
+          }
+          block_sum<1>(sm.red, redbuf, pw);
+          const Real alpha = (Real)(g / pw[0]);
+#pragma unroll
+          for (int p = 0; p < KPT; ++p) {
+            lam[p] += alpha * vp[p];
+            r[p] -= alpha * w[p];
+          }
+          share_P(r, sm.rv);
+          __syncthreads();
+          Acc rz[1] = {0};
+#pragma unroll
+          for (int p = 0; p < KPT; ++p) {
+            u[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
+            rz[0] += (Acc)r[p] * (Acc)u[p];
+          }
+          block_sum<1>(sm.red, redbuf, rz);
+          const Real beta = (Real)(rz[0] / g);
+          g = rz[0];
+#pragma unroll
+          for (int p = 0; p < KPT; ++p) vp[p] = u[p] + beta * vp[p];
+          ++its;
         }
-        share_P(r, sm.rv);
-        __syncthreads();
-        Real rz[1] = {0};
-#pragma unroll
-        for (int p = 0; p < KPT; ++p) {
-          u[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
-          rz[0] += r[p] * u[p];
-        }
-        block_sum<1>(sm.red, redbuf, rz);
-        const Real beta = rz[0] / gma;
-        gma = rz[0];
-#pragma unroll
-        for (int p = 0; p < KPT; ++p) vp[p] = u[p] + beta * vp[p];
-        ++its;
-      }
+        // Only the convergence test outlives the loop (status bits).
+        gma = (g > stop_a) ? (Real)1 : (Real)0;
+        stop = 0;
+      };
+      if (a.fp64_dot) run(double{});
+      else run(float{});
     } else {
       share_S(u);
       __syncthreads();
@@ -883,6 +902,39 @@ __global__ __launch_bounds__(kBlock) void sqp_kernel(KArgs a) {
   __shared__ __align__(16) char smem[sizeof(Smem<ND, KPT, Real>)];
   const int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
   sqp_solve<ND, KPT, Real>(a, sid, smem);
+}
+
+// Mixed-shape kernel: every workgroup reads its solve's (n, kpt) and runs the
+// matching specialisation, so a batch of uneven DoF and horizon is one launch.
+// The LDS footprint is the largest specialisation's; every specialisation
+// already runs one workgroup per CU, so occupancy is unchanged. (For 3 DoF,
+// two knots per 8-lane group already cover the maximum horizon.)
+template <class Real>
+constexpr size_t mixed_smem_bytes() {
+  size_t m = 0;
+  const size_t s[] = {sizeof(Smem<3, 1, Real>), sizeof(Smem<3, 2, Real>),
+                      sizeof(Smem<6, 1, Real>), sizeof(Smem<6, 2, Real>), sizeof(Smem<6, 4, Real>),
+                      sizeof(Smem<7, 1, Real>), sizeof(Smem<7, 2, Real>), sizeof(Smem<7, 4, Real>)};
+  for (size_t v : s) m = v > m ? v : m;
+  return m;
+}
+
+template <class Real>
+__global__ __launch_bounds__(kBlock) void sqp_mixed_kernel(KArgs a) {
+  __shared__ __align__(16) char smem[mixed_smem_bytes<Real>()];
+  const int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
+  const SolveDesc &D = a.desc[sid];
+  switch (D.n * 8 + D.kpt) {
+    case 3 * 8 + 1: sqp_solve<3, 1, Real>(a, sid, smem); break;
+    case 3 * 8 + 2: sqp_solve<3, 2, Real>(a, sid, smem); break;
+    case 6 * 8 + 1: sqp_solve<6, 1, Real>(a, sid, smem); break;
+    case 6 * 8 + 2: sqp_solve<6, 2, Real>(a, sid, smem); break;
+    case 6 * 8 + 4: sqp_solve<6, 4, Real>(a, sid, smem); break;
+    case 7 * 8 + 1: sqp_solve<7, 1, Real>(a, sid, smem); break;
+    case 7 * 8 + 2: sqp_solve<7, 2, Real>(a, sid, smem); break;
+    case 7 * 8 + 4: sqp_solve<7, 4, Real>(a, sid, smem); break;
+    default: break;  // the host only builds the shapes above
+  }
 }
 
 }  // namespace gato

@@ -11,7 +11,6 @@ hipError_t launch_sqp_n3(int kpt, bool f64, int grid, const KArgs &a, hipStream_
     case 3: hipLaunchKernelGGL((sqp_kernel<3, 1, double>), g, b, 0, s, a); break;
     case 4: hipLaunchKernelGGL((sqp_kernel<3, 2, float>), g, b, 0, s, a); break;
     case 5: hipLaunchKernelGGL((sqp_kernel<3, 2, double>), g, b, 0, s, a); break;
-
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -30,9 +30,13 @@ def test_default_params():
     p = g._Params()
     g.lib().gato_default_params(C.byref(p))
     assert (p.sqp_iters, p.pcg_tol, p.pcg_max_iter, p.mu, p.beta, p.n_alpha, p.rho, p.schur_fp64,
-            p.warm_lambda) == (10, 1e-5, 0, 10.0, 2.0, 8, 0.0, 1, 1)
+            p.warm_lambda, p.fp64_block_inv, p.fp64_dot) == (10, 1e-5, 0, 10.0, 2.0, 8, 0.0, 1, 1, 0, 0)
     d = g.Params()
-    assert (d.sqp_iters, d.pcg_tol, d.n_alpha, d.schur_fp64) == (p.sqp_iters, p.pcg_tol, p.n_alpha, p.schur_fp64)
+    c = d.c()
+    for f, _ in g._Params._fields_:
+        assert getattr(c, f) == getattr(p, f), f"Params default of {f} differs from gato_default_params"
+    assert g.Params().precision() == "fp64-schur"
+    assert g.Params(schur_fp64=0, fp64_dot=1).precision() == "fp32+fp64-dot"
 
 
 def test_workspace_bytes():
@@ -86,4 +90,15 @@ def test_invalid_arguments_are_rejected_on_the_host():
     h = C.c_void_p()
     assert g.lib().gato_batch_create(0, None, None, None, None, C.byref(h)) == g.GATO_EINVAL
     assert g.lib().gato_solve(None, None, None, None, None, None) == g.GATO_EINVAL
+    rc, msg = _create([good_r], [good_p], g.Params(schur_fp64=0, fp64_dot=2))
+    assert rc == g.GATO_EINVAL and "fp64_dot" in msg
+    rc, msg = _create([good_r], [good_p], g.Params(schur_fp64=0, fp64_block_inv=-1))
+    assert rc == g.GATO_EINVAL and "fp64_block_inv" in msg
+    L = g.lib()
+    n = C.c_int()
+    assert L.gato_set_dispatch(None, 0) == g.GATO_EINVAL
+    assert L.gato_buckets(None, None, 0, C.byref(n)) == g.GATO_EINVAL
+    assert L.gato_set_mapping(None, 7, 32, 1) == g.GATO_EINVAL
+    assert L.gato_autotune(None, None, None, None, None, 1, 1) == g.GATO_EINVAL
+    assert L.gato_step_graph(None, None, None, None, None, 1, None) == g.GATO_EINVAL
     del keep

@@ -90,11 +90,17 @@ def test_kkt_parity_on_identical_qp_data(n, N, M, fp64):
     b.close()
 
 
-def test_fp32_schur_misses_the_kkt_tolerance():
-    # The reason the Schur complement and PCG run in FP64: with S~ stored in
-    # FP32 the KKT-solution error stalls near 1e-3 (kappa(S~) ~ 1e5-1e6 here),
-    # while the FP64 variant meets 1e-5 on the same QP data.
-    _say("kkt fp32 vs fp64")
+PRECISIONS = {"fp64-schur": dict(schur_fp64=1), "fp32": dict(schur_fp64=0),
+              "fp32+fp64-inv": dict(schur_fp64=0, fp64_block_inv=1), "fp32+fp64-dot": dict(schur_fp64=0, fp64_dot=1),
+              "fp32+fp64-inv+fp64-dot": dict(schur_fp64=0, fp64_block_inv=1, fp64_dot=1)}
+
+
+def test_precision_toggles_kkt_error():
+    # KKT-solution error on identical QP data for every precision setting.
+    # The FP64 Schur/PCG variant meets 1e-5. With S~ formed and stored in FP32
+    # the error stalls near 1e-3 (kappa(S~) ~ 1e5-1e6 here); the FP64 block
+    # inverse and FP64 inner products are reported beside it.
+    _say("kkt precision toggles")
     n, N, M = 7, 32, 3
     solves = [w.chain_solve(12, i, n=n, N=N) for i in range(M)]
     nx, nu = 2 * n, n
@@ -102,22 +108,26 @@ def test_fp32_schur_misses_the_kkt_tolerance():
     dev = lambda key, shape: torch.from_numpy(np.stack([c[key] for c in cast]).astype(np.float32).reshape(shape)).cuda()
     args = (dev("A", (M, N - 1, nx, nx)), dev("B", (M, N - 1, nx, nu)), dev("e", (M, N - 1, nx)),
             dev("q", (M, N, nx)), dev("r", (M, N - 1, nu)), dev("c0", (M, nx)))
-    errs = {}
-    for fp64 in (0, 1):
-        b = g.Batch.from_solves(solves, g.Params(pcg_tol=1e-7, schur_fp64=fp64))
-        dX, dU, _, _ = (t.cpu().numpy() for t in b.debug_kkt(*args))
+    refs = []
+    for i, s in enumerate(solves):
+        c = cast[i]
+        rX, rU, _, _ = oracle.kkt_from_lq(c["A"], c["B"], c["e"], c["q"], c["r"], c["c0"], _qh(s), s.Rd)
+        refs.append(np.concatenate([rX.ravel(), rU.ravel()]))
+    errs, iters = {}, {}
+    for name, kw in PRECISIONS.items():
+        b = g.Batch.from_solves(solves, g.Params(pcg_tol=1e-7, **kw))
+        dX, dU, _, its = (t.cpu().numpy() for t in b.debug_kkt(*args))
         b.close()
         worst = 0.0
-        for i, s in enumerate(solves):
-            c = cast[i]
-            rX, rU, _, _ = oracle.kkt_from_lq(c["A"], c["B"], c["e"], c["q"], c["r"], c["c0"], _qh(s), s.Rd)
-            ref = np.concatenate([rX.ravel(), rU.ravel()])
+        for i in range(M):
             got = np.concatenate([dX[i].ravel(), dU[i].ravel()])
-            worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
-        errs[fp64] = worst
-    print(f"KKT-solution error: all-FP32 {errs[0]:.2e}, FP64 Schur/PCG {errs[1]:.2e}")
-    assert errs[1] <= 1e-5
-    assert 1e-5 < errs[0] < 1e-2
+            worst = max(worst, np.abs(got - refs[i]).max() / np.abs(refs[i]).max())
+        errs[name], iters[name] = worst, int(its.max())
+    print("KKT-solution error (PCG tol 1e-7): " + ", ".join(f"{k} {v:.2e} ({iters[k]} its)" for k, v in errs.items()))
+    assert errs["fp64-schur"] <= 1e-5
+    assert errs["fp32"] > 1e-5
+    for k, v in errs.items():
+        assert np.isfinite(v) and v < 1e-1, (k, v)
 
 
 def _run_gpu(solves, params, X=None, U=None):
