@@ -11,8 +11,11 @@ timed loop). Inputs are synthetic and resident in HBM before timing starts.
 Also measured: the batch-size sweep M in {1, 16, 32, 64, 128, 256} for the
 batched launch and for the plain form (M one-solve launches in order), per-call
 latency p50/p99 from HIP events, the trajectory error against the FP64 oracle
-on sampled solves, the roofline position of the fused kernel and the oracle's
-CPU throughput on a bounded sample.
+on sampled solves, the roofline position of the fused kernel, every precision
+setting (throughput, trajectory and KKT-solution error), the uneven batch
+(mixed DoF and horizon, per-shape against mixed-shape launch, autotuned,
+graph-captured), the served MPC loop at several Poisson arrival rates, and
+the oracle's CPU throughput on a bounded sample.
 
 Prints one JSON line.
 """
@@ -31,6 +34,31 @@ sys.path.insert(0, ROOT)
 
 PEAK_ALU = 78.6e12       # FP64 (and unpacked FP32) vector FLOP/s: 256 CU x 64 FMA lanes x 2 x 2.4 GHz
 SWEEP = (1, 16, 32, 64, 128, 256)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "sqp_kernel_7dof_N32_M256_hbm_traffic.md")
+KERNEL_SOURCES = ("gato_sqp.hpp", "gato_rbd.hpp", "gato_internal.hpp", "sqp_n7.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary, or None if the kernel sources changed since it was taken."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_07625_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    try:
+        with open(TRAFFIC_SUMMARY) as fh:
+            for line in fh:
+                k, _, v = line.strip().partition(": ")
+                vals[k] = v
+    except OSError:
+        return None
+    if vals.get("kernel-source-sha256-16") != h.hexdigest()[:16]:
+        return None
+    return float(vals["traffic-bytes-per-launch"])
 
 
 def _pcts(ms):
@@ -127,19 +155,156 @@ def end_to_end_ms(g, torch, M, reps, params, seed=0):
 
 
 def accuracy(g, res, params, sample=4):
-    """Max relative trajectory error of sampled solves against the FP64 oracle
-    (dense KKT), the oracle replaying the GPU's accepted steps."""
+    """Max relative trajectory error of sampled solves, the oracle replaying the
+    GPU's accepted steps: against the exact FP64 oracle (dense KKT LU), and
+    against the FP64 oracle running the same method (Schur + PCG at the same
+    tolerance and warm start). The last figure, the FP64 method against the
+    exact oracle, is the truncation of the PCG tolerance itself."""
     import oracle
-    errs = []
+
+    def rel(X, U, ref):
+        return max(np.abs(X - ref.X).max() / np.abs(ref.X).max(), np.abs(U - ref.U).max() / np.abs(ref.U).max())
+
+    e_exact, e_pcg, e_method = [], [], []
     idx = np.linspace(0, res["M"] - 1, min(sample, res["M"])).astype(int)
     for i in idx:
         s = res["solves"][i]
-        ref = oracle.sqp(s, oracle.Params(sqp_iters=params.sqp_iters, kkt_mode=0),
-                         alpha_replay=res["stats"][i]["alpha"].astype(np.float64))
-        ex = np.abs(res["X"][i] - ref.X).max() / np.abs(ref.X).max()
-        eu = np.abs(res["U"][i] - ref.U).max() / np.abs(ref.U).max()
-        errs.append(max(ex, eu))
-    return dict(max_rel_traj_err_vs_fp64_oracle=float(max(errs)), solves_checked=[int(i) for i in idx])
+        al = res["stats"][i]["alpha"].astype(np.float64)
+        common = dict(sqp_iters=params.sqp_iters, mu=params.mu, beta=params.beta, n_alpha=params.n_alpha)
+        exact = oracle.sqp(s, oracle.Params(kkt_mode=0, **common), alpha_replay=al)
+        meth = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=params.pcg_tol, warm_lambda=params.warm_lambda,
+                                           **common), alpha_replay=al)
+        e_exact.append(rel(res["X"][i], res["U"][i], exact))
+        e_pcg.append(rel(res["X"][i], res["U"][i], meth))
+        e_method.append(rel(meth.X, meth.U, exact))
+    return dict(max_rel_traj_err_vs_fp64_oracle=float(max(e_exact)),
+                max_rel_traj_err_vs_fp64_same_method=float(max(e_pcg)),
+                fp64_same_method_vs_exact=float(max(e_method)), solves_checked=[int(i) for i in idx])
+
+
+PRECISIONS = (dict(schur_fp64=1), dict(schur_fp64=0), dict(schur_fp64=0, fp64_block_inv=1),
+              dict(schur_fp64=0, fp64_dot=1), dict(schur_fp64=0, fp64_block_inv=1, fp64_dot=1))
+
+
+def kkt_error(g, torch, params, n_solves=3, seed=12):
+    """KKT-solution error on identical QP data: the oracle's FP64 LQ data at the
+    initial guess, rounded once to FP32, solved by the GPU (Schur + PCG) and by
+    the oracle's dense LU; max over solves of ||dZ_gpu - dZ_ora||_inf / ||dZ_ora||_inf."""
+    import oracle
+    import workload as w
+    solves = [w.chain_solve(seed, i) for i in range(n_solves)]
+    n, N = solves[0].n, solves[0].N
+    nx, nu, M = 2 * n, n, n_solves
+    f32 = lambda a: np.asarray(a, np.float64).astype(np.float32)
+    data = [{k: f32(v) for k, v in oracle.lq(s, s.X0, s.U0).items()} for s in solves]
+    dev = lambda key, shape: torch.from_numpy(np.stack([d[key] for d in data]).reshape(shape)).cuda()
+    b = g.Batch.from_solves(solves, params)
+    dX, dU, _, its = (t.cpu().numpy() for t in b.debug_kkt(
+        dev("A", (M, N - 1, nx, nx)), dev("B", (M, N - 1, nx, nu)), dev("e", (M, N - 1, nx)),
+        dev("q", (M, N, nx)), dev("r", (M, N - 1, nu)), dev("c0", (M, nx))))
+    b.close()
+    worst = 0.0
+    for i, s in enumerate(solves):
+        d = {k: v.astype(np.float64) for k, v in data[i].items()}
+        Qh = np.array([(s.Qd if k < N - 1 else s.QNd) for k in range(N)])
+        rX, rU, _, _ = oracle.kkt_from_lq(d["A"], d["B"], d["e"], d["q"], d["r"], d["c0"], Qh, s.Rd)
+        ref = np.concatenate([rX.ravel(), rU.ravel()])
+        got = np.concatenate([dX[i].ravel(), dU[i].ravel()])
+        worst = max(worst, float(np.abs(got - ref).max() / np.abs(ref).max()))
+    return worst, int(its.max())
+
+
+def precision_report(g, torch, M, steps, pcg_tol, sample=2):
+    """Per precision setting: solves/s of the headline batch, trajectory error of
+    sampled solves against the FP64 oracle, KKT-solution error on identical QP data."""
+    out = []
+    for kw in PRECISIONS:
+        params = g.Params(sqp_iters=10, pcg_tol=pcg_tol, **kw)
+        r = run_batched(g, torch, M, steps, 2, params)
+        km = np.asarray(r["kernel_ms"])
+        acc = accuracy(g, r, params, sample=sample)
+        kkt, its = kkt_error(g, torch, g.Params(pcg_tol=pcg_tol, **kw))
+        out.append(dict(precision=params.precision(), solves_per_s=M / (km.mean() * 1e-3),
+                        max_rel_traj_err=acc["max_rel_traj_err_vs_fp64_oracle"], kkt_rel_err=kkt,
+                        kkt_pcg_iters=its, pcg_iters_per_solve=float(r["stats"]["pcg_iters"].sum(axis=1).mean())))
+        print(f"# precision {out[-1]}", file=sys.stderr, flush=True)
+    return out
+
+
+def uneven_report(g, torch, M=128, steps=3, seed=0):
+    """Uneven batch: M solves with DoF from {3, 6, 7} and N from {16, 32, 64, 128},
+    10 SQP iterations; per-shape launches against one mixed-shape launch, the
+    autotuned mapping, and the graph-captured step; both precisions."""
+    import workload as w
+    solves = w.uneven_batch(seed, M=M)
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    out = {}
+
+    def timed(b, graph=False):
+        X, U = X0.clone(), U0.clone()
+        ms = []
+        for r in range(steps + 1):
+            X.copy_(X0)
+            U.copy_(U0)
+            b.reset_warm_start()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.step(xs, goal, X, U, 10, graph=graph)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    for fp64 in (1, 0):
+        b = g.Batch.from_solves(solves, g.Params(sqp_iters=10, schur_fp64=fp64))
+        b.set_dispatch(g.DISPATCH_GROUPED)
+        t_grouped = timed(b)
+        b.set_dispatch(g.DISPATCH_MIXED)
+        t_mixed = timed(b)
+        buckets = b.autotune(xs, goal, X0, U0, n_iters=2, reps=3)
+        t_tuned = timed(b)
+        t_graph = timed(b, graph=True)
+        b.close()
+        out["fp64-schur" if fp64 else "fp32"] = dict(
+            grouped_ms=t_grouped, mixed_ms=t_mixed, tuned_mixed_ms=t_tuned, tuned_mixed_graph_ms=t_graph,
+            solves_per_s=M / (min(t_tuned, t_graph) * 1e-3),
+            buckets=[(x["n_dof"], x["N"], x["count"], x["kpt"]) for x in buckets])
+        print(f"# uneven {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def serving(g, torch, rates, duration_s, pool=256, iters=1, slots=3, deadline_s=1e-3, seed=0):
+    """Served MPC loop: Poisson arrivals over a pool of instances, each request
+    warm-started from its instance's device-resident trajectory shifted one knot,
+    goal perturbed by N(0, 0.05) rad; continuous batching over `slots` streams."""
+    import workload as w
+    from paper_2510_07625_amd.serve import GpuExecutor, Request, Scheduler
+    solves = w.chain_batch(seed, pool)
+    b = g.Batch.from_solves(solves, g.Params(sqp_iters=iters))
+    xs, goal, X, U = g.pack_inputs(solves)
+    ex = GpuExecutor(b, slots=slots, n_iters=iters)
+    goals = np.stack([s.qgoal for s in solves])
+    out = []
+    for rate in rates:
+        b.set_trajectories(X, U)
+        b.reset_warm_start()
+        torch.cuda.synchronize()
+        rng = np.random.default_rng([seed, int(rate)])
+        n = int(rate * duration_s)
+        t = np.cumsum(rng.exponential(1.0 / rate, n))
+        inst = rng.integers(pool, size=n)
+        reqs = [Request(i, int(inst[i]), float(t[i]), goals[inst[i]] + rng.normal(0.0, 0.05, goals.shape[1]))
+                for i in range(n)]
+        sch = Scheduler(ex, np.stack([s.xs for s in solves]), memory_budget=pool * ex.bytes_per_request,
+                        deadline_s=deadline_s, queue_limit=4 * pool)
+        rep = sch.run(reqs)
+        sm = rep.summary()
+        sm.update(rate_req_s=rate, offered=n, nonfinite=int(sum(1 for c in rep.completions if c.status & 2)))
+        out.append(sm)
+        print(f"# served {rate} req/s: {sm}", file=sys.stderr, flush=True)
+    b.close()
+    return out
 
 
 def cpu_baseline(n_solves=32, threads=None):
@@ -168,11 +333,17 @@ def main():
     ap.add_argument("--pcg-tol", type=float, default=1e-5)
     ap.add_argument("--profile-run", action="store_true",
                     help="only the timed batched steps (no sweep, end-to-end, accuracy or CPU legs)")
+    ap.add_argument("--no-precision", action="store_true", help="skip the per-precision-setting report")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch report")
+    ap.add_argument("--serve-seconds", type=float, default=2.0,
+                    help="duration of each served-loop rate (0 skips the served loop)")
+    ap.add_argument("--serve-rates", type=str, default="2000,5000,10000,20000,50000")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for HBM counter scaling)")
     args = ap.parse_args()
     if args.profile_run:
         args.no_sweep = args.no_cpu = True
+        args.serve_seconds = 0
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; solves shard across GPUs without any exchange, "
                                    "so a multi-GPU run is M/G independent copies of the 1-GPU run",
@@ -200,7 +371,7 @@ def main():
     flops_launch = sum(g.sqp_iteration_flops(7, 32, params.n_alpha, pcg[i]) for i in range(M))
     achieved = flops_launch / (kern.mean() * 1e-3)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_ALU / 1e12, unit="TFLOP/s",
-                frac=achieved / PEAK_ALU, traffic=None,
+                frac=achieved / PEAK_ALU, traffic=measured_traffic(),
                 kernel="gato::sqp_kernel<7, 1, double>",
                 flops_per_launch=flops_launch, avg_kernel_ms=float(kern.mean()),
                 pcg_iters_per_solve=float(pcg.sum(axis=1).mean()))
@@ -217,6 +388,10 @@ def main():
             plain.append(dict(M=m, solves_per_s=m / (np.mean(ms) * 1e-3), p50_ms=a, p99_ms=b))
     e2e = [float("nan")] if args.profile_run else end_to_end_ms(g, torch, M, 10, params)
     acc = None if args.profile_run else accuracy(g, main_res, params)
+    prec = [] if args.profile_run or args.no_precision else precision_report(g, torch, M, 5, args.pcg_tol)
+    uneven = {} if args.profile_run or args.no_uneven else uneven_report(g, torch)
+    served = (serving(g, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
+              if args.serve_seconds > 0 else [])
     out = {
         "metric": "SQP solves/s + p99 latency, 7-DoF N=32 batch 1-256, batched vs plain",
         "value": value,
@@ -239,6 +414,9 @@ def main():
         "sweep_batched": sweep,
         "sweep_plain": plain,
         "accuracy": acc,
+        "precision": prec,
+        "uneven": uneven,
+        "serving": served,
         "roofline": roof,
     }
     if not args.no_cpu:

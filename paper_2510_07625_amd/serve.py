@@ -20,7 +20,8 @@ same methods can stand in for it (the tests use a simulated one).
 from __future__ import annotations
 
 import time
-from dataclasses import dataclass, field
+from collections import deque
+from dataclasses import dataclass
 
 import numpy as np
 
@@ -111,7 +112,12 @@ class Scheduler:
         reqs = sorted(requests, key=lambda r: r.arrival)
         pending = list(reqs)
         pending.reverse()                        # pop() from the end = earliest arrival
-        waiting: list = []
+        # Waiting requests: a FIFO per instance, and a FIFO of the instances
+        # that have a waiting request and nothing in flight (O(1) per request).
+        queues: dict = {}
+        ready: deque = deque()
+        in_ready: set = set()
+        n_waiting = 0
         inflight: list = []
         busy = set()
         bytes_inflight = 0
@@ -119,15 +125,23 @@ class Scheduler:
         launches, launched_reqs, max_inflight = 0, 0, 0
         free_slots = list(range(self.ex.slots))
         per_req = int(self.ex.bytes_per_request)
-        while pending or waiting or inflight:
+
+        def make_ready(inst):
+            if inst not in busy and inst not in in_ready and queues.get(inst):
+                ready.append(inst)
+                in_ready.add(inst)
+
+        while pending or n_waiting or inflight:
             now = self.clock.now()
             # 1. Admit every request that has arrived.
             while pending and pending[-1].arrival <= now:
                 r = pending.pop()
-                if self.queue_limit is not None and len(waiting) >= self.queue_limit:
+                if self.queue_limit is not None and n_waiting >= self.queue_limit:
                     rejected.append(r)
                 else:
-                    waiting.append(r)
+                    queues.setdefault(r.instance, deque()).append(r)
+                    n_waiting += 1
+                    make_ready(r.instance)
             # 2. Retire finished launches (results become host-visible now).
             still = []
             for L in inflight:
@@ -138,39 +152,38 @@ class Scheduler:
                         done.append(Completion(r.rid, r.instance, r.arrival, L.launched, t_done, int(status),
                                                np.asarray(x1), np.asarray(u0)))
                         busy.discard(r.instance)
+                        make_ready(r.instance)
                     bytes_inflight -= L.nbytes
                     free_slots.append(L.handle_slot)
                 else:
                     still.append(L)
             inflight = still
-            # 3. Launch every eligible waiting request while a slot is free.
-            if free_slots and waiting:
-                batch, rest, seen = [], [], set()
+            # 3. Launch the oldest request of every ready instance while a slot is free.
+            if free_slots and ready:
                 room = (self.budget - bytes_inflight) // max(per_req, 1)
-                for r in waiting:
-                    if (r.instance in busy or r.instance in seen or len(batch) >= self.ex.capacity
-                            or len(batch) >= room):
-                        rest.append(r)
-                    else:
-                        batch.append(r)
-                        seen.add(r.instance)
-                if batch:
+                take = min(len(ready), self.ex.capacity, room)
+                if take > 0:
+                    batch = []
+                    for _ in range(take):
+                        inst = ready.popleft()
+                        in_ready.discard(inst)
+                        batch.append(queues[inst].popleft())
+                        busy.add(inst)
+                    n_waiting -= take
                     slot = free_slots.pop()
                     xs = np.stack([self.state[r.instance] for r in batch])
                     t_l = self.clock.now()
                     h = self.ex.launch(slot, batch, xs)
-                    L = _Launch(h, batch, t_l, per_req * len(batch))
+                    L = _Launch(h, batch, t_l, per_req * take)
                     L.handle_slot = slot
                     inflight.append(L)
-                    busy.update(seen)
                     bytes_inflight += L.nbytes
                     launches += 1
-                    launched_reqs += len(batch)
+                    launched_reqs += take
                     max_inflight = max(max_inflight, len(inflight))
-                    waiting = rest
                     continue
             # 4. Nothing to do right now: wait for the next arrival or completion.
-            if not inflight and pending and not (free_slots and waiting):
+            if not inflight and pending and not (free_slots and ready):
                 self.clock.wait_until(pending[-1].arrival)
             elif hasattr(self.clock, "idle"):
                 self.clock.idle(inflight, pending)
