@@ -86,6 +86,7 @@ def lib():
         L.orc_fd_derivatives.argtypes = [rp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_step.argtypes = [rp, C.c_double, dp, dp, dp]
         L.orc_step_jacobians.argtypes = [rp, C.c_double, dp, dp, dp, dp, dp]
+        L.orc_plant_rk4.argtypes = [rp, C.c_double, C.c_int, dp, dp, dp]
         L.orc_lq.argtypes = [rp, pp, C.c_double, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_kkt_parts.argtypes = [rp, pp, C.c_double, dp, dp, dp, dp, dp, dp, dp, dp]
         L.orc_schur.argtypes = [rp, pp, C.c_double, dp, dp, dp, dp, dp, dp, dp]
@@ -163,6 +164,17 @@ def step(s, x, u, h=None) -> np.ndarray:
     xn = np.zeros(2 * s.n)
     if lib().orc_step(C.byref(c.robot), float(s.dt if h is None else h), _ptr(x), _ptr(u), _ptr(xn)) != 0:
         raise FloatingPointError("mass matrix not positive definite")
+    return xn
+
+
+def plant_rk4(s, x, tau, h: float = 0.01, substeps: int = 10) -> np.ndarray:
+    """Closed-loop plant: RK4 on x' = [qd; FD(q, qd, tau)], tau held over h (Sec. IV-E)."""
+    c = _Ctx(s)
+    x, tau = _f64(x), _f64(tau)
+    xn = np.zeros(2 * s.n)
+    rc = lib().orc_plant_rk4(C.byref(c.robot), float(h), int(substeps), _ptr(x), _ptr(tau), _ptr(xn))
+    if rc != 0:
+        raise FloatingPointError("mass matrix not positive definite" if rc == -1 else "substeps must be >= 1")
     return xn
 
 

@@ -408,6 +408,34 @@ bool step(const orc_robot &rb, double h, const double *x, const double *u, doubl
   return true;
 }
 
+// Plant of the closed-loop simulations (Sec. IV-E integrates the robot at
+// 1 kHz with RK4): the continuous dynamics x' = f(x) = [qd; FD(q, qd, tau)],
+// tau held constant over the interval, advanced by `substeps` classical
+// fourth-order Runge-Kutta steps of length h / substeps:
+//   k1 = f(x), k2 = f(x + d/2 k1), k3 = f(x + d/2 k2), k4 = f(x + d k3),
+//   x <- x + d/6 (k1 + 2 k2 + 2 k3 + k4).
+bool plant_rk4(const orc_robot &rb, double h, int substeps, const double *x, const double *tau, double *xn) {
+  const int n = rb.n, nx = 2 * n;
+  const double d = h / substeps;
+  std::vector<double> y(x, x + nx), k1(nx), k2(nx), k3(nx), k4(nx), t(nx);
+  auto f = [&](const double *z, double *out) {
+    for (int i = 0; i < n; ++i) out[i] = z[n + i];
+    return forward_dynamics(rb, z, z + n, tau, out + n, nullptr);
+  };
+  for (int s = 0; s < substeps; ++s) {
+    if (!f(y.data(), k1.data())) return false;
+    for (int i = 0; i < nx; ++i) t[i] = y[i] + 0.5 * d * k1[i];
+    if (!f(t.data(), k2.data())) return false;
+    for (int i = 0; i < nx; ++i) t[i] = y[i] + 0.5 * d * k2[i];
+    if (!f(t.data(), k3.data())) return false;
+    for (int i = 0; i < nx; ++i) t[i] = y[i] + d * k3[i];
+    if (!f(t.data(), k4.data())) return false;
+    for (int i = 0; i < nx; ++i) y[i] += d / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+  }
+  std::memcpy(xn, y.data(), sizeof(double) * nx);
+  return true;
+}
+
 // Jacobians of the Euler step: A = [[I, hI], [h dqdd/dq, I + h dqdd/dqd]],
 // B = [[0], [h M^-1]].
 bool step_jacobians(const orc_robot &rb, double h, const double *x, const double *u, double *xn,
@@ -924,6 +952,11 @@ int orc_fd_derivatives(const orc_robot *rb, const double *q, const double *qd, c
 
 int orc_step(const orc_robot *rb, double h, const double *x, const double *u, double *xn) {
   return step(*rb, h, x, u, xn) ? 0 : -1;
+}
+
+int orc_plant_rk4(const orc_robot *rb, double h, int substeps, const double *x, const double *tau, double *xn) {
+  if (substeps < 1) return -2;
+  return plant_rk4(*rb, h, substeps, x, tau, xn) ? 0 : -1;
 }
 
 int orc_step_jacobians(const orc_robot *rb, double h, const double *x, const double *u, double *xn,
