@@ -45,13 +45,13 @@ class _Problem(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("sqp_iters", C.c_int), ("kkt_mode", C.c_int), ("pcg_tol", C.c_double),
                 ("pcg_max_iter", C.c_int), ("warm_lambda", C.c_int), ("mu", C.c_double),
-                ("beta", C.c_double), ("n_alpha", C.c_int), ("rho", C.c_double)]
+                ("beta", C.c_double), ("n_alpha", C.c_int), ("rho", C.c_double), ("rho_adapt", C.c_int)]
 
 
 class _IterLog(C.Structure):
     _fields_ = [("merit0", C.c_double), ("merit", C.c_double), ("alpha", C.c_double), ("J", C.c_double),
                 ("c1", C.c_double), ("kkt_res", C.c_double), ("pcg_iters", C.c_int), ("status", C.c_int),
-                ("argmin", C.c_int), ("pad", C.c_int), ("merits", C.c_double * MAX_ALPHA)]
+                ("argmin", C.c_int), ("pad", C.c_int), ("rho", C.c_double), ("merits", C.c_double * MAX_ALPHA)]
 
 
 @dataclass
@@ -66,7 +66,8 @@ class Params:
     mu: float = 10.0
     beta: float = 2.0
     n_alpha: int = 8
-    rho: float = 0.0
+    rho: float = 0.0           # initial damping on every Q_k
+    rho_adapt: int = 0         # 1: rho /= 3 after a descent, rho *= 2 after none
 
 
 _lib = None
@@ -97,7 +98,8 @@ def lib():
                                       dp]
         L.orc_merit.argtypes = [rp, pp, dp, dp, dp, dp, C.c_double, dp, dp]
         L.orc_merit.restype = C.c_double
-        L.orc_sqp.argtypes = [rp, pp, C.POINTER(_Params), dp, dp, dp, dp, dp, C.POINTER(_IterLog), dp]
+        L.orc_sqp.argtypes = [rp, pp, C.POINTER(_Params), dp, dp, dp, dp, dp, C.POINTER(_IterLog), dp,
+                              C.POINTER(C.c_int)]
         _lib = L
     return _lib
 
@@ -313,7 +315,8 @@ class SqpResult:
     rc: int
 
 
-def sqp(s, params: Params | None = None, X=None, U=None, lam=None, alpha_replay=None) -> SqpResult:
+def sqp(s, params: Params | None = None, X=None, U=None, lam=None, alpha_replay=None,
+        descent_replay=None) -> SqpResult:
     """The SQP loop for one solve (Sec. II-A, Algorithm 1)."""
     p = params or Params()
     c = _Ctx(s)
@@ -323,18 +326,20 @@ def sqp(s, params: Params | None = None, X=None, U=None, lam=None, alpha_replay=
     lamv = _f64(np.zeros((N, nx)) if lam is None else lam).copy()
     xs, qg = _f64(s.xs), _f64(s.qgoal)
     prm = _Params(p.sqp_iters, p.kkt_mode, p.pcg_tol, p.pcg_max_iter, p.warm_lambda, p.mu, p.beta, p.n_alpha,
-                  p.rho)
+                  p.rho, p.rho_adapt)
     logs = (_IterLog * max(p.sqp_iters, 1))()
     rep = None
     if alpha_replay is not None:
         rep = _f64(alpha_replay)
     rc = lib().orc_sqp(C.byref(c.robot), C.byref(c.prob), C.byref(prm), _ptr(xs), _ptr(qg), _ptr(X), _ptr(U),
-                       _ptr(lamv), logs, _ptr(rep) if rep is not None else None)
+                       _ptr(lamv), logs, _ptr(rep) if rep is not None else None,
+                       (C.c_int * len(descent_replay))(*[int(v) for v in descent_replay])
+                       if descent_replay is not None else None)
     out = []
     for i in range(p.sqp_iters):
         L = logs[i]
         out.append(dict(merit0=L.merit0, merit=L.merit, alpha=L.alpha, J=L.J, c1=L.c1, kkt_res=L.kkt_res,
-                        pcg_iters=L.pcg_iters, status=L.status, argmin=L.argmin,
+                        pcg_iters=L.pcg_iters, status=L.status, argmin=L.argmin, rho=L.rho,
                         merits=np.array(L.merits[:p.n_alpha])))
     return SqpResult(X=X, U=U, lam=lamv, logs=out, rc=rc)
 

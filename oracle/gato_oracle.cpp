@@ -78,7 +78,8 @@ typedef struct {
   double mu;           /* merit weight on ||c||_1 */
   double beta;         /* step ratio, alpha_i = beta^-i */
   int n_alpha;         /* number of candidate steps */
-  double rho;          /* damping added to the diagonal of every Q_k */
+  double rho;          /* damping added to the diagonal of every Q_k (initial value) */
+  int rho_adapt;       /* 1: rho /= 3 after an iteration with descent, rho *= 2 without (capped at 1e8) */
 } orc_params;
 
 #define ORC_MAX_ALPHA 32
@@ -94,6 +95,7 @@ typedef struct {
   int status;          /* 1 PCG max-iter, 2 non-finite, 4 no descent */
   int argmin;
   int pad;
+  double rho;          /* damping used in this iteration */
   double merits[ORC_MAX_ALPHA];
 } orc_iter_log;
 
@@ -1082,20 +1084,25 @@ double orc_merit(const orc_robot *rb, const orc_problem *pr, const double *xs, c
 // hold the initial guess on entry and the result on exit; lam [N nx] carries the
 // PCG warm start in and the last multipliers out. log has sqp_iters entries (or is
 // NULL). alpha_replay (or NULL) prescribes the accepted step of each iteration;
-// a replayed step still records every candidate merit.
+// a replayed step still records every candidate merit. descent_replay (or NULL)
+// prescribes, per iteration, whether the line search counts as a descent for the
+// rho adaptation (1 descent, 0 none), so that a replay follows the same rho
+// sequence when two merits tie at FP32 resolution on the other side.
 int orc_sqp(const orc_robot *rb, const orc_problem *pr, const orc_params *prm, const double *xs,
             const double *qgoal, double *X, double *U, double *lam, orc_iter_log *log,
-            const double *alpha_replay) {
+            const double *alpha_replay, const int *descent_replay) {
   const int n = rb->n, nx = 2 * n, nu = n, N = pr->N;
   const size_t nX = (size_t)N * nx, nU = (size_t)(N - 1) * nu;
   if (prm->n_alpha < 1 || prm->n_alpha > ORC_MAX_ALPHA) return -2;
   std::vector<double> dZ((size_t)N * nx + nU), lamv((size_t)N * nx, 0.0), Xt(nX), Ut(nU);
   if (lam && prm->warm_lambda) std::memcpy(lamv.data(), lam, sizeof(double) * nX);
   int rc = 0;
+  double rho = prm->rho;
   for (int it = 0; it < prm->sqp_iters; ++it) {
     orc_iter_log L;
     std::memset(&L, 0, sizeof(L));
-    Lq lq = build_lq(*rb, *pr, prm->rho, xs, qgoal, X, U);
+    L.rho = rho;
+    Lq lq = build_lq(*rb, *pr, rho, xs, qgoal, X, U);
     bool ok = lq.ok;
     if (prm->kkt_mode == 0) {
       ok = ok && solve_kkt_dense(lq, dZ.data(), lamv.data());
@@ -1116,6 +1123,7 @@ int orc_sqp(const orc_robot *rb, const orc_problem *pr, const orc_params *prm, c
       L.status |= ST_NONFINITE;
       if (log) log[it] = L;
       rc = 1;
+      if (prm->rho_adapt) rho = std::min(2.0 * rho, 1e8);
       continue;
     }
     double J0, c0;
@@ -1153,6 +1161,10 @@ int orc_sqp(const orc_robot *rb, const orc_problem *pr, const orc_params *prm, c
     L.merit = J1 + prm->mu * c1;
     if (L.status) rc = 1;
     if (log) log[it] = L;
+    if (prm->rho_adapt) {
+      const bool descent = descent_replay ? descent_replay[it] != 0 : !(L.status & ST_NO_DESCENT);
+      rho = descent ? rho / 3.0 : std::min(2.0 * rho, 1e8);
+    }
   }
   if (lam) std::memcpy(lam, lamv.data(), sizeof(double) * nX);
   return rc;

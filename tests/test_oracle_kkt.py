@@ -278,3 +278,47 @@ def test_riccati_is_stable_on_long_horizons(oracle_lib, n, N):
     np.testing.assert_allclose(dU, dU_ref, atol=1e-8 * np.abs(dU_ref).max())
     np.testing.assert_allclose(lam.ravel(), lam_ref, atol=1e-8 * np.abs(lam_ref).max())
     assert res < 1e-9
+
+
+def test_rho_damps_only_the_hessian_and_adapts_with_the_line_search(oracle_lib):
+    # rho is added to the diagonal of every Q_k in the QP Hessian only (the
+    # gradient and the merit keep the undamped Q). The step of one iteration is
+    # checked against a numpy-assembled damped KKT system. With rho_adapt, rho
+    # is divided by 3 after an iteration whose best candidate lowers the merit
+    # and doubled otherwise; descent_replay overrides that decision.
+    s = w.double_integrator_solve(0, 2, n=3, N=6, spring_k=1.0)
+    X0 = _rollout(s, s.U0)
+    rho = 0.7
+    G, g, C, c = oracle.kkt_parts(s, X0, s.U0, rho=0.0)
+    nx, N = 6, s.N
+    Gd = G.copy()
+    idx = np.diag_indices_from(Gd)
+    # State blocks of the unknown ordering [x_0, u_0, x_1, u_1, ..., x_{N-1}].
+    is_state = np.zeros(G.shape[0], bool)
+    off = 0
+    for k in range(N):
+        is_state[off:off + nx] = True
+        off += nx + (3 if k < N - 1 else 0)
+    Gd[idx] += np.where(is_state, rho, 0.0)
+    m = C.shape[0]
+    K = np.block([[Gd, C.T], [C, np.zeros((m, m))]])
+    dZ = np.linalg.solve(K, np.concatenate([-g, c]))[:G.shape[0]]
+    dX, dU = oracle.split_dz(s, dZ)
+    res = oracle.sqp(s, oracle.Params(sqp_iters=1, kkt_mode=0, rho=rho), X=X0, U=s.U0,
+                     alpha_replay=np.array([1.0]))
+    np.testing.assert_allclose(res.X, X0 + dX, atol=1e-11)
+    np.testing.assert_allclose(res.U, s.U0 + dU, atol=1e-11)
+    # Adaptation bookkeeping over a nonlinear chain.
+    sc = w.chain_solve(5, 0, n=3, N=12)
+    r = oracle.sqp(sc, oracle.Params(sqp_iters=8, kkt_mode=0, rho=1.0, rho_adapt=1))
+    seq = [L["rho"] for L in r.logs]
+    assert seq[0] == 1.0
+    for i in range(1, 8):
+        nd = r.logs[i - 1]["status"] & 4
+        assert seq[i] == pytest.approx(seq[i - 1] * 2.0 if nd else seq[i - 1] / 3.0, rel=1e-15)
+    forced = [1, 0, 0, 1, 1, 1, 0, 1]
+    r2 = oracle.sqp(sc, oracle.Params(sqp_iters=8, kkt_mode=0, rho=1.0, rho_adapt=1), descent_replay=forced)
+    want = [1.0]
+    for d in forced[:-1]:
+        want.append(want[-1] / 3.0 if d else want[-1] * 2.0)
+    np.testing.assert_allclose([L["rho"] for L in r2.logs], want, rtol=1e-15)
