@@ -14,8 +14,9 @@ latency p50/p99 from HIP events, the trajectory error against the FP64 oracle
 on sampled solves, the roofline position of the fused kernel, every precision
 setting (throughput, trajectory and KKT-solution error), the uneven batch
 (mixed DoF and horizon, per-shape against mixed-shape launch, autotuned,
-graph-captured), the served MPC loop at several Poisson arrival rates, and
-the oracle's CPU throughput on a bounded sample.
+graph-captured), the closed-loop disturbance batch (RK4 plant, torque
+impulses, ticks replayed in the oracle), the served MPC loop at several
+Poisson arrival rates, and the oracle's CPU throughput on a bounded sample.
 
 Prints one JSON line.
 """
@@ -274,6 +275,119 @@ def uneven_report(g, torch, M=128, steps=3, seed=0):
     return out
 
 
+def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, oracle_ticks=150, seed=0,
+                       pcg_tol=1e-5):
+    """Closed-loop disturbance batch: M 7-DoF N-knot MPC instances stepped `ticks`
+    control ticks at dt = 0.01 s, plant RK4 with 10 sub-steps of 1 ms, a torque
+    impulse N(0, 5^2) N m per joint for one tick at ticks 100, 200, ..., 900,
+    `iters` SQP iterations per tick. Reports solves/s and the tracking error;
+    replays sampled ticks of `sample` instances in the FP64 oracle from the same
+    plant state and warm start; runs the FP64 oracle's own closed loop for those
+    instances over the first `oracle_ticks` ticks (report only: the FP32 and
+    FP64 loops may drift apart)."""
+    import dataclasses
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    import workload as w
+    from paper_2510_07625_amd import closed_loop
+    solves = w.chain_batch(seed, M, N=N)
+    b = g.Batch.from_solves(solves, g.Params(sqp_iters=iters, pcg_tol=pcg_tol))
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    b.set_trajectories(X0, U0)
+    rng = np.random.default_rng([seed, 5])
+    kicks = {t: torch.from_numpy(rng.normal(0.0, 5.0, (M, 7)).astype(np.float32)).cuda()
+             for t in range(100, ticks, 100)}
+    idx = np.linspace(0, M - 1, sample).astype(int)
+    rec = sorted({0, 100, 101, ticks // 2, ticks - 1} & set(range(ticks)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run = closed_loop.run(b, xs, goal, ticks, n_iters=iters, disturbance=kicks.get, record_ticks=rec)
+    wall = time.perf_counter() - t0
+    b.close()
+    q = run.states.cpu().numpy()[:, :, :7].astype(np.float64)
+    qg = np.stack([s.qgoal for s in solves])
+    track = np.linalg.norm(q - qg[None], axis=2)              # [ticks + 1, M]
+    mean_track = track.mean(axis=1)
+    dev_ms = float(np.sum(run.tick_ms))
+    # Ticks replayed in the exact FP64 oracle (Riccati, pinned against the dense KKT solve).
+    errs = []
+    for t in rec:
+        R = run.records[t]
+        for i in idx:
+            s = solves[i]
+            Xw = R["X_prev"][i].astype(np.float64)[np.minimum(np.arange(N) + 1, N - 1)]
+            Uw = R["U_prev"][i].astype(np.float64)[np.minimum(np.arange(N - 1) + 1, N - 2)]
+            st = dataclasses.replace(s, xs=R["xs"][i].astype(np.float64))
+            ref = oracle.sqp(st, oracle.Params(sqp_iters=iters, kkt_mode=2), X=Xw, U=Uw,
+                             alpha_replay=R["stats"][i]["alpha"].astype(np.float64))
+            errs.append(max(np.abs(R["X"][i] - ref.X).max() / np.abs(ref.X).max(),
+                            np.abs(R["U"][i] - ref.U).max() / np.abs(ref.U).max()))
+
+    # The oracle's own closed loop for the sampled instances (bounded).
+    def oracle_loop(i):
+        s = solves[i]
+        x, X, U = s.xs.copy(), s.X0.copy(), s.U0.copy()
+        out = [np.linalg.norm(x[:7] - s.qgoal)]
+        for t in range(oracle_ticks):
+            Xw, Uw = X[np.minimum(np.arange(N) + 1, N - 1)], U[np.minimum(np.arange(N - 1) + 1, N - 2)]
+            r = oracle.sqp(dataclasses.replace(s, xs=x), oracle.Params(sqp_iters=iters, kkt_mode=2), X=Xw, U=Uw)
+            X, U = r.X, r.U
+            tau = U[0] + (kicks[t][i].cpu().numpy().astype(np.float64) if t in kicks else 0.0)
+            x = oracle.plant_rk4(s, x, tau, 0.01, 10)
+            out.append(np.linalg.norm(x[:7] - s.qgoal))
+        return np.array(out)
+
+    oracle.lib()
+    t1 = time.perf_counter()
+    with ThreadPoolExecutor(len(idx)) as ex:
+        otrack = np.stack(list(ex.map(oracle_loop, idx)), axis=1)
+    o_wall = time.perf_counter() - t1
+    gtrack = track[:oracle_ticks + 1, idx]
+    p50, p99 = _pcts(run.tick_ms)
+    out = dict(M=M, N=N, ticks=ticks, sqp_iters_per_tick=iters, pcg_tol=pcg_tol,
+               solves_per_s=M * ticks / (dev_ms * 1e-3), wall_solves_per_s=M * ticks / wall,
+               tick_p50_ms=p50, tick_p99_ms=p99,
+               tracking_error_rad=dict(mean=float(mean_track.mean()), final=float(mean_track[-1]),
+                                       before_kicks=[float(mean_track[t]) for t in range(100, ticks, 100)],
+                                       peak_after_kicks=[float(mean_track[t + 1:t + 100].max())
+                                                         for t in range(100, ticks, 100)]),
+               tick_replay_max_rel_err_vs_fp64_oracle=float(max(errs)), ticks_replayed=rec,
+               instances_replayed=[int(i) for i in idx],
+               oracle_loop=dict(ticks=oracle_ticks, wall_s=o_wall,
+                                max_abs_tracking_diff_rad=float(np.abs(otrack - gtrack).max()),
+                                mean_tracking_gpu=float(gtrack.mean()), mean_tracking_oracle=float(otrack.mean())))
+    print(f"# closed loop {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def heatmap(g, torch, Ms=(1, 8, 32, 64, 128, 256, 512), Ns=(8, 16, 32, 64, 128), n=6, iters=1, reps=20):
+    """Time of one batched call of `iters` SQP iterations (a real-time iteration
+    for iters = 1) over M seeded n-DoF chains of N knots, for every (M, N):
+    the batch-size/horizon map of the paper's Fig. 3 (right), on synthetic
+    chains. Median of `reps` HIP-event-timed calls, warm start kept between
+    calls as in a running controller."""
+    import workload as w
+    rows = []
+    for N in Ns:
+        for M in Ms:
+            solves = w.chain_batch(1, M, n=n, N=N)
+            b = g.Batch.from_solves(solves, g.Params(sqp_iters=iters))
+            xs, goal, X, U = g.pack_inputs(solves)
+            ms = []
+            for r in range(reps + 2):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                b.step(xs, goal, X, U, iters)
+                e1.record()
+                torch.cuda.synchronize()
+                if r >= 2:
+                    ms.append(e0.elapsed_time(e1))
+            b.close()
+            rows.append(dict(M=M, N=N, knots=M * N, median_us=float(np.median(ms)) * 1e3))
+            print(f"# heatmap {rows[-1]}", file=sys.stderr, flush=True)
+    return rows
+
+
 def serving(g, torch, rates, duration_s, pool=256, iters=1, slots=3, deadline_s=1e-3, seed=0):
     """Served MPC loop: Poisson arrivals over a pool of instances, each request
     warm-started from its instance's device-resident trajectory shifted one knot,
@@ -335,6 +449,9 @@ def main():
                     help="only the timed batched steps (no sweep, end-to-end, accuracy or CPU legs)")
     ap.add_argument("--no-precision", action="store_true", help="skip the per-precision-setting report")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch report")
+    ap.add_argument("--heatmap", action="store_true",
+                    help="also time one SQP iteration over M in 1..512 x N in 8..128 (6-DoF chains)")
+    ap.add_argument("--closed-loop-ticks", type=int, default=1000, help="ticks of the closed-loop batch (0 skips)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="duration of each served-loop rate (0 skips the served loop)")
     ap.add_argument("--serve-rates", type=str, default="2000,5000,10000,20000,50000")
@@ -390,6 +507,9 @@ def main():
     acc = None if args.profile_run else accuracy(g, main_res, params)
     prec = [] if args.profile_run or args.no_precision else precision_report(g, torch, M, 5, args.pcg_tol)
     uneven = {} if args.profile_run or args.no_uneven else uneven_report(g, torch)
+    hmap = heatmap(g, torch) if args.heatmap else []
+    closed = {} if args.profile_run or args.closed_loop_ticks <= 0 else closed_loop_report(
+        g, torch, ticks=args.closed_loop_ticks)
     served = (serving(g, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
               if args.serve_seconds > 0 else [])
     out = {
@@ -416,6 +536,8 @@ def main():
         "accuracy": acc,
         "precision": prec,
         "uneven": uneven,
+        "closed_loop": closed,
+        "heatmap": hmap,
         "serving": served,
         "roofline": roof,
     }

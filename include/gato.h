@@ -91,7 +91,7 @@ typedef struct {
  * Solver settings. The paper defers its values to its code; the defaults set
  * by gato_default_params are: sqp_iters 10, pcg_tol 1e-5, pcg_max_iter 0
  * (= N nx), mu 10, beta 2, n_alpha 8 (alpha_i = beta^-i, i = 0..7), rho 0,
- * schur_fp64 1, warm_lambda 1, fp64_block_inv 0, fp64_dot 0.
+ * schur_fp64 1, warm_lambda 1, fp64_block_inv 0, fp64_dot 0, rho_adapt 0.
  *
  * Precision: with schur_fp64 = 1 the Schur rows, gamma~, the diagonal-block
  * inverses, the PCG vectors and inner products are FP64 (preconditioner blocks
@@ -109,12 +109,17 @@ typedef struct {
   double mu;           /* merit weight on ||c||_1, Eq. (3) */
   double beta;         /* > 1, Eq. (7) */
   int n_alpha;         /* candidate steps, 1..GATO_MAX_ALPHA */
-  double rho;          /* added to the diagonal of every Q_k (incl. Q_N) */
+  double rho;          /* added to the diagonal of every Q_k (incl. Q_N) in the QP
+                          Hessian; the initial per-solve value (see gato_set_rho) */
   int schur_fp64;      /* 1: Schur complement, PCG vectors and dot products in
                           FP64; 0: all FP32 (see the toggles below) */
   int warm_lambda;     /* 1: PCG starts from the solve's previous multipliers */
   int fp64_block_inv;  /* schur_fp64 = 0 only: FP64 diagonal-block inversion */
   int fp64_dot;        /* schur_fp64 = 0 only: FP64 PCG inner-product accumulation */
+  int rho_adapt;       /* 1: after each SQP iteration a solve's rho is divided by 3
+                          if its line search lowered the merit and doubled (at most
+                          1e8) otherwise, as the case study of Sec. IV-C adjusts
+                          rho from the line-search status */
 } gato_params;
 
 /* Per solve and SQP iteration. */
@@ -124,6 +129,7 @@ typedef struct {
   float alpha;         /* accepted step */
   int pcg_iters;       /* PCG iterations of this SQP iteration */
   unsigned status;     /* GATO_ST_* bits */
+  float rho;           /* damping used in this iteration */
 } gato_solve_stats;
 
 /* Fills *p with the defaults listed above. */
@@ -237,7 +243,8 @@ int gato_get_trajectories(gato_batch *b, float *d_X, float *d_U);
  * ([n_req][N_max][nx_max], [n_req][N_max-1][nu_max]) and statistics to
  * d_stats ([n_req][n_iters]). Launched on hip_stream (NULL: the batch stream)
  * so that several steps on disjoint slots can overlap. Batches that mix shapes
- * run through the mixed-shape kernel. Errors: GATO_EINVAL.
+ * run through the mixed-shape kernel. A slot outside 0..M-1 is skipped (its
+ * outputs are left as they were). Errors: GATO_EINVAL.
  */
 int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d_xs, const float *d_goal,
                     int n_iters, int shift, float *d_Xout, float *d_Uout, gato_solve_stats *d_stats,
@@ -245,6 +252,32 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
 
 /* Resets the PCG warm-start multipliers of every solve to zero (stream-ordered). */
 int gato_reset_warm_start(gato_batch *b);
+
+/*
+ * Plant of closed-loop studies (the simulations of Sec. IV-E integrate the
+ * robot at 1 kHz with RK4). For r < n, advances the state d_x[r] ([n][nx_max],
+ * device) of the robot of slot d_slots[r] (device int array, or NULL for slot
+ * r) by h seconds: `substeps` classical fourth-order Runge-Kutta steps on the
+ * continuous dynamics x' = [qd; M(q)^-1 (tau - b(q, qd))] with tau = d_tau[r]
+ * ([n][nu_max], device) held constant. FP64 arithmetic; the result goes to
+ * d_xn[r] (may be d_x). d_status[r] (device, may be NULL) is 0, or
+ * GATO_ST_NONFINITE for a non-finite result, an indefinite inertia matrix or a
+ * slot outside 0..M-1. Launched on hip_stream (NULL: the batch stream).
+ * Errors: GATO_EINVAL (n outside 1..M, NULL buffers, h <= 0, substeps outside
+ * 1..100000).
+ */
+int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, const float *d_tau, double h,
+                    int substeps, float *d_xn, unsigned *d_status, void *hip_stream);
+
+/*
+ * Per-solve damping rho (Sec. IV-C samples rho across the batch): h_rho[M]
+ * (host, each finite and >= 0) replaces every solve's current rho; with
+ * rho_adapt the kernels update it after every SQP iteration and
+ * gato_get_rho reads it back. gato_reset_warm_start leaves rho as it is.
+ * Synchronous. Errors: GATO_EINVAL, GATO_EDEVICE.
+ */
+int gato_set_rho(gato_batch *b, const double *h_rho);
+int gato_get_rho(gato_batch *b, double *h_rho);
 
 /*
  * Dispatch of a batch whose solves differ in DoF or horizon (the uneven batch).

@@ -45,12 +45,12 @@ class _Params(C.Structure):
     _fields_ = [("sqp_iters", C.c_int), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int),
                 ("mu", C.c_double), ("beta", C.c_double), ("n_alpha", C.c_int), ("rho", C.c_double),
                 ("schur_fp64", C.c_int), ("warm_lambda", C.c_int), ("fp64_block_inv", C.c_int),
-                ("fp64_dot", C.c_int)]
+                ("fp64_dot", C.c_int), ("rho_adapt", C.c_int)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("merit0", C.c_float), ("merit", C.c_float), ("alpha", C.c_float), ("pcg_iters", C.c_int),
-                ("status", C.c_uint)]
+                ("status", C.c_uint), ("rho", C.c_float)]
 
 
 class Bucket(C.Structure):
@@ -59,14 +59,15 @@ class Bucket(C.Structure):
 
 
 STATS_DTYPE = np.dtype([("merit0", np.float32), ("merit", np.float32), ("alpha", np.float32),
-                        ("pcg_iters", np.int32), ("status", np.uint32)])
+                        ("pcg_iters", np.int32), ("status", np.uint32), ("rho", np.float32)])
 
 # Entry points declared in include/gato.h.
 EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "gato_batch_destroy",
            "gato_batch_shape", "gato_solve", "gato_step", "gato_step_plain", "gato_debug_lq",
            "gato_debug_kkt", "gato_reset_warm_start", "gato_rbd_flops", "gato_profile_phases",
-           "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_set_dispatch",
-           "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_last_error")
+           "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_plant_step", "gato_set_dispatch",
+           "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_set_rho", "gato_get_rho",
+           "gato_last_error")
 
 _lib = None
 
@@ -100,7 +101,10 @@ def lib() -> C.CDLL:
         L.gato_set_trajectories.argtypes = [vp, vp, vp]
         L.gato_get_trajectories.argtypes = [vp, vp, vp]
         L.gato_serve_step.argtypes = [vp, ip, vp, vp, vp, ip, ip, vp, vp, vp, vp]
+        L.gato_plant_step.argtypes = [vp, ip, vp, vp, vp, C.c_double, ip, vp, vp, vp]
         L.gato_set_dispatch.argtypes = [vp, ip]
+        L.gato_set_rho.argtypes = [vp, C.POINTER(C.c_double)]
+        L.gato_get_rho.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_buckets.argtypes = [vp, C.POINTER(Bucket), ip, C.POINTER(ip)]
         L.gato_set_mapping.argtypes = [vp, ip, ip, ip]
         L.gato_autotune.argtypes = [vp, vp, vp, vp, vp, ip, ip]
@@ -132,10 +136,12 @@ class Params:
     warm_lambda: int = 1
     fp64_block_inv: int = 0
     fp64_dot: int = 0
+    rho_adapt: int = 0
 
     def c(self) -> _Params:
         return _Params(self.sqp_iters, self.pcg_tol, self.pcg_max_iter, self.mu, self.beta, self.n_alpha,
-                       self.rho, self.schur_fp64, self.warm_lambda, self.fp64_block_inv, self.fp64_dot)
+                       self.rho, self.schur_fp64, self.warm_lambda, self.fp64_block_inv, self.fp64_dot,
+                       self.rho_adapt)
 
     def precision(self) -> str:
         """Short name of the precision configuration."""
@@ -302,6 +308,16 @@ class Batch:
         fn = lib().gato_step_plain if plain else (lib().gato_step_graph if graph else lib().gato_step)
         _check(fn(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), int(n_iters), _dptr(d_stats)))
 
+    def set_rho(self, rho):
+        """gato_set_rho: per-solve damping (M values)."""
+        r = np.ascontiguousarray(np.broadcast_to(np.asarray(rho, np.float64), (self.M,)))
+        _check(lib().gato_set_rho(self._h, r.ctypes.data_as(C.POINTER(C.c_double))))
+
+    def get_rho(self) -> np.ndarray:
+        r = np.zeros(self.M, np.float64)
+        _check(lib().gato_get_rho(self._h, r.ctypes.data_as(C.POINTER(C.c_double))))
+        return r
+
     def set_dispatch(self, mode: int):
         """gato_set_dispatch: DISPATCH_AUTO, DISPATCH_GROUPED or DISPATCH_MIXED."""
         _check(lib().gato_set_dispatch(self._h, int(mode)))
@@ -404,6 +420,25 @@ class Batch:
         st = stream.cuda_stream if stream is not None else None
         _check(lib().gato_serve_step(self._h, R, _dptr(slots), _dptr(xs), _dptr(goal), int(n_iters), int(shift),
                                      _dptr(Xout), _dptr(Uout), _dptr(d_stats), C.c_void_p(st) if st else None))
+
+    def plant_step(self, x, tau, h: float = 0.01, substeps: int = 10, slots=None, xn=None, status=None,
+                   stream=None):
+        """gato_plant_step: RK4 plant over h for R instances (x [R, nx_max], tau [R, nu_max]); returns xn."""
+        import torch
+        R = int(x.shape[0])
+        self._chk(x, (R, self.nx_max))
+        self._chk(tau, (R, self.nu_max))
+        if slots is not None:
+            self._chk(slots, (R,), torch.int32)
+        if xn is None:
+            xn = torch.empty_like(x)
+        self._chk(xn, (R, self.nx_max))
+        if status is not None:
+            self._chk(status, (R,), torch.int32)
+        st = stream.cuda_stream if stream is not None else None
+        _check(lib().gato_plant_step(self._h, R, _dptr(slots), _dptr(x), _dptr(tau), float(h), int(substeps),
+                                     _dptr(xn), _dptr(status), C.c_void_p(st) if st else None))
+        return xn
 
     def reset_warm_start(self):
         _check(lib().gato_reset_warm_start(self._h))

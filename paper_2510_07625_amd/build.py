@@ -17,7 +17,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgato.so")
 ARCH = os.environ.get("GATO_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["sqp_mixed_f64.hip", "sqp_mixed_f32.hip", "sqp_n7.hip", "sqp_n6.hip", "sqp_n3.hip", "gato_api.hip",
-           "gato_flops.cpp"]
+           "gato_plant.hip", "gato_flops.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

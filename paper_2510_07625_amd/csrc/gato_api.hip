@@ -51,7 +51,7 @@ bool dof_supported(int n) { return n == 3 || n == 6 || n == 7; }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t offA, offB, offD, offP, total;
+  size_t offA, offB, offD, offT, total;
 };
 
 Layout layout_for(int n, int N) {
@@ -60,8 +60,8 @@ Layout layout_for(int n, int N) {
   l.offA = 0;
   l.offB = align256(l.offA + (size_t)(N - 1) * nx * nx * sizeof(float));
   l.offD = align256(l.offB + (size_t)(N - 1) * nx * nu * sizeof(float));
-  l.offP = align256(l.offD + (size_t)N * nx * nx * sizeof(float));
-  l.total = align256(l.offP + (size_t)N * nx * nx * sizeof(float));
+  l.offT = align256(l.offD + (size_t)N * nx * nx * sizeof(float));
+  l.total = align256(l.offT + (size_t)N * nx * nx * sizeof(double));
   return l;
 }
 
@@ -97,6 +97,8 @@ struct gato_batch {
   size_t xres_bytes = 0, ures_bytes = 0;
   gato_solve_stats *d_stats = nullptr;
   size_t stats_cap = 0;
+  unsigned *d_plant_status = nullptr;  // [M], used when the caller passes none
+  double *d_rho = nullptr;             // [M] per-solve damping
   // Launch groups: solves of one (n, kpt) shape, longest horizon first.
   struct Group {
     int n, kpt, count;
@@ -159,6 +161,7 @@ void gato_default_params(gato_params *p) {
   p->beta = 2.0;
   p->n_alpha = 8;
   p->rho = 0.0;
+  p->rho_adapt = 0;
   p->schur_fp64 = 1;
   p->warm_lambda = 1;
   p->fp64_block_inv = 0;
@@ -179,6 +182,7 @@ static int check_params(const gato_params *p) {
   if (p->warm_lambda != 0 && p->warm_lambda != 1) return fail(GATO_EINVAL, "warm_lambda must be 0 or 1");
   if (p->fp64_block_inv != 0 && p->fp64_block_inv != 1) return fail(GATO_EINVAL, "fp64_block_inv must be 0 or 1");
   if (p->fp64_dot != 0 && p->fp64_dot != 1) return fail(GATO_EINVAL, "fp64_dot must be 0 or 1");
+  if (p->rho_adapt != 0 && p->rho_adapt != 1) return fail(GATO_EINVAL, "rho_adapt must be 0 or 1");
   return GATO_OK;
 }
 
@@ -253,8 +257,8 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     for (int j = 0; j < nx; ++j) {
       d.Wq[j] = (float)q.Q_diag[j];
       d.Wn[j] = (float)q.QN_diag[j];
-      d.Qi[j] = 1.0 / (q.Q_diag[j] + prm.rho);
-      d.Qni[j] = 1.0 / (q.QN_diag[j] + prm.rho);
+      d.Qd[j] = q.Q_diag[j];
+      d.QNd[j] = q.QN_diag[j];
     }
     for (int j = 0; j < n; ++j) {
       d.Wr[j] = (float)q.R_diag[j];
@@ -277,7 +281,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     desc[i].offA = (int64_t)l.offA;
     desc[i].offB = (int64_t)l.offB;
     desc[i].offD = (int64_t)l.offD;
-    desc[i].offP = (int64_t)l.offP;
+    desc[i].offT = (int64_t)l.offT;
     off += l.total;
   }
   b->ws_bytes = off;
@@ -306,6 +310,15 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(resident X)"); }
   e = hipMalloc((void **)&b->d_Ures, b->ures_bytes);
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(resident U)"); }
+  e = hipMalloc((void **)&b->d_plant_status, M * sizeof(unsigned));
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(plant status)"); }
+  e = hipMalloc((void **)&b->d_rho, M * sizeof(double));
+  if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(rho)"); }
+  {
+    const std::vector<double> r0(M, prm.rho);
+    e = hipMemcpy(b->d_rho, r0.data(), M * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemcpy(rho)"); }
+  }
   e = hipMemset(b->d_Xres, 0, b->xres_bytes);
   if (e == hipSuccess) e = hipMemset(b->d_Ures, 0, b->ures_bytes);
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemset(resident X, U)"); }
@@ -330,6 +343,8 @@ void gato_batch_destroy(gato_batch *b) {
   if (b->d_Xres) (void)hipFree(b->d_Xres);
   if (b->d_Ures) (void)hipFree(b->d_Ures);
   if (b->d_stats) (void)hipFree(b->d_stats);
+  if (b->d_plant_status) (void)hipFree(b->d_plant_status);
+  if (b->d_rho) (void)hipFree(b->d_rho);
   delete b;
 }
 
@@ -349,6 +364,7 @@ gato::KArgs base_args(gato_batch *b) {
   gato::KArgs a;
   std::memset(&a, 0, sizeof(a));
   a.desc = b->d_desc;
+  a.M = b->M;
   a.ws = b->d_ws;
   a.lam = b->d_lam;
   a.nx_max = 2 * b->n_max;
@@ -360,6 +376,8 @@ gato::KArgs base_args(gato_batch *b) {
   a.beta = (float)b->p.beta;
   a.n_alpha = b->p.n_alpha;
   a.warm = b->p.warm_lambda;
+  a.rho = b->d_rho;
+  a.rho_adapt = b->p.rho_adapt;
   a.fp64_inv = b->p.fp64_block_inv;
   a.fp64_dot = b->p.fp64_dot;
   return a;
@@ -585,6 +603,49 @@ int gato_reset_warm_start(gato_batch *b) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   hipError_t e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, b->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(lambda)");
+  return GATO_OK;
+}
+
+int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, const float *d_tau, double h,
+                    int substeps, float *d_xn, unsigned *d_status, void *hip_stream) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (n < 1 || n > b->M) return fail(GATO_EINVAL, "n must be in 1..M");
+  if (!d_x || !d_tau || !d_xn) return fail(GATO_EINVAL, "x, tau and xn must not be NULL");
+  if (!pos_finite(h)) return fail(GATO_EINVAL, "h must be positive");
+  if (substeps < 1 || substeps > 100000) return fail(GATO_EINVAL, "substeps must be in 1..100000");
+  gato::PlantArgs a;
+  a.desc = b->d_desc;
+  a.M = b->M;
+  a.n = n;
+  a.slots = d_slots;
+  a.x = d_x;
+  a.tau = d_tau;
+  a.xn = d_xn;
+  a.status = d_status ? d_status : b->d_plant_status;
+  a.nx_max = 2 * b->n_max;
+  a.nu_max = b->n_max;
+  a.h = h;
+  a.substeps = substeps;
+  hipError_t e = gato::launch_plant(a, hip_stream ? (hipStream_t)hip_stream : b->stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return GATO_OK;
+}
+
+int gato_set_rho(gato_batch *b, const double *h_rho) {
+  if (!b || !h_rho) return fail(GATO_EINVAL, "batch and rho must not be NULL");
+  for (int i = 0; i < b->M; ++i)
+    if (!(std::isfinite(h_rho[i]) && h_rho[i] >= 0.0)) return fail(GATO_EINVAL, "rho must be finite and >= 0");
+  hipError_t e = b->stream ? hipStreamSynchronize(b->stream) : hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(b->d_rho, h_rho, b->M * sizeof(double), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(rho)");
+  return GATO_OK;
+}
+
+int gato_get_rho(gato_batch *b, double *h_rho) {
+  if (!b || !h_rho) return fail(GATO_EINVAL, "batch and rho must not be NULL");
+  hipError_t e = b->stream ? hipStreamSynchronize(b->stream) : hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(h_rho, b->d_rho, b->M * sizeof(double), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(rho)");
   return GATO_OK;
 }
 

@@ -22,12 +22,12 @@ struct SolveDesc {
   float Wq[16];       // stage state weights (diagonal of Q)
   float Wn[16];       // terminal weights (diagonal of Q_N)
   float Wr[8];        // control weights (diagonal of R)
-  double Qi[16];      // 1 / (Q + rho)
-  double Qni[16];     // 1 / (Q_N + rho)
+  double Qd[16];      // diagonal of Q (the kernel forms 1 / (Q + rho) per iteration)
+  double QNd[16];     // diagonal of Q_N
   double Ri[8];       // 1 / R
   int64_t ws_off;     // byte offset of this solve's workspace
-  int64_t offA, offB, offD, offP;  // byte offsets inside it: A_k, B_k, inverse diagonal
-                                   // blocks and preconditioner off-diagonal blocks (float)
+  int64_t offA, offB, offD, offT;  // byte offsets inside it: A_k, B_k and the inverse
+                                   // diagonal blocks (float); Schur diagonal rows (double)
 };
 
 enum KernelMode { kModeSqp = 0, kModeLq = 1, kModeKkt = 2 };
@@ -50,9 +50,12 @@ struct KArgs {
   float beta;
   int n_alpha;
   int warm;
+  double *rho;               // [M] per-solve damping on every Q_k (read at start, written back if adapted)
+  int rho_adapt;             // 1: rho /= 3 after an iteration with descent, rho *= 2 otherwise (cap 1e8)
   int fp64_inv;              // all-FP32 variant: FP64 Gauss-Jordan for the diagonal-block inverses
   int fp64_dot;              // all-FP32 variant: FP64 accumulation of the PCG inner products
   int mode;
+  int M;                     // solves in the batch: solve indices from `order` outside 0..M-1 are skipped
   int sid_base;              // solve index of blockIdx.x == 0
   const int *order;          // optional block -> solve map (longest first), or null
   // Stage entry points.
@@ -68,6 +71,21 @@ struct KArgs {
   int by_block;
   int shift;
   float *Xout, *Uout;
+};
+
+// Closed-loop plant step (gato_plant_step).
+struct PlantArgs {
+  const SolveDesc *desc;
+  int M;                     // solves in the batch (slot bound)
+  int n;                     // instances in this call
+  const int *slots;          // [n] slot of each instance, or null (identity)
+  const float *x;            // [n][nx_max]
+  const float *tau;          // [n][nu_max]
+  float *xn;                 // [n][nx_max]
+  unsigned *status;          // [n]
+  int nx_max, nu_max;
+  double h;
+  int substeps;
 };
 
 }  // namespace gato

@@ -13,6 +13,9 @@ namespace gato {
 // compiled.
 hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
 
+// Launches the closed-loop plant step (RK4, one thread per instance).
+hipError_t launch_plant(const PlantArgs &a, hipStream_t s);
+
 // Largest compiled knots-per-group value for n DoF (3 DoF: 64 lane groups
 // of 8, so 2 knots per group reach the maximum horizon).
 inline int kpt_max(int n) { return 2 * n > 8 ? 4 : 2; }

@@ -71,6 +71,10 @@ __host__ __device__ inline void sin_cos(float x, float *s, float *c) {
   *s = sinf(x);
   *c = cosf(x);
 }
+__host__ __device__ inline void sin_cos(double x, double *s, double *c) {
+  *s = sin(x);
+  *c = cos(x);
+}
 template <class S>
 __host__ __device__ inline void sin_cos(dual<S> x, dual<S> *s, dual<S> *c) {
   S sv, cv;
@@ -306,6 +310,8 @@ __host__ __device__ inline void crba(const Chain &ch, const S *cq, const S *sq, 
 // a pivot is not positive.
 __host__ __device__ inline bool positive(float x) { return x > 0.f; }
 __host__ __device__ inline float sqrt_pos(float x) { return sqrtf(fmaxf(x, 1e-30f)); }
+__host__ __device__ inline bool positive(double x) { return x > 0.0; }
+__host__ __device__ inline double sqrt_pos(double x) { return sqrt(fmax(x, 1e-300)); }
 
 template <int ND, class S>
 __host__ __device__ inline bool cholesky(S (*A)[ND]) {

@@ -73,7 +73,12 @@ struct Smem {
   Real sv[KN][G];          // Q_k^-1 times pv
   double piv[Sh::SLOTS][G];  // Gauss-Jordan pivot rows, one per lane group
   double red[2][3][kBlock / 64];  // per-wavefront partial sums
-  double mp[kMaxAlpha + 1][KN];  // per-knot merit terms; row n_alpha: current point
+  double mp0[KN];          // per-knot merit terms at the current point
+  double Qi[G], Qni[G];    // 1 / (Q + rho), 1 / (Q_N + rho) for the current rho
+  union {
+    double mp[kMaxAlpha][KN];  // per-knot merit terms of the step candidates (line search)
+    Real tv[KN][G];            // exchange inside a lane group (PCG preconditioner)
+  };
   double merit[kMaxAlpha + 1];
   float alpha[kMaxAlpha];
   float xs[G], xg[G], c0[G];
@@ -186,10 +191,14 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     if constexpr (kLds) return sm.Dinv[k];
     else return reinterpret_cast<float *>(ws + D.offD) + (size_t)k * NX * NX;
   };
-  auto Pblk = [&](int k) -> float * {
+  auto Pblk = [&](int k) -> float * {   // explicit preconditioner blocks: kpt == 1 only
     if constexpr (kLds) return sm.Poff[k];
-    else return reinterpret_cast<float *>(ws + D.offP) + (size_t)k * NX * NX;
+    else return nullptr;
   };
+  // Rows of the Schur diagonal blocks, kept in the workspace (read back through
+  // L2) when four knots per lane group would not fit them in registers.
+  constexpr bool kThGlobal = KPT >= 4;
+  auto Tblk = [&](int k) -> Real * { return reinterpret_cast<Real *>(ws + D.offT) + (size_t)k * NX * NX; };
 
   // ---- Stage the iterate and the solve constants in LDS.
   // (With a warm-start shift, knot k starts from the previous knot k + shift,
@@ -228,6 +237,8 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
                  ? (Real)gL[min(k + sh, N - 1) * a.nx_max + lane0] : (Real)0;
   }
   int redbuf = 0;
+  // Damping on every Q_k (Sec. IV-C); uniform across the workgroup.
+  double rho = a.rho[sid];
   __syncthreads();
 
   for (int it = 0; it < a.iters; ++it) {
@@ -236,6 +247,11 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // where they would stay live across every phase and spill.
     int lane = lane0, slot = slot0;
     asm volatile("" : "+v"(lane), "+v"(slot));
+    // Q^-1 and Q_N^-1 for this iteration's rho (first read after phase 1's barrier).
+    if (tid < G) {
+      sm.Qi[tid] = tid < NX ? 1.0 / (D.Qd[tid] + rho) : 0.0;
+      sm.Qni[tid] = tid < NX ? 1.0 / (D.QNd[tid] + rho) : 0.0;
+    }
     int &bad_flag = sm.bad[it & 1];
     unsigned long long *clk = (a.clk && tid == 0) ? a.clk + ((size_t)sid * a.iters + it) * 8 : nullptr;
     unsigned long long cyc0 = 0;
@@ -277,7 +293,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           }
 #pragma unroll
           for (int i = 0; i < NU; ++i) cost += 0.5f * D.Wr[i] * u[i] * u[i];
-          sm.mp[n_alpha][k] = (double)cost + (double)a.mu * (double)viol;
+          sm.mp0[k] = (double)cost + (double)a.mu * (double)viol;
           if (!ok || !isfinite(viol) || !isfinite(cost)) bad_flag = 1;
         }
         wave_sync();
@@ -330,7 +346,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           cost += 0.5f * D.Wn[i] * d * d;
           viol += fabsf(sm.xs[i] - sm.X[0][i]);
         }
-        sm.mp[n_alpha][N - 1] = (double)cost + (double)a.mu * (double)viol;
+        sm.mp0[N - 1] = (double)cost + (double)a.mu * (double)viol;
       }
       if (a.mode == kModeLq) {
         __syncthreads();
@@ -380,7 +396,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     if (clk) clk[1] = wall_clock64();
 
     // ================= 2. Schur complement rows and diagonal-block inverses.
-    Real th[KPT][NX];     // row of the diagonal block theta_{k-1} (Q_0^-1 for k = 0)
+    Real th[kThGlobal ? 1 : KPT][NX];   // row of the diagonal block theta_{k-1} (Q_0^-1 for k = 0)
     // A entries are exact in FP32 and are kept so (converted to Real at use),
     // which halves their register footprint.
     float Am[KPT][NX];    // row `lane` of A_{k-1}: S~_{k,k-1} = -A_{k-1} Q_{k-1}^-1
@@ -392,9 +408,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     for (int p = 0; p < KPT; ++p) {
       const int k = slot + p * SLOTS;
       const bool valid = k < N && lane < NX;
+      Real thr[NX];
 #pragma unroll
       for (int m = 0; m < NX; ++m) {
-        th[p][m] = 0;
+        thr[m] = 0;
         Am[p][m] = 0.f;
         Ac[p][m] = 0.f;
         Pd[p][m] = 0;
@@ -402,12 +419,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       gam[p] = 0;
       qown[p] = 0;
       if (valid) {
-        const double *Qik = (k < N - 1) ? D.Qi : D.Qni;
+        const double *Qik = (k < N - 1) ? sm.Qi : sm.Qni;
         qown[p] = (Real)Qik[lane];
         if (k == 0) {
 #pragma unroll
-          for (int m = 0; m < NX; ++m) th[p][m] = (m == lane) ? (Real)D.Qi[lane] : (Real)0;
-          gam[p] = (Real)sm.c0[lane] + (Real)D.Qi[lane] * (Real)sm.qg[0][lane];
+          for (int m = 0; m < NX; ++m) thr[m] = (m == lane) ? (Real)sm.Qi[lane] : (Real)0;
+          gam[p] = (Real)sm.c0[lane] + (Real)sm.Qi[lane] * (Real)sm.qg[0][lane];
         } else {
           const int km = k - 1;
           const float *A = Ablk(km);
@@ -416,7 +433,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
           for (int m = 0; m < NX; ++m) {
             Am[p][m] = A[lane * NX + m];
-            ArQ[m] = (Real)Am[p][m] * (Real)D.Qi[m];
+            ArQ[m] = (Real)Am[p][m] * (Real)sm.Qi[m];
           }
 #pragma unroll
           for (int m = 0; m < NU; ++m) BrR[m] = (Real)B[lane * NU + m] * (Real)D.Ri[m];
@@ -427,7 +444,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             for (int m = 0; m < NX; ++m) t += ArQ[m] * (Real)A[c * NX + m];
 #pragma unroll
             for (int m = 0; m < NU; ++m) t += BrR[m] * (Real)B[c * NU + m];
-            th[p][c] = t;
+            thr[c] = t;
           }
           Real z = (Real)sm.e[km][lane] + (Real)Qik[lane] * (Real)sm.qg[k][lane];
 #pragma unroll
@@ -446,7 +463,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       // (the block is SPD, so no pivoting is needed).
       if (k < N) {
         if (k == 0) {
-          const Real d0 = lane < NX ? (Real)1 / (Real)D.Qi[lane] : (Real)0;
+          const Real d0 = lane < NX ? (Real)1 / (Real)sm.Qi[lane] : (Real)0;
 #pragma unroll
           for (int m = 0; m < NX; ++m) Pd[p][m] = (m == lane) ? d0 : (Real)0;
         } else {
@@ -456,7 +473,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             using T = decltype(tag);
             T row[NX];
 #pragma unroll
-            for (int c = 0; c < NX; ++c) row[c] = (T)th[p][c];
+            for (int c = 0; c < NX; ++c) row[c] = (T)thr[c];
 #pragma unroll
             for (int pv = 0; pv < NX; ++pv) {
               if (lane == pv) {
@@ -490,6 +507,16 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           for (int c = 0; c < NX; ++c) Dk[c] = (float)Pd[p][c];
         }
       }
+      if constexpr (kThGlobal) {
+        if (valid) {
+          Real *Tk = Tblk(k) + lane * NX;
+#pragma unroll
+          for (int c = 0; c < NX; ++c) Tk[c] = thr[c];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NX; ++c) th[p][c] = thr[c];
+      }
     }
     __syncthreads();
     if (clk) clk[2] = wall_clock64();
@@ -500,7 +527,18 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // keep it, and publish it so that knot k-1 can read its column.
     // Preconditioner blocks are stored in FP32 and applied in Real arithmetic:
     // a fixed linear operator, as the pipelined recurrences require.
-    float Pm[KPT][NX], Pp[KPT][NX], Pdf[KPT][NX];
+    // With kFactP (several knots per lane group, where registers are short)
+    // the off-diagonal blocks are not formed: P w = D^-1 (w - O D^-1 w), with O
+    // the off-diagonal blocks of S~ that the S~ product already holds.
+    constexpr bool kFactP = KPT > 1;
+    constexpr int KP = kFactP ? 1 : KPT;
+    float Pm[KP][NX], Pp[KP][NX], Pdf[KPT][NX];
+#pragma unroll
+    for (int p = 0; p < KPT; ++p) {
+#pragma unroll
+      for (int m = 0; m < NX; ++m) Pdf[p][m] = (float)Pd[p][m];
+    }
+    if constexpr (!kFactP) {
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {
       const int k = slot + p * SLOTS;
@@ -509,7 +547,6 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       for (int m = 0; m < NX; ++m) {
         Pm[p][m] = 0.f;
         Pp[p][m] = 0.f;
-        Pdf[p][m] = (float)Pd[p][m];
       }
       if (valid && k >= 1) {
         const float *A = Ablk(k - 1);
@@ -520,7 +557,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           float s = 0.f;
 #pragma unroll
           for (int m = 0; m < NX; ++m) s += (float)Pd[p][m] * A[m * NX + c];
-          t[c] = s * (float)D.Qi[c];   // = -(D_k^-1 phi_{k-1})[lane][c]
+          t[c] = s * (float)sm.Qi[c];   // = -(D_k^-1 phi_{k-1})[lane][c]
         }
         float *Po = Pblk(k - 1) + lane * NX;
 #pragma unroll
@@ -543,6 +580,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         for (int m = 0; m < NX; ++m) Pp[p][m] = Po[m * NX + lane];   // P_{k,k+1} = P_{k+1,k}^T
       }
     }
+    }  // !kFactP
 
     if (clk) clk[3] = wall_clock64();
     // ================= 4. PCG on S~ lambda = gamma~, pipelined arrangement.
@@ -578,7 +616,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       const int k = slot + p * SLOTS;
       Real acc = 0;
 #pragma unroll
-      for (int m = 0; m < NX; ++m) acc += th[p][m] * sm.pv[k][m];
+      for (int m = 0; m < NX; ++m) {
+        if constexpr (kThGlobal) acc += Tblk(k)[lane * NX + m] * sm.pv[k][m];
+        else acc += th[p][m] * sm.pv[k][m];
+      }
       if (k > 0) {
 #pragma unroll
         for (int m = 0; m < NX; ++m) acc -= (Real)Am[p][m] * sm.sv[k - 1][m];
@@ -594,17 +635,60 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     auto apply_P = [&](int p, Real (*buf)[G]) -> Real {
       const int k = slot + p * SLOTS;
       Real acc = 0;
+      if constexpr (!kFactP) {
 #pragma unroll
-      for (int m = 0; m < NX; ++m) acc += (Real)Pdf[p][m] * buf[k][m];
-      if (k > 0) {
+        for (int m = 0; m < NX; ++m) acc += (Real)Pdf[p][m] * buf[k][m];
+        if (k > 0) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) acc += (Real)Pm[p][m] * buf[k - 1][m];
-      }
-      if (k < N - 1) {
+          for (int m = 0; m < NX; ++m) acc += (Real)Pm[p][m] * buf[k - 1][m];
+        }
+        if (k < N - 1) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) acc += (Real)Pp[p][m] * buf[k + 1][m];
+          for (int m = 0; m < NX; ++m) acc += (Real)Pp[p][m] * buf[k + 1][m];
+        }
       }
       return acc;
+    };
+    // Factored preconditioner, two halves around the workgroup barrier that
+    // publishes the operand (the explicit form publishes it with share_P):
+    //   prepare: z_k = D_k^-1 v_k (own knot, exchanged inside the lane group),
+    //            published with Q_k^-1 z_k in rv / gv;
+    //   finish:  t_k = v_k - (O z)_k, then (P v)_k = D_k^-1 t_k.
+    auto group_dinv = [&](int p, Real x) -> Real {   // row `lane` of D_k^-1 times the group's x
+      const int k = slot + p * SLOTS;
+      sm.tv[k][lane] = (lane < NX) ? x : (Real)0;
+      wave_sync();
+      Real acc = 0;
+#pragma unroll
+      for (int m = 0; m < NX; ++m) acc += (Real)Pdf[p][m] * sm.tv[k][m];
+      wave_sync();
+      return acc;
+    };
+    auto prepare_P = [&](const Real *vals) {
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) {
+        const int k = slot + p * SLOTS;
+        if (k < N) {
+          const Real z = group_dinv(p, vals[p]);
+          sm.rv[k][lane] = (lane < NX) ? z : (Real)0;
+          sm.gv[k][lane] = (lane < NX) ? qown[p] * z : (Real)0;
+        }
+      }
+    };
+    auto finish_P = [&](int p, Real v) -> Real {
+      const int k = slot + p * SLOTS;
+      Real oz = 0;   // (O z)_k at row `lane`
+      if (k > 0) {
+#pragma unroll
+        for (int m = 0; m < NX; ++m) oz -= (Real)Am[p][m] * sm.gv[k - 1][m];
+      }
+      if (k < N - 1) {
+        Real t = 0;
+#pragma unroll
+        for (int m = 0; m < NX; ++m) t += (Real)Ac[p][m] * sm.rv[k + 1][m];
+        oz -= qown[p] * t;
+      }
+      return group_dinv(p, v - oz);
     };
     auto row_valid = [&](int p) { return (slot + p * SLOTS) < N && lane < NX; };
 
@@ -614,15 +698,30 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     __syncthreads();
 #pragma unroll
     for (int p = 0; p < KPT; ++p) r[p] = row_valid(p) ? gam[p] - apply_S(p) : (Real)0;
-    share_P(r, sm.rv);
-    share_P(gam, sm.gv);
-    __syncthreads();
+    Real Pgam[KPT];   // P gamma~, for the reference norm
+    if constexpr (kFactP) {
+      prepare_P(r);
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) u[p] = row_valid(p) ? finish_P(p, r[p]) : (Real)0;
+      __syncthreads();
+      prepare_P(gam);
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) Pgam[p] = row_valid(p) ? finish_P(p, gam[p]) : (Real)0;
+    } else {
+      share_P(r, sm.rv);
+      share_P(gam, sm.gv);
+      __syncthreads();
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) {
+        u[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
+        Pgam[p] = row_valid(p) ? apply_P(p, sm.gv) : (Real)0;
+      }
+    }
     Real eta_ref = 0;
 #pragma unroll
-    for (int p = 0; p < KPT; ++p) {
-      u[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
-      eta_ref += row_valid(p) ? gam[p] * apply_P(p, sm.gv) : (Real)0;
-    }
+    for (int p = 0; p < KPT; ++p) eta_ref += gam[p] * Pgam[p];
     const int max_it = a.pcg_max_iter > 0 ? a.pcg_max_iter : N * NX;
     Real gma = 0, stop = 0;
     int its = 0;
@@ -637,7 +736,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
         for (int p = 0; p < KPT; ++p) {
           sums[0] += (Acc)r[p] * (Acc)u[p];
-          sums[2] += row_valid(p) ? (Acc)gam[p] * (Acc)apply_P(p, sm.gv) : (Acc)0;
+          sums[2] += (Acc)gam[p] * (Acc)Pgam[p];
           vp[p] = u[p];
         }
         block_sum<3>(sm.red, redbuf, sums);
@@ -659,12 +758,14 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             lam[p] += alpha * vp[p];
             r[p] -= alpha * w[p];
           }
-          share_P(r, sm.rv);
+          if constexpr (kFactP) prepare_P(r);
+          else share_P(r, sm.rv);
           __syncthreads();
           Acc rz[1] = {0};
 #pragma unroll
           for (int p = 0; p < KPT; ++p) {
-            u[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
+            if constexpr (kFactP) u[p] = row_valid(p) ? finish_P(p, r[p]) : (Real)0;
+            else u[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
             rz[0] += (Acc)r[p] * (Acc)u[p];
           }
           block_sum<1>(sm.red, redbuf, rz);
@@ -698,8 +799,13 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
         for (int p = 0; p < KPT; ++p)
 #pragma unroll
-          for (int m = 0; m < NX; ++m)
-            asm volatile("" : "+v"(Am[p][m]), "+v"(Ac[p][m]), "+v"(Pm[p][m]), "+v"(Pp[p][m]), "+v"(Pdf[p][m]));
+          for (int m = 0; m < NX; ++m) asm volatile("" : "+v"(Am[p][m]), "+v"(Ac[p][m]), "+v"(Pdf[p][m]));
+        if constexpr (!kFactP) {
+#pragma unroll
+          for (int p = 0; p < KPT; ++p)
+#pragma unroll
+            for (int m = 0; m < NX; ++m) asm volatile("" : "+v"(Pm[p][m]), "+v"(Pp[p][m]));
+        }
         // Publish w for m = P w together with the partial inner products.
         Real pr = 0, pwu = 0;
 #pragma unroll
@@ -713,7 +819,8 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           sm.red[redbuf][0][wave] = pr;
           sm.red[redbuf][1][wave] = pwu;
         }
-        share_P(w, sm.rv);
+        if constexpr (kFactP) prepare_P(w);
+        else share_P(w, sm.rv);
         __syncthreads();
         Real g4[4], d4[4];
 #pragma unroll
@@ -732,7 +839,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         redbuf ^= 1;
         if (!(gma > stop) || its >= max_it) break;
 #pragma unroll
-        for (int p = 0; p < KPT; ++p) vm[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
+        for (int p = 0; p < KPT; ++p) {
+          if constexpr (kFactP) vm[p] = row_valid(p) ? finish_P(p, w[p]) : (Real)0;
+          else vm[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
+        }
         share_S(vm);
         const Real beta = (its == 0) ? (Real)0 : gma / gma_prev;
         const Real alpha = (its == 0) ? gma / dlt : gma / (dlt - beta * gma / alpha_prev);
@@ -837,7 +947,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     __syncthreads();
     if (tid <= n_alpha) {
       double sum = 0.0;
-      for (int k = 0; k < N; ++k) sum += sm.mp[tid][k];
+      for (int k = 0; k < N; ++k) sum += (tid == n_alpha) ? sm.mp0[k] : sm.mp[tid][k];
       sm.merit[tid] = sum;
     }
     __syncthreads();
@@ -849,6 +959,8 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     const bool bad = bad_flag != 0 || best < 0;
     if (bad) status |= GATO_ST_NONFINITE;
     else if (!(sm.merit[best] < sm.merit[n_alpha])) status |= GATO_ST_NO_DESCENT;
+    const double rho_used = rho;
+    if (a.rho_adapt) rho = (status & (GATO_ST_NONFINITE | GATO_ST_NO_DESCENT)) ? fmin(2.0 * rho, 1e8) : rho / 3.0;
     const float al = bad ? 0.f : sm.alpha[best];
     if (!bad) {
       for (int t = tid; t < N * G; t += kBlock) {
@@ -864,6 +976,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       st.alpha = al;
       st.pcg_iters = its;
       st.status = status;
+      st.rho = (float)rho_used;
       a.stats[(size_t)rid * a.stats_stride + it] = st;
     }
     __syncthreads();
@@ -873,9 +986,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     }
   }
 
-  // ---- Write back the iterate and the warm-start multipliers.
+  // ---- Write back the iterate, the warm-start multipliers and the adapted damping.
   const int lane = lane0, slot = slot0;
   if (a.mode == kModeSqp) {
+    if (a.rho_adapt && tid == 0) a.rho[sid] = rho;
     const size_t rxo = (size_t)blockIdx.x * a.N_max * a.nx_max;
     const size_t ruo = (size_t)blockIdx.x * (a.N_max - 1) * a.nu_max;
     for (int t = tid; t < N * G; t += kBlock) {
@@ -901,6 +1015,7 @@ template <int ND, int KPT, class Real>
 __global__ __launch_bounds__(kBlock) void sqp_kernel(KArgs a) {
   __shared__ __align__(16) char smem[sizeof(Smem<ND, KPT, Real>)];
   const int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
+  if (sid < 0 || sid >= a.M) return;   // a caller-provided slot out of range: nothing to do
   sqp_solve<ND, KPT, Real>(a, sid, smem);
 }
 
@@ -923,6 +1038,7 @@ template <class Real>
 __global__ __launch_bounds__(kBlock) void sqp_mixed_kernel(KArgs a) {
   __shared__ __align__(16) char smem[mixed_smem_bytes<Real>()];
   const int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
+  if (sid < 0 || sid >= a.M) return;   // a caller-provided slot out of range: nothing to do
   const SolveDesc &D = a.desc[sid];
   switch (D.n * 8 + D.kpt) {
     case 3 * 8 + 1: sqp_solve<3, 1, Real>(a, sid, smem); break;

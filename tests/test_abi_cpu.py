@@ -30,7 +30,7 @@ def test_default_params():
     p = g._Params()
     g.lib().gato_default_params(C.byref(p))
     assert (p.sqp_iters, p.pcg_tol, p.pcg_max_iter, p.mu, p.beta, p.n_alpha, p.rho, p.schur_fp64,
-            p.warm_lambda, p.fp64_block_inv, p.fp64_dot) == (10, 1e-5, 0, 10.0, 2.0, 8, 0.0, 1, 1, 0, 0)
+            p.warm_lambda, p.fp64_block_inv, p.fp64_dot, p.rho_adapt) == (10, 1e-5, 0, 10.0, 2.0, 8, 0.0, 1, 1, 0, 0, 0)
     d = g.Params()
     c = d.c()
     for f, _ in g._Params._fields_:
@@ -101,4 +101,9 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert L.gato_set_mapping(None, 7, 32, 1) == g.GATO_EINVAL
     assert L.gato_autotune(None, None, None, None, None, 1, 1) == g.GATO_EINVAL
     assert L.gato_step_graph(None, None, None, None, None, 1, None) == g.GATO_EINVAL
+    assert L.gato_plant_step(None, 1, None, None, None, 0.01, 10, None, None, None) == g.GATO_EINVAL
+    assert L.gato_set_rho(None, None) == g.GATO_EINVAL and L.gato_get_rho(None, None) == g.GATO_EINVAL
+    rc, msg = _create([good_r], [good_p], g.Params(rho_adapt=3))
+    assert rc == g.GATO_EINVAL and "rho_adapt" in msg
+    assert g.STATS_DTYPE.itemsize == C.sizeof(g.SolveStats) == 24
     del keep
