@@ -360,6 +360,40 @@ def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, ora
     return out
 
 
+def rho_sweep(g, torch, Ms=(1, 8, 32, 128), problems=8, N=64, dt=0.05, iters=100, seed=3):
+    """Batched rho sweep (the paper's Case Study 1 on synthetic 7-DoF chains):
+    every problem (zero-initialised, N knots, h = dt) is solved by a batch of M
+    copies whose initial rho is log-spaced in [1e-8, 1e1] (M = 1: rho = 0.1),
+    rho adapted after each SQP iteration from the line search. Reports, per M,
+    the best merit in the batch after selected iterations, normalised by the
+    initial merit and averaged over the problems, and the batch time."""
+    import workload as w
+    out = []
+    marks = [i for i in (1, 2, 5, 10, 20, 50, 100) if i <= iters]
+    for M in Ms:
+        rho0 = np.array([0.1]) if M == 1 else np.logspace(-8, 1, M)
+        solves, rhos = [], []
+        for p in range(problems):
+            base = w.chain_solve(seed, p, n=7, N=N, dt=dt, zero_init=True)
+            solves += [base] * M
+            rhos += list(rho0)
+        b = g.Batch.from_solves(solves, g.Params(sqp_iters=iters, rho_adapt=1))
+        b.set_rho(np.array(rhos))
+        xs, goal, X, U = g.pack_inputs(solves)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = b.solve(xs, goal, X, U)
+        dt_s = time.perf_counter() - t0
+        b.close()
+        merit = st["merit"].astype(np.float64).reshape(problems, M, iters)
+        m0 = st["merit0"][:, 0].astype(np.float64).reshape(problems, M)[:, 0]
+        best = merit.min(axis=1) / m0[:, None]                  # [problems, iters]
+        out.append(dict(M=M, batch_solves=M * problems, seconds=dt_s,
+                        best_normalised_merit={str(i): float(best[:, i - 1].mean()) for i in marks}))
+        print(f"# rho sweep {out[-1]}", file=sys.stderr, flush=True)
+    return out
+
+
 def heatmap(g, torch, Ms=(1, 8, 32, 64, 128, 256, 512), Ns=(8, 16, 32, 64, 128), n=6, iters=1, reps=20):
     """Time of one batched call of `iters` SQP iterations (a real-time iteration
     for iters = 1) over M seeded n-DoF chains of N knots, for every (M, N):
@@ -417,6 +451,7 @@ def serving(g, torch, rates, duration_s, pool=256, iters=1, slots=3, deadline_s=
         sm.update(rate_req_s=rate, offered=n, nonfinite=int(sum(1 for c in rep.completions if c.status & 2)))
         out.append(sm)
         print(f"# served {rate} req/s: {sm}", file=sys.stderr, flush=True)
+    ex.close()
     b.close()
     return out
 
@@ -451,6 +486,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch report")
     ap.add_argument("--heatmap", action="store_true",
                     help="also time one SQP iteration over M in 1..512 x N in 8..128 (6-DoF chains)")
+    ap.add_argument("--rho-sweep", action="store_true",
+                    help="also run the batched rho sweep with line-search rho adaptation")
     ap.add_argument("--closed-loop-ticks", type=int, default=1000, help="ticks of the closed-loop batch (0 skips)")
     ap.add_argument("--serve-seconds", type=float, default=2.0,
                     help="duration of each served-loop rate (0 skips the served loop)")
@@ -508,6 +545,7 @@ def main():
     prec = [] if args.profile_run or args.no_precision else precision_report(g, torch, M, 5, args.pcg_tol)
     uneven = {} if args.profile_run or args.no_uneven else uneven_report(g, torch)
     hmap = heatmap(g, torch) if args.heatmap else []
+    rsweep = rho_sweep(g, torch) if args.rho_sweep else []
     closed = {} if args.profile_run or args.closed_loop_ticks <= 0 else closed_loop_report(
         g, torch, ticks=args.closed_loop_ticks)
     served = (serving(g, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
@@ -538,6 +576,7 @@ def main():
         "uneven": uneven,
         "closed_loop": closed,
         "heatmap": hmap,
+        "rho_sweep": rsweep,
         "serving": served,
         "roofline": roof,
     }

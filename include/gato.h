@@ -254,6 +254,41 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
 int gato_reset_warm_start(gato_batch *b);
 
 /*
+ * Serving launch context: the host side of one serving launch in native code,
+ * for request loops that must not pay per-launch copies and allocations. A
+ * context owns a HIP stream (default priority), a completion event, pinned
+ * host staging and the device buffers of one launch of up to `capacity`
+ * requests (1..M) running n_iters SQP iterations each.
+ *   gato_serve_ctx_buffers: pointers to the pinned staging: inputs h_slots
+ *     [capacity], h_xs [capacity][nx_max], h_goal [capacity][nu_max] (the
+ *     caller writes requests 0..n_req-1 there), outputs h_x1
+ *     [capacity][nx_max] (knot 1 of each new plan, the plant's next state
+ *     under the plan), h_u0 [capacity][nu_max] (the first control) and
+ *     h_stats [capacity][n_iters]. Any pointer argument may be NULL.
+ *   gato_serve_ctx_submit: enqueues on the context's stream the copy of the
+ *     first n_req inputs, gato_serve_step (with the given shift) and the copy
+ *     of the outputs, then records the event. Returns at once. The outputs
+ *     and the inputs' staging must not be touched until the query says done.
+ *     Slots are checked on the host (GATO_EINVAL outside 0..M-1).
+ *   gato_serve_ctx_query: 1 when the last submit has finished (outputs
+ *     valid), 0 while it runs, negative on a device error.
+ *   gato_serve_ctx_trajectories: copies the full plans of the last submit,
+ *     [n_req][N_max][nx_max] and [n_req][N_max-1][nu_max], to host memory
+ *     (synchronous).
+ * Contexts of one batch may run at once on disjoint slots; the caller
+ * submits a slot again only after the launch that last held it is done.
+ * Errors: GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE.
+ */
+typedef struct gato_serve_ctx gato_serve_ctx;
+int gato_serve_ctx_create(gato_batch *b, int capacity, int n_iters, gato_serve_ctx **out);
+void gato_serve_ctx_destroy(gato_serve_ctx *c);
+int gato_serve_ctx_buffers(gato_serve_ctx *c, int **h_slots, float **h_xs, float **h_goal, const float **h_x1,
+                           const float **h_u0, const gato_solve_stats **h_stats);
+int gato_serve_ctx_submit(gato_serve_ctx *c, int n_req, int shift);
+int gato_serve_ctx_query(gato_serve_ctx *c);
+int gato_serve_ctx_trajectories(gato_serve_ctx *c, float *h_X, float *h_U);
+
+/*
  * Plant of closed-loop studies (the simulations of Sec. IV-E integrate the
  * robot at 1 kHz with RK4). For r < n, advances the state d_x[r] ([n][nx_max],
  * device) of the robot of slot d_slots[r] (device int array, or NULL for slot

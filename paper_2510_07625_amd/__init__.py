@@ -67,7 +67,8 @@ EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "
            "gato_debug_kkt", "gato_reset_warm_start", "gato_rbd_flops", "gato_profile_phases",
            "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_plant_step", "gato_set_dispatch",
            "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_set_rho", "gato_get_rho",
-           "gato_last_error")
+           "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
+           "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_last_error")
 
 _lib = None
 
@@ -104,6 +105,13 @@ def lib() -> C.CDLL:
         L.gato_plant_step.argtypes = [vp, ip, vp, vp, vp, C.c_double, ip, vp, vp, vp]
         L.gato_set_dispatch.argtypes = [vp, ip]
         L.gato_set_rho.argtypes = [vp, C.POINTER(C.c_double)]
+        L.gato_serve_ctx_create.argtypes = [vp, ip, ip, C.POINTER(vp)]
+        L.gato_serve_ctx_destroy.argtypes = [vp]
+        L.gato_serve_ctx_destroy.restype = None
+        L.gato_serve_ctx_buffers.argtypes = [vp] + [C.POINTER(vp)] * 6
+        L.gato_serve_ctx_submit.argtypes = [vp, ip, ip]
+        L.gato_serve_ctx_query.argtypes = [vp]
+        L.gato_serve_ctx_trajectories.argtypes = [vp, vp, vp]
         L.gato_get_rho.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_buckets.argtypes = [vp, C.POINTER(Bucket), ip, C.POINTER(ip)]
         L.gato_set_mapping.argtypes = [vp, ip, ip, ip]
@@ -442,6 +450,63 @@ class Batch:
 
     def reset_warm_start(self):
         _check(lib().gato_reset_warm_start(self._h))
+
+
+class ServeContext:
+    """A gato_serve_ctx: one serving launch's stream, event and pinned staging.
+
+    The staging is exposed as numpy arrays over the pinned memory (slots, xs,
+    goal in; x1, u0, stats out), written and read in place.
+    """
+
+    def __init__(self, batch: "Batch", capacity: int | None = None, n_iters: int = 1):
+        self.batch = batch
+        self.capacity = int(capacity or batch.M)
+        self.n_iters = int(n_iters)
+        h = C.c_void_p()
+        _check(lib().gato_serve_ctx_create(batch._h, self.capacity, self.n_iters, C.byref(h)))
+        self._h = h
+        p = [C.c_void_p() for _ in range(6)]
+        _check(lib().gato_serve_ctx_buffers(self._h, *[C.byref(x) for x in p]))
+        cap, nx, nu = self.capacity, batch.nx_max, batch.nu_max
+
+        def view(ptr, ctype, shape, dtype=None):
+            a = np.ctypeslib.as_array(C.cast(ptr, C.POINTER(ctype)), shape=shape)
+            return a.view(dtype) if dtype is not None else a
+
+        self.slots = view(p[0], C.c_int32, (cap,))
+        self.xs = view(p[1], C.c_float, (cap, nx))
+        self.goal = view(p[2], C.c_float, (cap, nu))
+        self.x1 = view(p[3], C.c_float, (cap, nx))
+        self.u0 = view(p[4], C.c_float, (cap, nu))
+        nb = cap * self.n_iters * STATS_DTYPE.itemsize
+        self.stats = view(p[5], C.c_uint8, (nb,)).view(STATS_DTYPE).reshape(cap, self.n_iters)
+        self.n = 0
+
+    def submit(self, n_req: int, shift: int = 1):
+        self.n = int(n_req)
+        _check(lib().gato_serve_ctx_submit(self._h, self.n, int(shift)))
+
+    def done(self) -> bool:
+        return _check(lib().gato_serve_ctx_query(self._h)) == 1
+
+    def trajectories(self):
+        b = self.batch
+        X = np.zeros((self.n, b.N_max, b.nx_max), np.float32)
+        U = np.zeros((self.n, b.N_max - 1, b.nu_max), np.float32)
+        _check(lib().gato_serve_ctx_trajectories(self._h, X.ctypes.data_as(C.c_void_p), U.ctypes.data_as(C.c_void_p)))
+        return X, U
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().gato_serve_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pack_inputs(solves, device="cuda"):

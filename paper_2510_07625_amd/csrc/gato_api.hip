@@ -599,6 +599,139 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
   return GATO_OK;
 }
 
+}  // extern "C"
+
+// A launch context of the serving loop: its own stream and completion event,
+// pinned host staging that the caller fills and reads in place, and the
+// device buffers of one launch.
+struct gato_serve_ctx {
+  gato_batch *b = nullptr;
+  int cap = 0, n_iters = 0, n_last = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  int *h_slots = nullptr;            // pinned [cap]
+  float *h_xs = nullptr, *h_goal = nullptr;      // pinned [cap][nx_max], [cap][nu_max]
+  float *h_x1 = nullptr, *h_u0 = nullptr;        // pinned [cap][nx_max], [cap][nu_max]
+  gato_solve_stats *h_stats = nullptr;           // pinned [cap][n_iters]
+  int *d_slots = nullptr;
+  float *d_xs = nullptr, *d_goal = nullptr, *d_X = nullptr, *d_U = nullptr;
+  gato_solve_stats *d_stats = nullptr;
+};
+
+extern "C" {
+
+void gato_serve_ctx_destroy(gato_serve_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void *p : {(void *)c->h_slots, (void *)c->h_xs, (void *)c->h_goal, (void *)c->h_x1, (void *)c->h_u0,
+                  (void *)c->h_stats})
+    if (p) (void)hipHostFree(p);
+  for (void *p : {(void *)c->d_slots, (void *)c->d_xs, (void *)c->d_goal, (void *)c->d_X, (void *)c->d_U,
+                  (void *)c->d_stats})
+    if (p) (void)hipFree(p);
+  if (c->done) (void)hipEventDestroy(c->done);
+  if (c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+int gato_serve_ctx_create(gato_batch *b, int capacity, int n_iters, gato_serve_ctx **out) {
+  if (!out) return fail(GATO_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (capacity < 1 || capacity > b->M) return fail(GATO_EINVAL, "capacity must be in 1..M");
+  if (n_iters < 1) return fail(GATO_EINVAL, "n_iters must be >= 1");
+  gato_serve_ctx *c = new gato_serve_ctx();
+  c->b = b;
+  c->cap = capacity;
+  c->n_iters = n_iters;
+  const size_t nx = 2 * (size_t)b->n_max, nu = (size_t)b->n_max, N = (size_t)b->N_max, cap = (size_t)capacity;
+  hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_slots, cap * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_xs, cap * nx * sizeof(float), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_goal, cap * nu * sizeof(float), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_x1, cap * nx * sizeof(float), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&c->h_u0, cap * nu * sizeof(float), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void **)&c->h_stats, cap * n_iters * sizeof(gato_solve_stats), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void **)&c->d_slots, cap * sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void **)&c->d_xs, cap * nx * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void **)&c->d_goal, cap * nu * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void **)&c->d_X, cap * N * nx * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void **)&c->d_U, cap * (N - 1) * nu * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void **)&c->d_stats, cap * n_iters * sizeof(gato_solve_stats));
+  if (e != hipSuccess) {
+    gato_serve_ctx_destroy(c);
+    return hip_fail(e, "serve context set-up");
+  }
+  std::memset(c->h_slots, 0, cap * sizeof(int));
+  std::memset(c->h_xs, 0, cap * nx * sizeof(float));
+  std::memset(c->h_goal, 0, cap * nu * sizeof(float));
+  *out = c;
+  return GATO_OK;
+}
+
+int gato_serve_ctx_buffers(gato_serve_ctx *c, int **h_slots, float **h_xs, float **h_goal, const float **h_x1,
+                           const float **h_u0, const gato_solve_stats **h_stats) {
+  if (!c) return fail(GATO_EINVAL, "context is NULL");
+  if (h_slots) *h_slots = c->h_slots;
+  if (h_xs) *h_xs = c->h_xs;
+  if (h_goal) *h_goal = c->h_goal;
+  if (h_x1) *h_x1 = c->h_x1;
+  if (h_u0) *h_u0 = c->h_u0;
+  if (h_stats) *h_stats = c->h_stats;
+  return GATO_OK;
+}
+
+int gato_serve_ctx_submit(gato_serve_ctx *c, int n_req, int shift) {
+  if (!c) return fail(GATO_EINVAL, "context is NULL");
+  if (n_req < 1 || n_req > c->cap) return fail(GATO_EINVAL, "n_req must be in 1..capacity");
+  gato_batch *b = c->b;
+  const size_t nx = 2 * (size_t)b->n_max, nu = (size_t)b->n_max, N = (size_t)b->N_max, R = (size_t)n_req;
+  for (int r = 0; r < n_req; ++r)
+    if (c->h_slots[r] < 0 || c->h_slots[r] >= b->M) return fail(GATO_EINVAL, "slot outside 0..M-1");
+  hipStream_t s = c->stream;
+  hipError_t e = hipMemcpyAsync(c->d_slots, c->h_slots, R * sizeof(int), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_xs, c->h_xs, R * nx * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->d_goal, c->h_goal, R * nu * sizeof(float), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(serve inputs)");
+  const int rc = gato_serve_step(b, n_req, c->d_slots, c->d_xs, c->d_goal, c->n_iters, shift, c->d_X, c->d_U,
+                                 c->d_stats, s);
+  if (rc != GATO_OK) return rc;
+  // The plant's next state x_1 and the control u_0 of every request, and its statistics.
+  e = hipMemcpy2DAsync(c->h_x1, nx * sizeof(float), c->d_X + nx, N * nx * sizeof(float), nx * sizeof(float), R,
+                       hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpy2DAsync(c->h_u0, nu * sizeof(float), c->d_U, (N - 1) * nu * sizeof(float), nu * sizeof(float), R,
+                         hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->h_stats, c->d_stats, R * c->n_iters * sizeof(gato_solve_stats), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipEventRecord(c->done, s);
+  if (e != hipSuccess) return hip_fail(e, "serve outputs");
+  c->n_last = n_req;
+  return GATO_OK;
+}
+
+int gato_serve_ctx_query(gato_serve_ctx *c) {
+  if (!c) return fail(GATO_EINVAL, "context is NULL");
+  const hipError_t e = hipEventQuery(c->done);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  return hip_fail(e, "hipEventQuery");
+}
+
+int gato_serve_ctx_trajectories(gato_serve_ctx *c, float *h_X, float *h_U) {
+  if (!c || !h_X || !h_U) return fail(GATO_EINVAL, "context and buffers must not be NULL");
+  gato_batch *b = c->b;
+  const size_t nx = 2 * (size_t)b->n_max, nu = (size_t)b->n_max, N = (size_t)b->N_max, R = (size_t)c->n_last;
+  hipError_t e = hipMemcpyAsync(h_X, c->d_X, R * N * nx * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(h_U, c->d_U, R * (N - 1) * nu * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "serve trajectories");
+  return GATO_OK;
+}
+
 int gato_reset_warm_start(gato_batch *b) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   hipError_t e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, b->stream);

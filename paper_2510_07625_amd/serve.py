@@ -13,8 +13,8 @@ batch at a time). Admission is limited by device memory (bytes per in-flight
 request) and by one request in flight per instance. Latency runs from arrival
 to the moment the result is visible on the host.
 
-The executor does the device work; :class:`GpuExecutor` drives the C ABI
-(``gato_serve_step`` on one HIP stream per launch slot). Any object with the
+The executor does the device work; :class:`GpuExecutor` drives the C ABI's
+serving launch contexts (``gato_serve_ctx_*``, one HIP stream per launch slot). Any object with the
 same methods can stand in for it (the tests use a simulated one).
 """
 from __future__ import annotations
@@ -191,73 +191,47 @@ class Scheduler:
 
 
 class GpuExecutor:
-    """Drives ``gato_serve_step`` for a pool of MPC instances.
+    """Drives the serving launch contexts of the C ABI for a pool of MPC instances.
 
-    One HIP stream (default priority) and one set of pinned staging buffers
-    per launch slot; a launch is H2D of slots/start states/goals, the fused
-    SQP kernel over the requested instances, and D2H of the per-request
-    trajectories and statistics, all on the slot's stream.
+    One ``gato_serve_ctx`` per launch slot: its own HIP stream (default
+    priority), completion event and pinned staging. A launch writes the
+    requests into the pinned inputs and makes one native call that enqueues the
+    input copy, the fused SQP kernel over the requested instances (warm start
+    shifted one knot) and the copy back of each request's next state x1, first
+    control u0 and statistics; completion is an event query.
     """
 
-    def __init__(self, batch, slots: int = 4, n_iters: int = 1, base_goals: np.ndarray | None = None):
-        import torch
-
-        from . import STATS_DTYPE, workspace_bytes
-        self.torch = torch
+    def __init__(self, batch, slots: int = 4, n_iters: int = 1):
+        from . import ServeContext, workspace_bytes
         self.b = batch
         self.slots = slots
         self.capacity = batch.M
         self.n_iters = n_iters
         self.bytes_per_request = workspace_bytes(batch.n_max, batch.N_max, batch.params)
-        M, N, nx, nu = batch.M, batch.N_max, batch.nx_max, batch.nu_max
-        self.nx, self.nu = nx, nu
-        mk = lambda shape, dt=torch.float32: torch.zeros(shape, dtype=dt).pin_memory()
-        dev = lambda shape, dt=torch.float32: torch.zeros(shape, dtype=dt, device="cuda")
-        self.st = []
-        for _ in range(slots):
-            self.st.append(dict(
-                stream=torch.cuda.Stream(), event=torch.cuda.Event(),
-                h_slots=mk((M,), torch.int32), h_xs=mk((M, nx)), h_goal=mk((M, nu)),
-                d_slots=dev((M,), torch.int32), d_xs=dev((M, nx)), d_goal=dev((M, nu)),
-                d_X=dev((M, N, nx)), d_U=dev((M, N - 1, nu)),
-                d_stats=dev((M * n_iters * STATS_DTYPE.itemsize,), torch.uint8),
-                h_X=mk((M, N, nx)), h_U=mk((M, N - 1, nu)),
-                h_stats=mk((M * n_iters * STATS_DTYPE.itemsize,), torch.uint8), n=0))
-        self.stats_dtype = STATS_DTYPE
+        self.ctx = [ServeContext(batch, batch.M, n_iters) for _ in range(slots)]
+        self.nx, self.nu = batch.nx_max, batch.nu_max
 
     def launch(self, slot: int, reqs: list, xs: np.ndarray):
-        torch = self.torch
-        s = self.st[slot]
+        c = self.ctx[slot]
         R = len(reqs)
-        s["n"] = R
-        inst = np.array([r.instance for r in reqs], dtype=np.int32)
-        s["h_slots"][:R] = torch.from_numpy(inst)
-        s["h_xs"][:R, :xs.shape[1]] = torch.from_numpy(xs.astype(np.float32))
-        g = np.stack([r.goal for r in reqs]).astype(np.float32)
-        s["h_goal"][:R, :g.shape[1]] = torch.from_numpy(g)
-        # Every re-solve shifts the instance's previous solution by one knot
-        # (harmless for the constant initial guess).
-        shift = 1
-        with torch.cuda.stream(s["stream"]):
-            s["d_slots"][:R].copy_(s["h_slots"][:R], non_blocking=True)
-            s["d_xs"][:R].copy_(s["h_xs"][:R], non_blocking=True)
-            s["d_goal"][:R].copy_(s["h_goal"][:R], non_blocking=True)
-            self.b.serve_step(s["d_slots"][:R], s["d_xs"][:R], s["d_goal"][:R], n_iters=self.n_iters, shift=shift,
-                              Xout=s["d_X"][:R], Uout=s["d_U"][:R], d_stats=s["d_stats"], stream=s["stream"])
-            s["h_X"][:R].copy_(s["d_X"][:R], non_blocking=True)
-            s["h_U"][:R].copy_(s["d_U"][:R], non_blocking=True)
-            s["h_stats"].copy_(s["d_stats"], non_blocking=True)
-            s["event"].record(s["stream"])
+        c.slots[:R] = [r.instance for r in reqs]
+        c.xs[:R, :xs.shape[1]] = xs
+        for i, r in enumerate(reqs):
+            c.goal[i, :len(r.goal)] = r.goal
+        c.submit(R, shift=1)
         return slot
 
     def poll(self, slot: int) -> bool:
-        return self.st[slot]["event"].query()
+        return self.ctx[slot].done()
 
     def finish(self, slot: int):
-        s = self.st[slot]
-        R = s["n"]
-        X = s["h_X"][:R].numpy()
-        U = s["h_U"][:R].numpy()
-        st = np.frombuffer(s["h_stats"].numpy().tobytes(), dtype=self.stats_dtype)[:R * self.n_iters]
-        status = st["status"].reshape(R, self.n_iters).max(axis=1)
-        return [(status[r], X[r, 1].astype(np.float64), U[r, 0].astype(np.float64)) for r in range(R)]
+        c = self.ctx[slot]
+        R = c.n
+        status = c.stats["status"][:R].max(axis=1)
+        x1 = c.x1[:R].astype(np.float64)
+        u0 = c.u0[:R].astype(np.float64)
+        return [(status[r], x1[r], u0[r]) for r in range(R)]
+
+    def close(self):
+        for c in self.ctx:
+            c.close()

@@ -99,8 +99,43 @@ def test_short_served_run():
         reqs.append(Request(i, inst, t, solves[inst].qgoal + g_.normal(0, 0.05, 7)))
     sch = Scheduler(ex, np.stack([s.xs for s in solves]), deadline_s=1e-3)
     rep = sch.run(reqs)
+    ex.close()
     s = rep.summary()
     print("served:", s)
     assert s["completed"] == 300 and s["rejected"] == 0
     assert all((c.status & g.ST_NONFINITE) == 0 for c in rep.completions)
     b.close()
+
+
+def test_serve_context_equals_the_serve_step():
+    _say("serve context")
+    solves, b1, xs, goal, X, U = _pool(6, seed=6)
+    b2 = g.Batch.from_solves(solves, g.Params())
+    b1.set_trajectories(X, U)
+    b2.set_trajectories(X, U)
+    sl = [4, 1, 3]
+    ctx = g.ServeContext(b1, capacity=4, n_iters=2)
+    ctx.slots[:3] = sl
+    ctx.xs[:3] = xs[sl].cpu().numpy()
+    ctx.goal[:3] = goal[sl].cpu().numpy()
+    ctx.submit(3, shift=1)
+    while not ctx.done():
+        pass
+    Xo = torch.zeros((3,) + tuple(X.shape[1:]), device="cuda")
+    Uo = torch.zeros((3,) + tuple(U.shape[1:]), device="cuda")
+    st = torch.zeros(3 * 2 * g.STATS_DTYPE.itemsize, dtype=torch.uint8, device="cuda")
+    b2.serve_step(torch.tensor(sl, dtype=torch.int32, device="cuda"), xs[sl].contiguous(), goal[sl].contiguous(),
+                  n_iters=2, shift=1, Xout=Xo, Uout=Uo, d_stats=st)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ctx.x1[:3], Xo[:, 1].cpu().numpy())
+    np.testing.assert_array_equal(ctx.u0[:3], Uo[:, 0].cpu().numpy())
+    np.testing.assert_array_equal(ctx.stats[:3]["alpha"], g.Batch.decode_stats(st, 3, 2)["alpha"])
+    Xf, Uf = ctx.trajectories()
+    np.testing.assert_array_equal(Xf, Xo.cpu().numpy())
+    np.testing.assert_array_equal(Uf, Uo.cpu().numpy())
+    ctx.slots[0] = 99                                     # outside 0..M-1: rejected on the host
+    with pytest.raises(g.GatoError):
+        ctx.submit(1)
+    ctx.close()
+    b1.close()
+    b2.close()
