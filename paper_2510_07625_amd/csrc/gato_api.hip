@@ -253,6 +253,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     d.n = n;
     d.N = q.N;
     d.kpt = gato::kpt_for(n, q.N);
+    if (d.kpt == 0) return fail(GATO_EUNSUPPORTED, who + "no compiled mapping covers N = " + std::to_string(q.N));
     d.dt = (float)q.dt;
     for (int j = 0; j < nx; ++j) {
       d.Wq[j] = (float)q.Q_diag[j];

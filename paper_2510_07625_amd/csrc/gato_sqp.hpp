@@ -43,12 +43,13 @@ struct Shape {
   static constexpr int NL = ND * (ND + 1) / 2;      // packed Cholesky factor
 };
 
-// QP blocks live in LDS when one knot per lane group suffices (KPT == 1) and
-// in the solve's global workspace otherwise.
+// QP blocks live in LDS when the workgroup holds at most 32 knots, or one knot
+// per lane group, and in the solve's global workspace otherwise.
 template <int ND, int KPT>
 struct BlockStore {
-  static constexpr bool kLds = (KPT == 1);
-  static constexpr int LB = kLds ? Shape<ND>::SLOTS : 1;
+  static constexpr int KN = KPT * Shape<ND>::SLOTS;
+  static constexpr bool kLds = (KPT == 1) || (KN <= 32);
+  static constexpr int LB = kLds ? KN : 1;
 };
 
 template <int ND, int KPT, class Real>
@@ -135,6 +136,13 @@ __device__ __forceinline__ R wave_sum(R v) {
 
 // Sum over the workgroup of NV values: butterfly inside each wavefront, then a
 // fixed-order sum of the per-wavefront partials.
+// Pairwise sum of W values in a fixed order: ((v0 + v1) + (v2 + v3)) + ...
+template <int W>
+__device__ __forceinline__ double pair_tree(const double *v) {
+  if constexpr (W == 1) return v[0];
+  else return pair_tree<W / 2>(v) + pair_tree<W / 2>(v + W / 2);
+}
+
 // The partials travel through LDS as double (exact for float values).
 template <int NV, class V>
 __device__ __forceinline__ void block_sum(double (*red)[3][kBlock / 64], int &buf, V *v) {
@@ -822,20 +830,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         if constexpr (kFactP) prepare_P(w);
         else share_P(w, sm.rv);
         __syncthreads();
-        Real g4[4], d4[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {   // pairwise tree over the eight partials
-          g4[q] = sm.red[redbuf][0][2 * q] + sm.red[redbuf][0][2 * q + 1];
-          d4[q] = sm.red[redbuf][1][2 * q] + sm.red[redbuf][1][2 * q + 1];
-        }
-        gma = (g4[0] + g4[1]) + (g4[2] + g4[3]);
-        const Real dlt = (d4[0] + d4[1]) + (d4[2] + d4[3]);
-        if (its == 0) {
-          Real e4[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) e4[q] = sm.red[redbuf][2][2 * q] + sm.red[redbuf][2][2 * q + 1];
-          stop = (Real)a.pcg_tol * (Real)a.pcg_tol * ((e4[0] + e4[1]) + (e4[2] + e4[3]));
-        }
+        // Pairwise tree over the per-wavefront partials (fixed order).
+        gma = pair_tree<kBlock / 64>(sm.red[redbuf][0]);
+        const Real dlt = pair_tree<kBlock / 64>(sm.red[redbuf][1]);
+        if (its == 0) stop = (Real)a.pcg_tol * (Real)a.pcg_tol * pair_tree<kBlock / 64>(sm.red[redbuf][2]);
         redbuf ^= 1;
         if (!(gma > stop) || its >= max_it) break;
 #pragma unroll
