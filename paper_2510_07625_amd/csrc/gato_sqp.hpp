@@ -134,6 +134,24 @@ __device__ __forceinline__ R wave_sum(R v) {
   return lane_val(v, 0) + lane_val(v, 32);
 }
 
+// Two wavefront sums interleaved step by step (each step of one hides the
+// latency of the other's).
+template <class R>
+__device__ __forceinline__ void wave_sum2(R &a, R &b) {
+  a += dpp<0xB1>(a);
+  b += dpp<0xB1>(b);
+  a += dpp<0x4E>(a);
+  b += dpp<0x4E>(b);
+  a += dpp<0x141>(a);
+  b += dpp<0x141>(b);
+  a += dpp<0x140>(a);
+  b += dpp<0x140>(b);
+  a += swz16(a);
+  b += swz16(b);
+  a = lane_val(a, 0) + lane_val(a, 32);
+  b = lane_val(b, 0) + lane_val(b, 32);
+}
+
 // Sum over the workgroup of NV values: butterfly inside each wavefront, then a
 // fixed-order sum of the per-wavefront partials.
 // Pairwise sum of W values in a fixed order: ((v0 + v1) + (v2 + v3)) + ...
@@ -146,7 +164,7 @@ __device__ __forceinline__ double pair_tree(const double *v) {
 // The partials travel through LDS as double (exact for float values).
 template <int NV, class V>
 __device__ __forceinline__ void block_sum(double (*red)[3][kBlock / 64], int &buf, V *v) {
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
   for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
   if ((threadIdx.x & 63) == 0) {
@@ -620,40 +638,80 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         if (k < N) buf[k][lane] = (lane < NX) ? vals[p] : (Real)0;
       }
     };
+    // With one knot per lane group, block-row products accumulate in two
+    // interleaved partial sums per block (even and odd columns), so that the FMA
+    // chains are short and independent; with more knots the extra accumulators
+    // would cost registers (spills), so the odd columns fold into the even sums.
+    constexpr bool kSplit = (KPT == 1);
     auto apply_S = [&](int p) -> Real {
       const int k = slot + p * SLOTS;
-      Real acc = 0;
+      if constexpr (kSplit) {
+        Real d0 = 0, d1 = 0, l0 = 0, l1 = 0, u0 = 0, u1 = 0;
 #pragma unroll
-      for (int m = 0; m < NX; ++m) {
-        if constexpr (kThGlobal) acc += Tblk(k)[lane * NX + m] * sm.pv[k][m];
-        else acc += th[p][m] * sm.pv[k][m];
-      }
-      if (k > 0) {
+        for (int m = 0; m < NX; m += 2) {
+          d0 += th[p][m] * sm.pv[k][m];
+          d1 += th[p][m + 1] * sm.pv[k][m + 1];
+        }
+        if (k > 0) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) acc -= (Real)Am[p][m] * sm.sv[k - 1][m];
-      }
-      if (k < N - 1) {
-        Real t = 0;
+          for (int m = 0; m < NX; m += 2) {
+            l0 += (Real)Am[p][m] * sm.sv[k - 1][m];
+            l1 += (Real)Am[p][m + 1] * sm.sv[k - 1][m + 1];
+          }
+        }
+        if (k < N - 1) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) t += (Real)Ac[p][m] * sm.pv[k + 1][m];
-        acc -= qown[p] * t;
+          for (int m = 0; m < NX; m += 2) {
+            u0 += (Real)Ac[p][m] * sm.pv[k + 1][m];
+            u1 += (Real)Ac[p][m + 1] * sm.pv[k + 1][m + 1];
+          }
+        }
+        return ((d0 + d1) - (l0 + l1)) - qown[p] * (u0 + u1);
+      } else {
+        Real acc = 0;
+#pragma unroll
+        for (int m = 0; m < NX; ++m) {
+          if constexpr (kThGlobal) acc += Tblk(k)[lane * NX + m] * sm.pv[k][m];
+          else acc += th[p][m] * sm.pv[k][m];
+        }
+        if (k > 0) {
+#pragma unroll
+          for (int m = 0; m < NX; ++m) acc -= (Real)Am[p][m] * sm.sv[k - 1][m];
+        }
+        if (k < N - 1) {
+          Real t = 0;
+#pragma unroll
+          for (int m = 0; m < NX; ++m) t += (Real)Ac[p][m] * sm.pv[k + 1][m];
+          acc -= qown[p] * t;
+        }
+        return acc;
       }
-      return acc;
     };
     auto apply_P = [&](int p, Real (*buf)[G]) -> Real {
       const int k = slot + p * SLOTS;
       Real acc = 0;
       if constexpr (!kFactP) {
+        Real d0 = 0, d1 = 0, l0 = 0, l1 = 0, u0 = 0, u1 = 0;
 #pragma unroll
-        for (int m = 0; m < NX; ++m) acc += (Real)Pdf[p][m] * buf[k][m];
+        for (int m = 0; m < NX; m += 2) {
+          d0 += (Real)Pdf[p][m] * buf[k][m];
+          d1 += (Real)Pdf[p][m + 1] * buf[k][m + 1];
+        }
         if (k > 0) {
 #pragma unroll
-          for (int m = 0; m < NX; ++m) acc += (Real)Pm[p][m] * buf[k - 1][m];
+          for (int m = 0; m < NX; m += 2) {
+            l0 += (Real)Pm[p][m] * buf[k - 1][m];
+            l1 += (Real)Pm[p][m + 1] * buf[k - 1][m + 1];
+          }
         }
         if (k < N - 1) {
 #pragma unroll
-          for (int m = 0; m < NX; ++m) acc += (Real)Pp[p][m] * buf[k + 1][m];
+          for (int m = 0; m < NX; m += 2) {
+            u0 += (Real)Pp[p][m] * buf[k + 1][m];
+            u1 += (Real)Pp[p][m + 1] * buf[k + 1][m + 1];
+          }
         }
+        acc = (d0 + d1) + ((l0 + l1) + (u0 + u1));
       }
       return acc;
     };
@@ -798,9 +856,13 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         vz[p] = vq[p] = vs[p] = vp[p] = 0;
       }
       eta_ref = wave_sum(eta_ref);
-      const int wave = tid >> 6;
+      const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: kept in a scalar register
       if ((tid & 63) == 0) sm.red[redbuf][2][wave] = eta_ref;
-      Real gma_prev = 1, alpha_prev = 1;
+      // rg = 1 / gamma_prev and c = 1 / (gamma_prev alpha_prev), formed in the
+      // previous iteration off the critical path, turn
+      //   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev)
+      // into beta = gamma rg, alpha = gamma / (delta - gamma^2 c): one division.
+      Real rg = 0, cga = 0;
       for (;;) {
         // Keep the FP32 matrix rows as FP32 across iterations (stops the
         // compiler from hoisting their conversions and doubling their registers).
@@ -821,8 +883,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           pr += r[p] * u[p];
           pwu += w[p] * u[p];
         }
-        pr = wave_sum(pr);
-        pwu = wave_sum(pwu);
+        if constexpr (kSplit) {
+          wave_sum2(pr, pwu);
+        } else {
+          pr = wave_sum(pr);
+          pwu = wave_sum(pwu);
+        }
         if ((tid & 63) == 0) {
           sm.red[redbuf][0][wave] = pr;
           sm.red[redbuf][1][wave] = pwu;
@@ -842,8 +908,11 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           else vm[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
         }
         share_S(vm);
-        const Real beta = (its == 0) ? (Real)0 : gma / gma_prev;
-        const Real alpha = (its == 0) ? gma / dlt : gma / (dlt - beta * gma / alpha_prev);
+        // (kpt > 1: the plain quotients, whose operands are short-lived; rg and
+        // cga then hold gamma_prev and alpha_prev.)
+        const Real beta = kSplit ? gma * rg : ((its == 0) ? (Real)0 : gma / rg);
+        const Real alpha = kSplit ? gma / (dlt - gma * gma * cga)
+                                  : ((its == 0) ? gma / dlt : gma / (dlt - beta * gma / cga));
         __syncthreads();
 #pragma unroll
         for (int p = 0; p < KPT; ++p) {
@@ -857,8 +926,13 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           u[p] -= alpha * vq[p];
           w[p] -= alpha * vz[p];
         }
-        gma_prev = gma;
-        alpha_prev = alpha;
+        if constexpr (kSplit) {
+          cga = (Real)1 / (gma * alpha);
+          rg = alpha * cga;
+        } else {
+          rg = gma;
+          cga = alpha;
+        }
         ++its;
       }
     }
