@@ -30,6 +30,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gato_internal.hpp"
 
 namespace gato {
@@ -97,14 +99,16 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // ---- Cross-lane sums. Every lane ends with the bit-identical total.
+// The patterns used (quad permutations, row mirrors) read a valid lane for
+// every lane, so the moves need no previous destination value.
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ float swz16(float v) {  // lane ^ 16 inside each half-wave
@@ -558,11 +562,14 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // the off-diagonal blocks of S~ that the S~ product already holds.
     constexpr bool kFactP = KPT > 1;
     constexpr int KP = kFactP ? 1 : KPT;
-    float Pm[KP][NX], Pp[KP][NX], Pdf[KPT][NX];
+    // (Held in FP32 and converted at use: Real-held rows would save the
+    // conversions but spill inside the PCG loop.)
+    using PT = float;
+    PT Pm[KP][NX], Pp[KP][NX], Pdf[KPT][NX];
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {
 #pragma unroll
-      for (int m = 0; m < NX; ++m) Pdf[p][m] = (float)Pd[p][m];
+      for (int m = 0; m < NX; ++m) Pdf[p][m] = (PT)(float)Pd[p][m];
     }
     if constexpr (!kFactP) {
 #pragma unroll
