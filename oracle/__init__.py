@@ -34,7 +34,7 @@ def build() -> str:
 
 class _Robot(C.Structure):
     _fields_ = [("model", C.c_int), ("n", C.c_int), ("link", C.POINTER(C.c_double)),
-                ("gravity", C.c_double), ("spring_k", C.c_double)]
+                ("gravity", C.c_double), ("spring_k", C.c_double), ("fext", C.c_double * 3)]
 
 
 class _Problem(C.Structure):
@@ -117,7 +117,9 @@ class _Ctx:
 
     def __init__(self, s):
         self.link = _f64(s.links).reshape(-1) if s.links is not None else np.zeros(5)
-        self.robot = _Robot(int(s.model), int(s.n), _ptr(self.link), float(s.gravity), float(s.spring_k))
+        fe = tuple(float(v) for v in getattr(s, "fext", (0.0, 0.0, 0.0)))
+        self.robot = _Robot(int(s.model), int(s.n), _ptr(self.link), float(s.gravity), float(s.spring_k),
+                            (C.c_double * 3)(*fe))
         N = getattr(s, "N", 2)
         self.Qd, self.Rd, self.QNd = (_f64(getattr(s, k, np.ones(1))) for k in ("Qd", "Rd", "QNd"))
         self.prob = _Problem(int(N), float(getattr(s, "dt", 0.01)), _ptr(self.Qd), _ptr(self.Rd), _ptr(self.QNd))

@@ -59,6 +59,7 @@ typedef struct {
   const double *link;  /* [n][5] length, mass, Ixx, Iyy, Izz */
   double gravity;      /* along -z of the base */
   double spring_k;     /* model 1 only */
+  double fext[3];      /* external force on the tip of the last link (base frame), model 0 */
 } orc_robot;
 
 typedef struct {
@@ -235,7 +236,10 @@ void inverse_dynamics(const orc_robot &rb, const T *q, const T *qd, const T *qdd
     Nm[i] = Iw * wd[i] + cross(w[i], Iw * w[i]);
   }
   // Backward pass: force and moment (about the joint) that link i-1 exerts on link i.
-  V3<T> f_next = v3<T>(zero, zero, zero), n_next = v3<T>(zero, zero, zero);
+  // An external force f on the tip p[n] of the last link enters as the force
+  // -f that a (virtual) next link exerts at p[n]; the joints then supply
+  // tau = M qdd + b - J(q)^T f.
+  V3<T> f_next = v3<T>(T(-rb.fext[0]), T(-rb.fext[1]), T(-rb.fext[2])), n_next = v3<T>(zero, zero, zero);
   for (int i = n - 1; i >= 0; --i) {
     const V3<T> f = F[i] + f_next;
     const V3<T> mom = Nm[i] + n_next + cross(c[i] - p[i], F[i]) + cross(p[i + 1] - p[i], f_next);

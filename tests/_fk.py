@@ -66,3 +66,16 @@ def lagrangian_id(links, q, qd, qdd, g=9.81, h=1e-5) -> np.ndarray:
     Mdot = sum(dM[j] * qd[j] for j in range(n))
     quad = np.array([qd @ dM[i] @ qd for i in range(n)])
     return M @ qdd + Mdot @ qd - 0.5 * quad + dV
+
+
+def tip(links, q) -> np.ndarray:
+    """Position of the tip of the last link (its far end along its local +z)."""
+    R, p, _, _ = frames(links, q)
+    return p[-1] + R[-1] @ np.array([0, 0, links[len(q) - 1][0]])
+
+
+def tip_jacobian(links, q) -> np.ndarray:
+    """Positional Jacobian of the tip: column j = z_j x (p_tip - p_j)."""
+    _, p, z, _ = frames(links, q)
+    pt = tip(links, q)
+    return np.stack([np.cross(z[j], pt - p[j]) for j in range(len(q))], axis=1)

@@ -48,6 +48,7 @@ class Solve:
     model: int = 0              # 0 revolute chain, 1 linear double-integrator chain
     gravity: float = GRAVITY
     spring_k: float = 0.0
+    fext: tuple = (0.0, 0.0, 0.0)   # external force on the tip of the last link (base frame), N
 
     @property
     def nx(self) -> int:
