@@ -394,6 +394,40 @@ def rho_sweep(g, torch, Ms=(1, 8, 32, 128), problems=8, N=64, dt=0.05, iters=100
     return out
 
 
+def hypothesis_report(g, torch, P=32, Hs=(1, 8, 32), ticks=200, seed=4, sigma=12.0):
+    """Batched hypothesize-and-test over tip forces (the paper's Case Study 2 on
+    synthetic 7-DoF chains, N = 32, 2 SQP iterations per tick): P instances whose
+    plants feel a constant unknown tip force N(0, 20^2) N per axis, each solved
+    with H force hypotheses re-centred every tick on the most consistent one.
+    Reports solves/s, the force-estimate error and the tracking error."""
+    import workload as w
+    from paper_2510_07625_amd import hypotheses
+    rng = np.random.default_rng([seed, 7])
+    f_true = rng.normal(0.0, 20.0, (P, 3))
+    base = [w.chain_solve(seed, p, n=7, N=32) for p in range(P)]
+    qg = np.stack([s.qgoal for s in base])
+    out = []
+    for H in Hs:
+        solves = [s for s in base for _ in range(H)]
+        b = g.Batch.from_solves(solves, g.Params(sqp_iters=2))
+        xs, goal, X, U = g.pack_inputs(solves)
+        b.set_trajectories(X, U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = hypotheses.run(b, P, H, xs[::H].contiguous(), goal[::H].contiguous(), ticks, lambda t: f_true,
+                           sigma=sigma)
+        dt_s = time.perf_counter() - t0
+        b.close()
+        track = np.linalg.norm(r.states[:, :, :7] - qg[None], axis=2).mean(axis=1)
+        ferr = np.linalg.norm(r.estimates - f_true[None], axis=2).mean(axis=1)
+        out.append(dict(H=H, P=P, ticks=ticks, solves_per_s=P * H * ticks / dt_s,
+                        tick_p50_ms=float(np.median(r.tick_ms)), tick_p99_ms=float(np.percentile(r.tick_ms, 99)),
+                        force_error_N=dict(start=float(ferr[0]), end=float(ferr[-20:].mean())),
+                        tracking_error_rad=dict(mean=float(track.mean()), end=float(track[-50:].mean()))))
+        print(f"# hypotheses {out[-1]}", file=sys.stderr, flush=True)
+    return out
+
+
 def heatmap(g, torch, Ms=(1, 8, 32, 64, 128, 256, 512), Ns=(8, 16, 32, 64, 128), n=6, iters=1, reps=20):
     """Time of one batched call of `iters` SQP iterations (a real-time iteration
     for iters = 1) over M seeded n-DoF chains of N knots, for every (M, N):
@@ -486,6 +520,8 @@ def main():
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch report")
     ap.add_argument("--heatmap", action="store_true",
                     help="also time one SQP iteration over M in 1..512 x N in 8..128 (6-DoF chains)")
+    ap.add_argument("--hypotheses", action="store_true",
+                    help="also run the batched hypothesize-and-test over tip forces")
     ap.add_argument("--rho-sweep", action="store_true",
                     help="also run the batched rho sweep with line-search rho adaptation")
     ap.add_argument("--closed-loop-ticks", type=int, default=1000, help="ticks of the closed-loop batch (0 skips)")
@@ -546,6 +582,7 @@ def main():
     uneven = {} if args.profile_run or args.no_uneven else uneven_report(g, torch)
     hmap = heatmap(g, torch) if args.heatmap else []
     rsweep = rho_sweep(g, torch) if args.rho_sweep else []
+    hyps = hypothesis_report(g, torch) if args.hypotheses else []
     closed = {} if args.profile_run or args.closed_loop_ticks <= 0 else closed_loop_report(
         g, torch, ticks=args.closed_loop_ticks)
     served = (serving(g, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
@@ -577,6 +614,7 @@ def main():
         "closed_loop": closed,
         "heatmap": hmap,
         "rho_sweep": rsweep,
+        "hypotheses": hyps,
         "serving": served,
         "roofline": roof,
     }

@@ -294,15 +294,30 @@ int gato_serve_ctx_trajectories(gato_serve_ctx *c, float *h_X, float *h_U);
  * device) of the robot of slot d_slots[r] (device int array, or NULL for slot
  * r) by h seconds: `substeps` classical fourth-order Runge-Kutta steps on the
  * continuous dynamics x' = [qd; M(q)^-1 (tau - b(q, qd))] with tau = d_tau[r]
- * ([n][nu_max], device) held constant. FP64 arithmetic; the result goes to
+ * ([n][nu_max], device) held constant, and an external force on the tip of
+ * the last link: d_fext[r] ([n][3], base frame, device) if d_fext is not
+ * NULL (the plant's true disturbance), else the slot's own force (see
+ * gato_set_external_force). FP64 arithmetic; the result goes to
  * d_xn[r] (may be d_x). d_status[r] (device, may be NULL) is 0, or
  * GATO_ST_NONFINITE for a non-finite result, an indefinite inertia matrix or a
  * slot outside 0..M-1. Launched on hip_stream (NULL: the batch stream).
  * Errors: GATO_EINVAL (n outside 1..M, NULL buffers, h <= 0, substeps outside
  * 1..100000).
  */
-int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, const float *d_tau, double h,
-                    int substeps, float *d_xn, unsigned *d_status, void *hip_stream);
+int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, const float *d_tau,
+                    const float *d_fext, double h, int substeps, float *d_xn, unsigned *d_status,
+                    void *hip_stream);
+
+/*
+ * External force on the tip of the last link of each solve's robot (the
+ * disturbance hypotheses of Sec. IV-D: the solves of a batch may differ only
+ * in the assumed force). h_f [M][3] (host, base frame, N, finite) replaces
+ * every solve's force; the dynamics become M(q) qdd + b(q, qd) = tau + J(q)^T f,
+ * with J the positional Jacobian of the tip, and their derivatives follow.
+ * Serial chains only (a non-zero force on another model is GATO_EINVAL).
+ * Synchronous. Errors: GATO_EINVAL, GATO_EDEVICE.
+ */
+int gato_set_external_force(gato_batch *b, const double *h_f);
 
 /*
  * Per-solve damping rho (Sec. IV-C samples rho across the batch): h_rho[M]

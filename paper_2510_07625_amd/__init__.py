@@ -65,7 +65,8 @@ STATS_DTYPE = np.dtype([("merit0", np.float32), ("merit", np.float32), ("alpha",
 EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "gato_batch_destroy",
            "gato_batch_shape", "gato_solve", "gato_step", "gato_step_plain", "gato_debug_lq",
            "gato_debug_kkt", "gato_reset_warm_start", "gato_rbd_flops", "gato_profile_phases",
-           "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_plant_step", "gato_set_dispatch",
+           "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_plant_step",
+           "gato_set_external_force", "gato_set_dispatch",
            "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_set_rho", "gato_get_rho",
            "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
            "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_last_error")
@@ -102,7 +103,8 @@ def lib() -> C.CDLL:
         L.gato_set_trajectories.argtypes = [vp, vp, vp]
         L.gato_get_trajectories.argtypes = [vp, vp, vp]
         L.gato_serve_step.argtypes = [vp, ip, vp, vp, vp, ip, ip, vp, vp, vp, vp]
-        L.gato_plant_step.argtypes = [vp, ip, vp, vp, vp, C.c_double, ip, vp, vp, vp]
+        L.gato_plant_step.argtypes = [vp, ip, vp, vp, vp, vp, C.c_double, ip, vp, vp, vp]
+        L.gato_set_external_force.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_set_dispatch.argtypes = [vp, ip]
         L.gato_set_rho.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_serve_ctx_create.argtypes = [vp, ip, ip, C.POINTER(vp)]
@@ -265,7 +267,11 @@ class Batch:
         """Builds a batch from objects with the fields of workload.Solve."""
         robots = [Robot(s.n, s.links, s.model, s.gravity, s.spring_k) for s in solves]
         problems = [Problem(s.N, s.dt, s.Qd, s.Rd, s.QNd) for s in solves]
-        return cls(robots, problems, params, stream)
+        b = cls(robots, problems, params, stream)
+        fe = np.array([getattr(s, "fext", (0.0, 0.0, 0.0)) for s in solves], np.float64)
+        if np.any(fe != 0.0):
+            b.set_external_force(fe)
+        return b
 
     def close(self):
         if getattr(self, "_h", None):
@@ -430,12 +436,15 @@ class Batch:
                                      _dptr(Xout), _dptr(Uout), _dptr(d_stats), C.c_void_p(st) if st else None))
 
     def plant_step(self, x, tau, h: float = 0.01, substeps: int = 10, slots=None, xn=None, status=None,
-                   stream=None):
-        """gato_plant_step: RK4 plant over h for R instances (x [R, nx_max], tau [R, nu_max]); returns xn."""
+                   stream=None, fext=None):
+        """gato_plant_step: RK4 plant over h for R instances (x [R, nx_max], tau [R, nu_max],
+        optional true tip force fext [R, 3]); returns xn."""
         import torch
         R = int(x.shape[0])
         self._chk(x, (R, self.nx_max))
         self._chk(tau, (R, self.nu_max))
+        if fext is not None:
+            self._chk(fext, (R, 3))
         if slots is not None:
             self._chk(slots, (R,), torch.int32)
         if xn is None:
@@ -444,9 +453,14 @@ class Batch:
         if status is not None:
             self._chk(status, (R,), torch.int32)
         st = stream.cuda_stream if stream is not None else None
-        _check(lib().gato_plant_step(self._h, R, _dptr(slots), _dptr(x), _dptr(tau), float(h), int(substeps),
-                                     _dptr(xn), _dptr(status), C.c_void_p(st) if st else None))
+        _check(lib().gato_plant_step(self._h, R, _dptr(slots), _dptr(x), _dptr(tau), _dptr(fext), float(h),
+                                     int(substeps), _dptr(xn), _dptr(status), C.c_void_p(st) if st else None))
         return xn
+
+    def set_external_force(self, f):
+        """gato_set_external_force: per-solve tip force [M, 3] (base frame, N)."""
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(f, np.float64), (self.M, 3)))
+        _check(lib().gato_set_external_force(self._h, a.ctypes.data_as(C.POINTER(C.c_double))))
 
     def reset_warm_start(self):
         _check(lib().gato_reset_warm_start(self._h))

@@ -247,6 +247,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
         d.chain.Io[j][1] = (float)(l[3] + l[1] * cz * cz);
         d.chain.Io[j][2] = (float)l[4];
       }
+      d.chain.Lt = (float)r.link[5 * (n - 1)];
     } else if (!std::isfinite(r.spring_k)) {
       return fail(GATO_EINVAL, who + "spring_k must be finite");
     }
@@ -740,8 +741,9 @@ int gato_reset_warm_start(gato_batch *b) {
   return GATO_OK;
 }
 
-int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, const float *d_tau, double h,
-                    int substeps, float *d_xn, unsigned *d_status, void *hip_stream) {
+int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, const float *d_tau,
+                    const float *d_fext, double h, int substeps, float *d_xn, unsigned *d_status,
+                    void *hip_stream) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (n < 1 || n > b->M) return fail(GATO_EINVAL, "n must be in 1..M");
   if (!d_x || !d_tau || !d_xn) return fail(GATO_EINVAL, "x, tau and xn must not be NULL");
@@ -754,6 +756,7 @@ int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, 
   a.slots = d_slots;
   a.x = d_x;
   a.tau = d_tau;
+  a.fext = d_fext;
   a.xn = d_xn;
   a.status = d_status ? d_status : b->d_plant_status;
   a.nx_max = 2 * b->n_max;
@@ -762,6 +765,26 @@ int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, 
   a.substeps = substeps;
   hipError_t e = gato::launch_plant(a, hip_stream ? (hipStream_t)hip_stream : b->stream);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return GATO_OK;
+}
+
+int gato_set_external_force(gato_batch *b, const double *h_f) {
+  if (!b || !h_f) return fail(GATO_EINVAL, "batch and forces must not be NULL");
+  for (int i = 0; i < 3 * b->M; ++i)
+    if (!std::isfinite(h_f[i])) return fail(GATO_EINVAL, "forces must be finite");
+  for (int i = 0; i < b->M; ++i)
+    if (b->desc[i].chain.model != GATO_MODEL_SERIAL_CHAIN &&
+        (h_f[3 * i] != 0.0 || h_f[3 * i + 1] != 0.0 || h_f[3 * i + 2] != 0.0))
+      return fail(GATO_EINVAL, "external forces apply to serial chains only");
+  hipError_t e = b->stream ? hipStreamSynchronize(b->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "synchronize");
+  for (int i = 0; i < b->M; ++i) {
+    gato::Chain &c = b->desc[i].chain;
+    for (int a = 0; a < 3; ++a) c.fe[a] = (float)h_f[3 * i + a];
+    c.has_fe = (c.fe[0] != 0.f || c.fe[1] != 0.f || c.fe[2] != 0.f) ? 1 : 0;
+  }
+  e = hipMemcpy(b->d_desc, b->desc.data(), b->M * sizeof(SolveDesc), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(desc)");
   return GATO_OK;
 }
 

@@ -81,6 +81,7 @@ struct PlantArgs {
   const int *slots;          // [n] slot of each instance, or null (identity)
   const float *x;            // [n][nx_max]
   const float *tau;          // [n][nu_max]
+  const float *fext;         // [n][3] external tip force per instance (base frame), or null: the slot's own
   float *xn;                 // [n][nx_max]
   unsigned *status;          // [n]
   int nx_max, nu_max;

@@ -65,7 +65,11 @@ __global__ __launch_bounds__(64) void plant_kernel(PlantArgs a) {
     a.status[r] = GATO_ST_NONFINITE;
     return;
   }
-  const Chain &ch = a.desc[sid].chain;
+  Chain ch = a.desc[sid].chain;
+  if (a.fext) {
+    for (int c = 0; c < 3; ++c) ch.fe[c] = a.fext[(size_t)r * 3 + c];
+    ch.has_fe = (ch.fe[0] != 0.f || ch.fe[1] != 0.f || ch.fe[2] != 0.f) && ch.model == 0;
+  }
   const float *x = a.x + (size_t)r * a.nx_max;
   const float *tau = a.tau + (size_t)r * a.nu_max;
   float *xn = a.xn + (size_t)r * a.nx_max;

@@ -38,6 +38,9 @@ struct Chain {
   float m[kMaxDof];       // mass
   float cz[kMaxDof];      // centre-of-mass offset along +z
   float Io[kMaxDof][3];   // rotational inertia about the joint (diagonal)
+  float Lt;               // offset of the tip along +z of the last link
+  float fe[3];            // external force on the tip (base frame)
+  int has_fe;             // fe is not zero
 };
 
 // ---------------------------------------------------------------------------
@@ -205,6 +208,29 @@ __host__ __device__ inline void rnea(const Chain &ch, const T *q, const T *cq, c
       for (int a = 0; a < 3; ++a) {
         fn[i - 1][a] = fn[i - 1][a] + n[a];
         ff[i - 1][a] = ff[i - 1][a] + f[a];
+      }
+    }
+  }
+  if (ch.has_fe) {
+    // External force f on the tip. The recursion is linear in the link
+    // wrenches, so its share is a separate backward pass (after the link
+    // wrenches above are dead): rotate f from the base into the last link's
+    // frame, take the wrench the joints must supply against it at the last
+    // joint, (-(r x f), -f) with r = (0, 0, Lt), and carry it to the base.
+    T f[3] = {cst<T>(ch.fe[0]), cst<T>(ch.fe[1]), cst<T>(ch.fe[2])};
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      if (i & 1) rot_E<true>(cq[i], sq[i], f[0], f[1], f[2]);
+      else rot_E<false>(cq[i], sq[i], f[0], f[1], f[2]);
+    }
+    T wn[3] = {ch.Lt * f[1], -(ch.Lt * f[0]), cst<T>(0.f)};
+    T wf[3] = {-f[0], -f[1], -f[2]};
+#pragma unroll
+    for (int i = ND - 1; i >= 0; --i) {
+      tau[i] = tau[i] + ((i & 1) ? wn[1] : wn[2]);
+      if (i > 0) {
+        if (i & 1) force_to_parent<true>(cq[i], sq[i], ch.Lp[i], wn, wf);
+        else force_to_parent<false>(cq[i], sq[i], ch.Lp[i], wn, wf);
       }
     }
   }

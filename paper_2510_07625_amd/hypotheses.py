@@ -1,0 +1,91 @@
+"""Batched hypothesize-and-test over external tip forces (Sec. IV-D).
+
+P MPC instances each carry H force hypotheses, one solve per (instance,
+hypothesis) in one batch (slot p H + j): the solves of an instance differ only
+in the assumed external force on the tip of the last link. Every control tick:
+
+1. all P H solves re-solve from their instance's plant state, warm-started
+   from their previous plans shifted one knot;
+2. each instance applies the first control of hypothesis 0 (its current
+   estimate) to its plant, which feels the true force;
+3. every hypothesis predicts the instance's next state under the applied
+   control with its own force (the RK4 plant of that solve); the hypothesis
+   closest to the measured next state (Euclidean norm over the state) becomes
+   the instance's estimate;
+4. the hypotheses are re-centred on the estimate: hypothesis j is the estimate
+   plus sigma r_j d_j, with d_j fixed directions uniform on the sphere and r_j
+   spread over (0, 1] (hypothesis 0: the estimate itself), so that both the
+   direction and the magnitude are explored around it.
+
+Device work is stream-ordered; the selection reads P H prediction errors back
+to the host each tick.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def offsets(H: int, seed: int = 0) -> np.ndarray:
+    """[H, 3] hypothesis offsets of unit scale: row 0 zero, rows j > 0 direction
+    uniform on the sphere times a radius spread over (0, 1]."""
+    rng = np.random.default_rng([seed, H])
+    out = np.zeros((H, 3))
+    if H > 1:
+        d = rng.normal(size=(H - 1, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        r = np.arange(1, H) / (H - 1)
+        out[1:] = d * r[:, None]
+    return out
+
+
+@dataclass
+class HypothesisRun:
+    states: np.ndarray        # [ticks + 1, P, nx] plant states
+    estimates: np.ndarray     # [ticks + 1, P, 3] force estimates (before each tick; last after it)
+    selected: np.ndarray      # [ticks, P] selected hypothesis index
+    tick_ms: list
+
+
+def run(batch, P: int, H: int, x0, goal, ticks: int, true_force, sigma: float = 10.0, n_iters: int = 1,
+        h: float = 0.01, substeps: int = 10, seed: int = 0, f0=None) -> HypothesisRun:
+    """batch holds P H solves (slot p H + j); x0 [P, nx_max] and goal [P, nu_max]
+    are device tensors; true_force(tick) returns the plants' true forces [P, 3]
+    (numpy); f0 [P, 3] is the initial estimate (default zero)."""
+    import time
+
+    import torch
+    M = P * H
+    assert batch.M == M
+    dev = x0.device
+    nx, nu, N = batch.nx_max, batch.nu_max, batch.N_max
+    off = offsets(H, seed) * sigma                                   # [H, 3]
+    est = np.zeros((P, 3)) if f0 is None else np.array(f0, np.float64).reshape(P, 3)
+    slots = torch.arange(M, dtype=torch.int32, device=dev)
+    inst_slots = (torch.arange(P, dtype=torch.int32, device=dev) * H).contiguous()
+    Xo = torch.empty((M, N, nx), dtype=torch.float32, device=dev)
+    Uo = torch.empty((M, N - 1, nu), dtype=torch.float32, device=dev)
+    goal_m = goal.repeat_interleave(H, dim=0).contiguous()
+    x = x0.clone()
+    states, ests, sel, tick_ms = [x.cpu().numpy()], [est.copy()], [], []
+    for t in range(ticks):
+        t0 = time.perf_counter()
+        hyp = (est[:, None, :] + off[None, :, :]).reshape(M, 3)
+        batch.set_external_force(hyp)
+        xs_m = x.repeat_interleave(H, dim=0).contiguous()
+        batch.serve_step(slots, xs_m, goal_m, n_iters=n_iters, shift=1, Xout=Xo, Uout=Uo)
+        u = Uo[::H, 0].contiguous()                                    # hypothesis 0 of every instance
+        f_true = torch.from_numpy(np.asarray(true_force(t), np.float32).reshape(P, 3)).to(dev)
+        x_next = batch.plant_step(x, u, h=h, substeps=substeps, slots=inst_slots, fext=f_true)
+        pred = batch.plant_step(xs_m, u.repeat_interleave(H, dim=0).contiguous(), h=h, substeps=substeps,
+                                slots=slots)                           # each solve's own hypothesis
+        err = (pred.view(P, H, nx) - x_next[:, None, :]).norm(dim=2)   # [P, H]
+        j = err.argmin(dim=1).cpu().numpy()
+        est = hyp.reshape(P, H, 3)[np.arange(P), j]
+        x = x_next
+        states.append(x.cpu().numpy())
+        ests.append(est.copy())
+        sel.append(j)
+        tick_ms.append((time.perf_counter() - t0) * 1e3)
+    return HypothesisRun(np.stack(states), np.stack(ests), np.stack(sel), tick_ms)

@@ -101,7 +101,8 @@ def test_invalid_arguments_are_rejected_on_the_host():
     assert L.gato_set_mapping(None, 7, 32, 1) == g.GATO_EINVAL
     assert L.gato_autotune(None, None, None, None, None, 1, 1) == g.GATO_EINVAL
     assert L.gato_step_graph(None, None, None, None, None, 1, None) == g.GATO_EINVAL
-    assert L.gato_plant_step(None, 1, None, None, None, 0.01, 10, None, None, None) == g.GATO_EINVAL
+    assert L.gato_plant_step(None, 1, None, None, None, None, 0.01, 10, None, None, None) == g.GATO_EINVAL
+    assert L.gato_set_external_force(None, None) == g.GATO_EINVAL
     assert L.gato_set_rho(None, None) == g.GATO_EINVAL and L.gato_get_rho(None, None) == g.GATO_EINVAL
     rc, msg = _create([good_r], [good_p], g.Params(rho_adapt=3))
     assert rc == g.GATO_EINVAL and "rho_adapt" in msg
