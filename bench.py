@@ -420,9 +420,11 @@ def hypothesis_report(g, torch, P=32, Hs=(1, 8, 32), ticks=200, seed=4, sigma=12
         b.close()
         track = np.linalg.norm(r.states[:, :, :7] - qg[None], axis=2).mean(axis=1)
         ferr = np.linalg.norm(r.estimates - f_true[None], axis=2).mean(axis=1)
+        cost = hypotheses.realized_cost(r, base)
         out.append(dict(H=H, P=P, ticks=ticks, solves_per_s=P * H * ticks / dt_s,
                         tick_p50_ms=float(np.median(r.tick_ms)), tick_p99_ms=float(np.percentile(r.tick_ms, 99)),
                         force_error_N=dict(start=float(ferr[0]), end=float(ferr[-20:].mean())),
+                        realized_cost=dict(mean=float(cost.mean()), median=float(np.median(cost))),
                         tracking_error_rad=dict(mean=float(track.mean()), end=float(track[-50:].mean()))))
         print(f"# hypotheses {out[-1]}", file=sys.stderr, flush=True)
     return out

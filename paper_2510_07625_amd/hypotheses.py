@@ -45,6 +45,7 @@ class HypothesisRun:
     states: np.ndarray        # [ticks + 1, P, nx] plant states
     estimates: np.ndarray     # [ticks + 1, P, 3] force estimates (before each tick; last after it)
     selected: np.ndarray      # [ticks, P] selected hypothesis index
+    controls: np.ndarray      # [ticks, P, nu] applied controls
     tick_ms: list
 
 
@@ -68,7 +69,7 @@ def run(batch, P: int, H: int, x0, goal, ticks: int, true_force, sigma: float = 
     Uo = torch.empty((M, N - 1, nu), dtype=torch.float32, device=dev)
     goal_m = goal.repeat_interleave(H, dim=0).contiguous()
     x = x0.clone()
-    states, ests, sel, tick_ms = [x.cpu().numpy()], [est.copy()], [], []
+    states, ests, sel, ctrl, tick_ms = [x.cpu().numpy()], [est.copy()], [], [], []
     for t in range(ticks):
         t0 = time.perf_counter()
         hyp = (est[:, None, :] + off[None, :, :]).reshape(M, 3)
@@ -85,7 +86,23 @@ def run(batch, P: int, H: int, x0, goal, ticks: int, true_force, sigma: float = 
         est = hyp.reshape(P, H, 3)[np.arange(P), j]
         x = x_next
         states.append(x.cpu().numpy())
+        ctrl.append(u.cpu().numpy())
         ests.append(est.copy())
         sel.append(j)
         tick_ms.append((time.perf_counter() - t0) * 1e3)
-    return HypothesisRun(np.stack(states), np.stack(ests), np.stack(sel), tick_ms)
+    return HypothesisRun(np.stack(states), np.stack(ests), np.stack(sel), np.stack(ctrl), tick_ms)
+
+
+def realized_cost(run: HypothesisRun, solves_per_instance, dt_weighting: bool = False) -> np.ndarray:
+    """Closed-loop stage cost actually incurred per instance, summed over the
+    ticks: 1/2 (x - x_g)^T Q (x - x_g) + 1/2 u^T R u with the problem's own
+    weights (x_g = [q_goal; 0]) -- the quantity each re-solve minimises."""
+    P = run.states.shape[1]
+    out = np.zeros(P)
+    for p, s in enumerate(solves_per_instance):
+        n = s.n
+        xg = np.concatenate([s.qgoal, np.zeros(n)])
+        d = run.states[:-1, p, :2 * n].astype(np.float64) - xg
+        u = run.controls[:, p, :n].astype(np.float64)
+        out[p] = 0.5 * np.sum(d * d * s.Qd) + 0.5 * np.sum(u * u * s.Rd)
+    return out

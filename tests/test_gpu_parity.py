@@ -196,6 +196,36 @@ def test_sqp_trajectory_at_config_tolerance(n, N, M):
         _replay_check(s, Xg[i], Ug[i], st[i], p, tol=max(1e-4, 3 * e_ref), check_merit=False)
 
 
+def test_full_size_batch_sampled_solves():
+    # The benchmark's launch: M = 256 seeded 7-DoF chains, N = 32, 10 SQP
+    # iterations, PCG tol 1e-5, one workgroup per solve (bench.py's step with
+    # the iterate restored and the warm start cleared). Sampled solves are
+    # replayed in the oracle; bound as at the configured tolerance above. The
+    # per-iteration statistics of every solve must be clean.
+    _say("full size M=256")
+    M = 256
+    solves = w.chain_batch(0, M)
+    p = g.Params(sqp_iters=10, pcg_tol=1e-5)
+    b = g.Batch.from_solves(solves, p)
+    xs, goal, X, U = g.pack_inputs(solves)
+    st_buf = b.stats_buffer(10)
+    b.reset_warm_start()
+    b.step(xs, goal, X, U, 10, st_buf)
+    torch.cuda.synchronize()
+    st = g.Batch.decode_stats(st_buf, M, 10)
+    Xg, Ug = X.cpu().numpy().astype(np.float64), U.cpu().numpy().astype(np.float64)
+    b.close()
+    assert not (st["status"] & (g.ST_NONFINITE | g.ST_PCG_MAXITER)).any()
+    for i in (0, 97, 255):
+        s = solves[i]
+        alphas = st[i]["alpha"].astype(np.float64)
+        exact = oracle.sqp(s, oracle.Params(kkt_mode=0), alpha_replay=alphas)
+        same = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=1e-5), alpha_replay=alphas)
+        e_ref = max(np.abs(same.X - exact.X).max() / np.abs(exact.X).max(),
+                    np.abs(same.U - exact.U).max() / np.abs(exact.U).max())
+        _replay_check(s, Xg[i], Ug[i], st[i], p, tol=max(1e-4, 3 * e_ref), check_merit=False)
+
+
 def test_uneven_batch_matches_single_solves():
     _say("uneven batch")
     solves = w.uneven_batch(5, M=6, horizons=(16, 32, 64))
