@@ -429,8 +429,21 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     Real th[kThGlobal ? 1 : KPT][NX];   // row of the diagonal block theta_{k-1} (Q_0^-1 for k = 0)
     // A entries are exact in FP32 and are kept so (converted to Real at use),
     // which halves their register footprint.
-    float Am[KPT][NX];    // row `lane` of A_{k-1}: S~_{k,k-1} = -A_{k-1} Q_{k-1}^-1
-    float Ac[KPT][NX];    // column `lane` of A_k: S~_{k,k+1} = -Q_k^-1 A_k^T
+    // With four knots per lane group (FP64 variant) these rows are read back
+    // from the A blocks in the workspace where they are used (as the Schur rows
+    // are), which frees 112 registers per lane; the FP32 variant has the room.
+    constexpr bool kRowsGlobal = KPT >= 4 && sizeof(Real) == 8;
+    constexpr int KR = kRowsGlobal ? 1 : KPT;
+    float Am[KR][NX];     // row `lane` of A_{k-1}: S~_{k,k-1} = -A_{k-1} Q_{k-1}^-1
+    float Ac[KR][NX];     // column `lane` of A_k: S~_{k,k+1} = -Q_k^-1 A_k^T
+    auto am = [&](int p, int m) -> float {
+      if constexpr (kRowsGlobal) return Ablk(slot + p * SLOTS - 1)[lane * NX + m];
+      else return Am[p][m];
+    };
+    auto ac = [&](int p, int m) -> float {
+      if constexpr (kRowsGlobal) return Ablk(slot + p * SLOTS)[m * NX + lane];
+      else return Ac[p][m];
+    };
     Real gam[KPT];
     Real qown[KPT];       // Q_k^-1 at (lane, lane)
     Real Pd[KPT][NX];     // row of the inverse diagonal block (preconditioner)
@@ -442,8 +455,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
       for (int m = 0; m < NX; ++m) {
         thr[m] = 0;
-        Am[p][m] = 0.f;
-        Ac[p][m] = 0.f;
+        if constexpr (!kRowsGlobal) {
+          Am[p][m] = 0.f;
+          Ac[p][m] = 0.f;
+        }
         Pd[p][m] = 0;
       }
       gam[p] = 0;
@@ -462,8 +477,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           Real ArQ[NX], BrR[NU];
 #pragma unroll
           for (int m = 0; m < NX; ++m) {
-            Am[p][m] = A[lane * NX + m];
-            ArQ[m] = (Real)Am[p][m] * (Real)sm.Qi[m];
+            const float arow = A[lane * NX + m];
+            if constexpr (!kRowsGlobal) Am[p][m] = arow;
+            ArQ[m] = (Real)arow * (Real)sm.Qi[m];
           }
 #pragma unroll
           for (int m = 0; m < NU; ++m) BrR[m] = (Real)B[lane * NU + m] * (Real)D.Ri[m];
@@ -483,10 +499,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           for (int m = 0; m < NU; ++m) z -= BrR[m] * (Real)sm.rg[km][m];
           gam[p] = z;
         }
-        if (k < N - 1) {
-          const float *A = Ablk(k);
+        if constexpr (!kRowsGlobal) {
+          if (k < N - 1) {
+            const float *A = Ablk(k);
 #pragma unroll
-          for (int m = 0; m < NX; ++m) Ac[p][m] = A[m * NX + lane];
+            for (int m = 0; m < NX; ++m) Ac[p][m] = A[m * NX + lane];
+          }
         }
       }
       // Inverse of the diagonal block: Gauss-Jordan inside the lane group
@@ -683,12 +701,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         }
         if (k > 0) {
 #pragma unroll
-          for (int m = 0; m < NX; ++m) acc -= (Real)Am[p][m] * sm.sv[k - 1][m];
+          for (int m = 0; m < NX; ++m) acc -= (Real)am(p, m) * sm.sv[k - 1][m];
         }
         if (k < N - 1) {
           Real t = 0;
 #pragma unroll
-          for (int m = 0; m < NX; ++m) t += (Real)Ac[p][m] * sm.pv[k + 1][m];
+          for (int m = 0; m < NX; ++m) t += (Real)ac(p, m) * sm.pv[k + 1][m];
           acc -= qown[p] * t;
         }
         return acc;
@@ -753,12 +771,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       Real oz = 0;   // (O z)_k at row `lane`
       if (k > 0) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) oz -= (Real)Am[p][m] * sm.gv[k - 1][m];
+        for (int m = 0; m < NX; ++m) oz -= (Real)am(p, m) * sm.gv[k - 1][m];
       }
       if (k < N - 1) {
         Real t = 0;
 #pragma unroll
-        for (int m = 0; m < NX; ++m) t += (Real)Ac[p][m] * sm.rv[k + 1][m];
+        for (int m = 0; m < NX; ++m) t += (Real)ac(p, m) * sm.rv[k + 1][m];
         oz -= qown[p] * t;
       }
       return group_dinv(p, v - oz);
@@ -876,7 +894,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
         for (int p = 0; p < KPT; ++p)
 #pragma unroll
-          for (int m = 0; m < NX; ++m) asm volatile("" : "+v"(Am[p][m]), "+v"(Ac[p][m]), "+v"(Pdf[p][m]));
+          for (int m = 0; m < NX; ++m) {
+            if constexpr (!kRowsGlobal) asm volatile("" : "+v"(Am[p][m]), "+v"(Ac[p][m]));
+            asm volatile("" : "+v"(Pdf[p][m]));
+          }
         if constexpr (!kFactP) {
 #pragma unroll
           for (int p = 0; p < KPT; ++p)
@@ -956,7 +977,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         Real sx = (Real)sm.qg[k][lane] - lam[p];
         if (k < N - 1) {
 #pragma unroll
-          for (int m = 0; m < NX; ++m) sx += (Real)Ac[p][m] * sm.pv[k + 1][m];
+          for (int m = 0; m < NX; ++m) sx += (Real)ac(p, m) * sm.pv[k + 1][m];
         }
         const float dx = (float)(-qown[p] * sx);
         sm.dX[k][lane] = dx;
