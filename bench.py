@@ -16,7 +16,7 @@ setting (throughput, trajectory and KKT-solution error), the uneven batch
 (mixed DoF and horizon, per-shape against mixed-shape launch, autotuned,
 graph-captured), the closed-loop disturbance batch (RK4 plant, torque
 impulses, ticks replayed in the oracle), the served MPC loop at several
-Poisson arrival rates, and the oracle's CPU throughput on a bounded sample.
+Poisson arrival rates (Python and native request loops), and the oracle's CPU throughput on a bounded sample.
 
 Prints one JSON line.
 """
@@ -461,32 +461,40 @@ def heatmap(g, torch, Ms=(1, 8, 32, 64, 128, 256, 512), Ns=(8, 16, 32, 64, 128),
 def serving(g, torch, rates, duration_s, pool=256, iters=1, slots=3, deadline_s=1e-3, seed=0):
     """Served MPC loop: Poisson arrivals over a pool of instances, each request
     warm-started from its instance's device-resident trajectory shifted one knot,
-    goal perturbed by N(0, 0.05) rad; continuous batching over `slots` streams."""
+    goal perturbed by N(0, 0.05) rad; continuous batching over `slots` streams,
+    by the Python scheduler and by the native loop (gato_serve_run) in turn."""
     import workload as w
-    from paper_2510_07625_amd.serve import GpuExecutor, Request, Scheduler
+    from paper_2510_07625_amd.serve import GpuExecutor, NativeScheduler, Request, Scheduler
     solves = w.chain_batch(seed, pool)
     b = g.Batch.from_solves(solves, g.Params(sqp_iters=iters))
     xs, goal, X, U = g.pack_inputs(solves)
     ex = GpuExecutor(b, slots=slots, n_iters=iters)
     goals = np.stack([s.qgoal for s in solves])
     out = []
+    x0 = np.stack([s.xs for s in solves])
     for rate in rates:
-        b.set_trajectories(X, U)
-        b.reset_warm_start()
-        torch.cuda.synchronize()
         rng = np.random.default_rng([seed, int(rate)])
         n = int(rate * duration_s)
         t = np.cumsum(rng.exponential(1.0 / rate, n))
         inst = rng.integers(pool, size=n)
         reqs = [Request(i, int(inst[i]), float(t[i]), goals[inst[i]] + rng.normal(0.0, 0.05, goals.shape[1]))
                 for i in range(n)]
-        sch = Scheduler(ex, np.stack([s.xs for s in solves]), memory_budget=pool * ex.bytes_per_request,
-                        deadline_s=deadline_s, queue_limit=4 * pool)
-        rep = sch.run(reqs)
-        sm = rep.summary()
-        sm.update(rate_req_s=rate, offered=n, nonfinite=int(sum(1 for c in rep.completions if c.status & 2)))
-        out.append(sm)
-        print(f"# served {rate} req/s: {sm}", file=sys.stderr, flush=True)
+        for loop in ("python", "native"):
+            b.set_trajectories(X, U)
+            b.reset_warm_start()
+            torch.cuda.synchronize()
+            if loop == "python":
+                sch = Scheduler(ex, x0, memory_budget=pool * ex.bytes_per_request, deadline_s=deadline_s,
+                                queue_limit=4 * pool)
+            else:
+                sch = NativeScheduler(b, x0, slots=slots, n_iters=iters, memory_budget=pool * ex.bytes_per_request,
+                                      deadline_s=deadline_s, queue_limit=4 * pool)
+            rep = sch.run(reqs)
+            sm = rep.summary()
+            sm.update(loop=loop, rate_req_s=rate, offered=n,
+                      nonfinite=int(sum(1 for c in rep.completions if c.status & 2)))
+            out.append(sm)
+            print(f"# served {rate} req/s ({loop} loop): {sm}", file=sys.stderr, flush=True)
     ex.close()
     b.close()
     return out

@@ -48,6 +48,7 @@ extern "C" {
 #define GATO_ST_PCG_MAXITER 1u /* PCG hit its iteration cap before the tolerance */
 #define GATO_ST_NONFINITE 2u   /* non-finite step or merit; the iterate was kept */
 #define GATO_ST_NO_DESCENT 4u  /* no candidate step lowered the merit (stepped anyway) */
+#define GATO_ST_ADMIT_REJECT 8u /* serving: the request was refused at admission (queue full) */
 
 /* Robot models. */
 #define GATO_MODEL_SERIAL_CHAIN 0        /* revolute chain, joint axes z, y, z, y, ... */
@@ -280,6 +281,32 @@ int gato_reset_warm_start(gato_batch *b);
  * Errors: GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE.
  */
 typedef struct gato_serve_ctx gato_serve_ctx;
+
+/*
+ * Native request loop over R MPC re-solve requests (the serving pattern: new
+ * requests join while others run on the device). Request r arrives at
+ * h_arrival_s[r] seconds after the call starts (ascending), for instance
+ * h_instance[r] (0..M-1) with goal h_goal[r] ([R][nu_max], host). The loop
+ * admits requests as they arrive into per-instance FIFOs (GATO_ST_ADMIT_REJECT
+ * when queue_limit > 0 requests already wait); whenever one of n_ctx launch
+ * contexts is free it launches the oldest waiting request of every instance
+ * that has nothing in flight, as many as memory_budget allows
+ * (gato_workspace_bytes per request; 0: no limit), each re-solved for n_iters
+ * SQP iterations from the instance's state h_state[instance] ([M][nx_max],
+ * host, updated in place to the plan's x_1 when the result arrives) and its
+ * previous plan shifted one knot. Outputs per request: h_latency_s (arrival
+ * to host-visible result, -1 if rejected), h_launch_s (launch time, may be
+ * NULL), h_status (OR of the iterations' status bits) and h_u0 (the control to
+ * apply, [R][nu_max], may be NULL; untouched for rejected requests).
+ * *h_launches (may be NULL) gets the number of launches. All host memory is
+ * the caller's. Blocking; busy-waits on the calling thread; each context
+ * runs on its own stream, so it does not wait on other work of the process.
+ * Errors: GATO_EINVAL (bad sizes, NULL arrays, instance out of range,
+ * arrival times not ascending or not finite), GATO_ENOMEM, GATO_EDEVICE.
+ */
+int gato_serve_run(gato_batch *b, int n_ctx, int n_iters, int R, const double *h_arrival_s, const int *h_instance,
+                   const float *h_goal, float *h_state, int queue_limit, size_t memory_budget, double *h_latency_s,
+                   double *h_launch_s, unsigned *h_status, float *h_u0, int *h_launches);
 int gato_serve_ctx_create(gato_batch *b, int capacity, int n_iters, gato_serve_ctx **out);
 void gato_serve_ctx_destroy(gato_serve_ctx *c);
 int gato_serve_ctx_buffers(gato_serve_ctx *c, int **h_slots, float **h_xs, float **h_goal, const float **h_x1,

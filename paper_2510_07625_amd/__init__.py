@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgato.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "gato.h")
 
 GATO_OK, GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE, GATO_EUNSUPPORTED = 0, -1, -2, -3, -4
-ST_PCG_MAXITER, ST_NONFINITE, ST_NO_DESCENT = 1, 2, 4
+ST_PCG_MAXITER, ST_NONFINITE, ST_NO_DESCENT, ST_ADMIT_REJECT = 1, 2, 4, 8
 MODEL_SERIAL_CHAIN, MODEL_DOUBLE_INTEGRATOR = 0, 1
 MAX_DOF, MAX_KNOTS, MAX_ALPHA = 7, 128, 16
 DISPATCH_AUTO, DISPATCH_GROUPED, DISPATCH_MIXED = 0, 1, 2
@@ -69,7 +69,7 @@ EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "
            "gato_set_external_force", "gato_set_dispatch",
            "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_set_rho", "gato_get_rho",
            "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
-           "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_last_error")
+           "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_serve_run", "gato_last_error")
 
 _lib = None
 
@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
         L.gato_serve_ctx_query.argtypes = [vp]
         L.gato_serve_ctx_trajectories.argtypes = [vp, vp, vp]
         L.gato_get_rho.argtypes = [vp, C.POINTER(C.c_double)]
+        L.gato_serve_run.argtypes = [vp, ip, ip, ip, vp, vp, vp, vp, ip, C.c_size_t, vp, vp, vp, vp, C.POINTER(ip)]
         L.gato_buckets.argtypes = [vp, C.POINTER(Bucket), ip, C.POINTER(ip)]
         L.gato_set_mapping.argtypes = [vp, ip, ip, ip]
         L.gato_autotune.argtypes = [vp, vp, vp, vp, vp, ip, ip]

@@ -3,7 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -731,6 +733,130 @@ int gato_serve_ctx_trajectories(gato_serve_ctx *c, float *h_X, float *h_U) {
     e = hipMemcpyAsync(h_U, c->d_U, R * (N - 1) * nu * sizeof(float), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(e, "serve trajectories");
+  return GATO_OK;
+}
+
+int gato_serve_run(gato_batch *b, int n_ctx, int n_iters, int R, const double *h_arrival_s, const int *h_instance,
+                   const float *h_goal, float *h_state, int queue_limit, size_t memory_budget, double *h_latency_s,
+                   double *h_launch_s, unsigned *h_status, float *h_u0, int *h_launches) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (n_ctx < 1 || n_ctx > 16) return fail(GATO_EINVAL, "n_ctx must be in 1..16");
+  if (n_iters < 1) return fail(GATO_EINVAL, "n_iters must be >= 1");
+  if (R < 0) return fail(GATO_EINVAL, "R must be >= 0");
+  if (R > 0 && (!h_arrival_s || !h_instance || !h_goal || !h_latency_s || !h_status))
+    return fail(GATO_EINVAL, "request arrays must not be NULL");
+  if (!h_state) return fail(GATO_EINVAL, "state must not be NULL");
+  for (int r = 0; r < R; ++r) {
+    if (h_instance[r] < 0 || h_instance[r] >= b->M) return fail(GATO_EINVAL, "instance outside 0..M-1");
+    if (!std::isfinite(h_arrival_s[r]) || (r > 0 && h_arrival_s[r] < h_arrival_s[r - 1]))
+      return fail(GATO_EINVAL, "arrival times must be finite and ascending");
+  }
+  const int M = b->M, nx = 2 * b->n_max, nu = b->n_max;
+  const size_t per_req = gato_workspace_bytes(b->n_max, b->N_max, &b->p);
+  std::vector<gato_serve_ctx *> ctx(n_ctx, nullptr);
+  auto cleanup = [&]() {
+    for (auto *c : ctx)
+      if (c) gato_serve_ctx_destroy(c);
+  };
+  for (int i = 0; i < n_ctx; ++i) {
+    const int rc = gato_serve_ctx_create(b, M, n_iters, &ctx[i]);
+    if (rc != GATO_OK) { cleanup(); return rc; }
+  }
+  std::vector<std::deque<int>> fifo(M);
+  std::deque<int> ready;
+  std::vector<char> in_ready(M, 0), busy(M, 0);
+  std::vector<std::vector<int>> launched(n_ctx);
+  std::vector<double> t_launch(n_ctx, 0.0);
+  std::vector<int> free_ctx;
+  for (int i = n_ctx - 1; i >= 0; --i) free_ctx.push_back(i);
+  size_t inflight_bytes = 0;
+  int next = 0, waiting = 0, inflight = 0, launches = 0;
+  for (int r = 0; r < R; ++r) {
+    h_latency_s[r] = -1.0;
+    h_status[r] = 0u;
+    if (h_launch_s) h_launch_s[r] = -1.0;
+  }
+  auto make_ready = [&](int inst) {
+    if (!busy[inst] && !in_ready[inst] && !fifo[inst].empty()) {
+      ready.push_back(inst);
+      in_ready[inst] = 1;
+    }
+  };
+  const auto t0 = std::chrono::steady_clock::now();
+  auto now = [&]() { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+  while (next < R || waiting > 0 || inflight > 0) {
+    const double t = now();
+    // 1. Admit arrivals.
+    while (next < R && h_arrival_s[next] <= t) {
+      if (queue_limit > 0 && waiting >= queue_limit) {
+        h_status[next] = GATO_ST_ADMIT_REJECT;
+      } else {
+        fifo[h_instance[next]].push_back(next);
+        ++waiting;
+        make_ready(h_instance[next]);
+      }
+      ++next;
+    }
+    // 2. Retire finished launches.
+    for (int c = 0; c < n_ctx; ++c) {
+      if (launched[c].empty()) continue;
+      const int q = gato_serve_ctx_query(ctx[c]);
+      if (q < 0) { cleanup(); return q; }
+      if (q == 0) continue;
+      const double td = now();
+      for (size_t j = 0; j < launched[c].size(); ++j) {
+        const int r = launched[c][j], inst = h_instance[r];
+        std::memcpy(h_state + (size_t)inst * nx, ctx[c]->h_x1 + j * nx, nx * sizeof(float));
+        if (h_u0) std::memcpy(h_u0 + (size_t)r * nu, ctx[c]->h_u0 + j * nu, nu * sizeof(float));
+        unsigned st = 0u;
+        for (int it = 0; it < n_iters; ++it) st |= ctx[c]->h_stats[j * n_iters + it].status;
+        h_status[r] = st;
+        h_latency_s[r] = td - h_arrival_s[r];
+        busy[inst] = 0;
+        make_ready(inst);
+      }
+      inflight_bytes -= per_req * launched[c].size();
+      launched[c].clear();
+      --inflight;
+      free_ctx.push_back(c);
+    }
+    // 3. Launch the oldest request of every ready instance while a context is free.
+    if (!free_ctx.empty() && !ready.empty()) {
+      size_t room = ready.size();
+      if (memory_budget > 0 && per_req > 0)
+        room = std::min(room, memory_budget > inflight_bytes ? (memory_budget - inflight_bytes) / per_req : 0);
+      if (room > 0) {
+        const int c = free_ctx.back();
+        free_ctx.pop_back();
+        gato_serve_ctx *cx = ctx[c];
+        const int n = (int)std::min(room, (size_t)M);
+        for (int j = 0; j < n; ++j) {
+          const int inst = ready.front();
+          ready.pop_front();
+          in_ready[inst] = 0;
+          const int r = fifo[inst].front();
+          fifo[inst].pop_front();
+          busy[inst] = 1;
+          cx->h_slots[j] = inst;
+          std::memcpy(cx->h_xs + (size_t)j * nx, h_state + (size_t)inst * nx, nx * sizeof(float));
+          std::memcpy(cx->h_goal + (size_t)j * nu, h_goal + (size_t)r * nu, nu * sizeof(float));
+          launched[c].push_back(r);
+        }
+        waiting -= n;
+        const double tl = now();
+        for (int r : launched[c])
+          if (h_launch_s) h_launch_s[r] = tl;
+        const int rc = gato_serve_ctx_submit(cx, n, 1);
+        if (rc != GATO_OK) { cleanup(); return rc; }
+        inflight_bytes += per_req * n;
+        ++inflight;
+        ++launches;
+        continue;
+      }
+    }
+  }
+  cleanup();
+  if (h_launches) *h_launches = launches;
   return GATO_OK;
 }
 

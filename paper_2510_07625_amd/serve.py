@@ -190,6 +190,68 @@ class Scheduler:
         return ServeReport(done, rejected, self.deadline, launches, launched_reqs / max(launches, 1), max_inflight)
 
 
+class NativeScheduler:
+    """The same continuous-batching policy run natively (``gato_serve_run``).
+
+    Per-instance FIFOs, the ready queue of idle instances, the queue limit and
+    the memory budget behave as in :class:`Scheduler`; the loop, the clock
+    (steady clock, seconds from the start of the call) and the launch
+    contexts are all in the C library, so the host overhead per launch is a
+    few microseconds instead of Python's tens. The start states are updated in
+    place as results arrive, exactly as :class:`Scheduler` does.
+    """
+
+    def __init__(self, batch, start_states: np.ndarray, slots: int = 4, n_iters: int = 1,
+                 memory_budget: int | None = None, deadline_s: float = 1e-3, queue_limit: int | None = None):
+        self.b = batch
+        self.slots = int(slots)
+        self.n_iters = int(n_iters)
+        self.budget = int(memory_budget or 0)
+        self.deadline = deadline_s
+        self.queue_limit = int(queue_limit or 0)
+        self.state = np.zeros((batch.M, batch.nx_max), np.float32)
+        s = np.asarray(start_states, np.float32)
+        self.state[:, :s.shape[1]] = s
+
+    def run(self, requests: list) -> ServeReport:
+        import ctypes as C
+        from . import ST_ADMIT_REJECT, _check, lib
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        R, nu = len(reqs), self.b.nu_max
+        arrival = np.array([r.arrival for r in reqs], np.float64)
+        inst = np.array([r.instance for r in reqs], np.int32)
+        goal = np.zeros((R, nu), np.float32)
+        for i, r in enumerate(reqs):
+            goal[i, :len(r.goal)] = r.goal
+        lat = np.zeros(R, np.float64)
+        tl = np.zeros(R, np.float64)
+        status = np.zeros(R, np.uint32)
+        u0 = np.zeros((R, nu), np.float32)
+        launches = C.c_int()
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        _check(lib().gato_serve_run(self.b._h, self.slots, self.n_iters, R, p(arrival), p(inst), p(goal),
+                                    p(self.state), self.queue_limit, self.budget, p(lat), p(tl), p(status),
+                                    p(u0), C.byref(launches)))
+        done, rejected = [], []
+        for i, r in enumerate(reqs):
+            if status[i] & ST_ADMIT_REJECT:
+                rejected.append(r)
+            else:
+                done.append(Completion(r.rid, r.instance, r.arrival, float(tl[i]), r.arrival + float(lat[i]),
+                                       int(status[i]), None, u0[i].astype(np.float64)))
+        # Launch intervals (requests of one launch share its launch time) give the peak concurrency.
+        spans: dict = {}
+        for c in done:
+            spans[c.launched] = max(spans.get(c.launched, c.done), c.done)
+        events = sorted([(t, 1) for t in spans] + [(e, -1) for e in spans.values()], key=lambda x: (x[0], x[1]))
+        cur = peak = 0
+        for _, d in events:
+            cur += d
+            peak = max(peak, cur)
+        n_l = max(launches.value, 1)
+        return ServeReport(done, rejected, self.deadline, launches.value, len(done) / n_l, peak)
+
+
 class GpuExecutor:
     """Drives the serving launch contexts of the C ABI for a pool of MPC instances.
 
@@ -227,7 +289,7 @@ class GpuExecutor:
     def finish(self, slot: int):
         c = self.ctx[slot]
         R = c.n
-        status = c.stats["status"][:R].max(axis=1)
+        status = np.bitwise_or.reduce(c.stats["status"][:R], axis=1)
         x1 = c.x1[:R].astype(np.float64)
         u0 = c.u0[:R].astype(np.float64)
         return [(status[r], x1[r], u0[r]) for r in range(R)]

@@ -14,7 +14,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_2510_07625_amd as g  # noqa: E402
-from paper_2510_07625_amd.serve import GpuExecutor, Request, Scheduler  # noqa: E402
+from paper_2510_07625_amd.serve import GpuExecutor, NativeScheduler, Request, Scheduler  # noqa: E402
 
 
 def _say(msg):
@@ -139,3 +139,61 @@ def test_serve_context_equals_the_serve_step():
     ctx.close()
     b1.close()
     b2.close()
+
+
+def _stream(P, solves, n, rate, seed):
+    g_ = np.random.default_rng(seed)
+    reqs, t = [], 0.0
+    for i in range(n):
+        t += g_.exponential(1 / rate)
+        inst = int(g_.integers(P))
+        reqs.append(Request(i, inst, t, solves[inst].qgoal + g_.normal(0, 0.05, 7)))
+    return reqs
+
+
+def test_native_loop_ends_in_the_same_states_as_the_python_loop():
+    # A request's result depends only on its instance's own history (its FIFO
+    # order, start states and warm starts), never on which launch it joined,
+    # so both loops must leave every instance in the bit-identical state.
+    _say("native serve loop vs python loop")
+    P = 24
+    solves, b1, xs, goal, X, U = _pool(P, seed=7)
+    b2 = g.Batch.from_solves(solves, g.Params())
+    b1.set_trajectories(X, U)
+    b2.set_trajectories(X, U)
+    reqs = _stream(P, solves, 400, 20000.0, seed=1)
+    x0 = np.stack([s.xs for s in solves])
+    ex = GpuExecutor(b1, slots=3, n_iters=2)
+    py = Scheduler(ex, x0, deadline_s=1e-3)
+    rp = py.run(reqs)
+    ex.close()
+    nat = NativeScheduler(b2, x0, slots=3, n_iters=2)
+    rn = nat.run(reqs)
+    sp, sn = rp.summary(), rn.summary()
+    print("python:", sp)
+    print("native:", sn)
+    assert sn["completed"] == sp["completed"] == 400 and sn["rejected"] == 0
+    np.testing.assert_array_equal(nat.state, py.state.astype(np.float32))
+    # The control of each instance's last request agrees too.
+    last_p = {c.instance: c for c in sorted(rp.completions, key=lambda c: c.rid)}
+    last_n = {c.instance: c for c in sorted(rn.completions, key=lambda c: c.rid)}
+    for i in last_p:
+        np.testing.assert_array_equal(last_n[i].u0, last_p[i].u0)
+        assert last_n[i].status == last_p[i].status
+    assert all(c.launched >= c.arrival and c.done > c.launched for c in rn.completions)
+    assert 1 <= rn.launches <= 400 and 1 <= rn.max_inflight <= 3
+    b1.close()
+    b2.close()
+
+
+def test_native_loop_rejects_beyond_the_queue_limit():
+    _say("native serve loop queue limit")
+    P = 8
+    solves, b, xs, goal, X, U = _pool(P, seed=8)
+    b.set_trajectories(X, U)
+    reqs = [Request(i, i % P, 0.0, solves[i % P].qgoal) for i in range(64)]   # one burst
+    nat = NativeScheduler(b, np.stack([s.xs for s in solves]), slots=2, n_iters=1, queue_limit=10)
+    rep = nat.run(reqs)
+    assert len(rep.rejected) == 54 and len(rep.completions) == 10
+    assert sorted(c.rid for c in rep.completions) == list(range(10))
+    b.close()
