@@ -39,7 +39,8 @@ class _Robot(C.Structure):
 
 class _Problem(C.Structure):
     _fields_ = [("N", C.c_int), ("dt", C.c_double), ("Qd", C.POINTER(C.c_double)),
-                ("Rd", C.POINTER(C.c_double)), ("QNd", C.POINTER(C.c_double))]
+                ("Rd", C.POINTER(C.c_double)), ("QNd", C.POINTER(C.c_double)),
+                ("Wee", C.POINTER(C.c_double)), ("WeeN", C.POINTER(C.c_double)), ("pref", C.POINTER(C.c_double))]
 
 
 class _Params(C.Structure):
@@ -98,6 +99,8 @@ def lib():
                                       dp]
         L.orc_merit.argtypes = [rp, pp, dp, dp, dp, dp, C.c_double, dp, dp]
         L.orc_merit.restype = C.c_double
+        L.orc_tip.argtypes = [rp, dp, dp, dp]
+        L.orc_lq_hessian.argtypes = [rp, pp, C.c_double, dp, dp, dp, dp, dp]
         L.orc_sqp.argtypes = [rp, pp, C.POINTER(_Params), dp, dp, dp, dp, dp, C.POINTER(_IterLog), dp,
                               C.POINTER(C.c_int)]
         _lib = L
@@ -123,6 +126,11 @@ class _Ctx:
         N = getattr(s, "N", 2)
         self.Qd, self.Rd, self.QNd = (_f64(getattr(s, k, np.ones(1))) for k in ("Qd", "Rd", "QNd"))
         self.prob = _Problem(int(N), float(getattr(s, "dt", 0.01)), _ptr(self.Qd), _ptr(self.Rd), _ptr(self.QNd))
+        if getattr(s, "Wee", None) is not None:
+            # Task-space tracking of the tip (all three or none).
+            self.Wee, self.WeeN = _f64(s.Wee).reshape(3), _f64(s.WeeN).reshape(3)
+            self.pref = _f64(s.pref).reshape(int(N), 3)
+            self.prob.Wee, self.prob.WeeN, self.prob.pref = _ptr(self.Wee), _ptr(self.WeeN), _ptr(self.pref)
 
 
 def inverse_dynamics(s, q, qd, qdd, gravity: bool = True) -> np.ndarray:
@@ -205,6 +213,27 @@ def lq(s, X, U, rho: float = 0.0) -> dict:
     lib().orc_lq(C.byref(c.robot), C.byref(c.prob), float(rho), _ptr(xs), _ptr(qg), _ptr(X), _ptr(U),
                  *(_ptr(out[k]) for k in ("A", "B", "e", "q", "r", "c0")))
     return out
+
+
+def tip(s, q):
+    """Tip position [3] (base frame) and its Jacobian [3, n] at joint angles q."""
+    c = _Ctx(s)
+    q = _f64(q)
+    p, J = np.zeros(3), np.zeros((3, s.n))
+    if lib().orc_tip(C.byref(c.robot), _ptr(q), _ptr(p), _ptr(J)) != 0:
+        raise ValueError("tip kinematics need the revolute chain model")
+    return p, J
+
+
+def lq_hessian(s, X, U, rho: float = 0.0) -> np.ndarray:
+    """State Hessian blocks Q_k [N, nx, nx] of the QP at (X, U)."""
+    c = _Ctx(s)
+    X, U, xs, qg = _f64(X), _f64(U), _f64(s.xs), _f64(s.qgoal)
+    nx, N = 2 * s.n, s.N
+    Qf = np.zeros((N, nx, nx))
+    lib().orc_lq_hessian(C.byref(c.robot), C.byref(c.prob), float(rho), _ptr(xs), _ptr(qg), _ptr(X), _ptr(U),
+                         _ptr(Qf))
+    return Qf
 
 
 def kkt_parts(s, X, U, rho: float = 0.0):

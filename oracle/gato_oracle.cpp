@@ -34,6 +34,11 @@
 //       i = 0..A-1; ties go to the larger step.
 //   R8  Trial merits use the nonlinear defects at the trial point, one knot at a
 //       time (multiple shooting), as the per-knot merit blocks of Algorithm 1.
+//   R9  Task-space tracking (the experiments of Sec. IV track the end effector):
+//       knot k adds 1/2 (p(q_k) - pref_k)^T W (p(q_k) - pref_k) with p the tip
+//       position. The QP takes its exact gradient J^T W (p - pref) and its
+//       Gauss-Newton Hessian J^T W J, so each Q_k is a dense SPD block and
+//       Eq. (5) is used with the dense Q_k^-1 exactly as written.
 //
 // Robot model (the paper's robots are not available): a serial chain of n
 // revolute joints whose axes alternate z, y, z, y, ... starting with joint 0.
@@ -45,6 +50,7 @@
 // (q'' = u - k T q, T = tridiag(-1, 2, -1)), gives a linear system for the
 // Riccati pin.
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -68,6 +74,12 @@ typedef struct {
   const double *Qd;    /* [2n] diagonal of Q (stages 0..N-2) */
   const double *Rd;    /* [n]  diagonal of R */
   const double *QNd;   /* [2n] diagonal of Q_N (last knot) */
+  /* Task-space (end-effector) tracking, model 0; NULL Wee: none. Each knot
+   * adds 1/2 (p(q_k) - pref_k)^T diag(W) (p(q_k) - pref_k), p the tip position
+   * in the base frame, W = Wee for k < N-1 and WeeN for the last knot. */
+  const double *Wee;   /* [3] */
+  const double *WeeN;  /* [3] */
+  const double *pref;  /* [N][3] reference tip positions */
 } orc_problem;
 
 typedef struct {
@@ -248,6 +260,39 @@ void inverse_dynamics(const orc_robot &rb, const T *q, const T *qd, const T *qdd
     n_next = mom;
   }
 }
+
+// Position of the tip (the end of the last link) in base coordinates: the
+// frames are chained from the base exactly as in the kinematics above.
+template <class T>
+V3<T> tip_position(const orc_robot &rb, const T *q) {
+  const int n = rb.n;
+  const T zero(0.0);
+  V3<T> p = v3<T>(zero, zero, zero);
+  M3<T> Rm = eye3<T>();
+  for (int i = 0; i < n; ++i) {
+    if (i > 0) p = p + Rm * v3<T>(zero, zero, T(rb.link[5 * (i - 1) + 0]));
+    Rm = Rm * joint_rotation<T>(i, q[i]);
+  }
+  return p + Rm * v3<T>(zero, zero, T(rb.link[5 * (n - 1) + 0]));
+}
+
+// Tip position p[3] and its Jacobian J[3][n] = dp/dq (one dual-number pass per
+// joint).
+void tip_jacobian(const orc_robot &rb, const double *q, double *p, double *J) {
+  const int n = rb.n;
+  const V3<double> pv = tip_position<double>(rb, q);
+  p[0] = pv.x; p[1] = pv.y; p[2] = pv.z;
+  std::vector<Dual> qd(n);
+  for (int j = 0; j < n; ++j) {
+    for (int i = 0; i < n; ++i) qd[i] = Dual(q[i], i == j ? 1.0 : 0.0);
+    const V3<Dual> t = tip_position<Dual>(rb, qd.data());
+    J[0 * n + j] = t.x.d;
+    J[1 * n + j] = t.y.d;
+    J[2 * n + j] = t.z.d;
+  }
+}
+
+bool has_task(const orc_problem &pr) { return pr.Wee != nullptr && pr.WeeN != nullptr && pr.pref != nullptr; }
 
 // ---------------------------------------------------------------------------
 // Small dense linear algebra (row-major, FP64).
@@ -474,7 +519,8 @@ struct Lq {
   int n, nx, nu, N;
   std::vector<double> A, B, e;   // [N-1][nx][nx], [N-1][nx][nu], [N-1][nx]
   std::vector<double> q, r;      // [N][nx], [N-1][nu]
-  std::vector<double> Qh, Rh;    // [N][nx] diagonal Hessians (incl. rho), [nu]
+  std::vector<double> Qf;        // [N][nx][nx] state Hessian blocks Q_k (incl. rho)
+  std::vector<double> Rh;        // [nu] diagonal of R
   std::vector<double> c0;        // [nx] x_s - x_0
   bool ok;
 };
@@ -491,7 +537,7 @@ Lq build_lq(const orc_robot &rb, const orc_problem &pr, double rho, const double
   lq.e.assign((size_t)(N - 1) * nx, 0.0);
   lq.q.assign((size_t)N * nx, 0.0);
   lq.r.assign((size_t)(N > 1 ? N - 1 : 0) * nu, 0.0);
-  lq.Qh.assign((size_t)N * nx, 0.0);
+  lq.Qf.assign((size_t)N * nx * nx, 0.0);
   lq.Rh.assign(nu, 0.0);
   lq.c0.assign(nx, 0.0);
   std::vector<double> fx(nx);
@@ -503,9 +549,23 @@ Lq build_lq(const orc_robot &rb, const orc_problem &pr, double rho, const double
   }
   for (int k = 0; k < N; ++k) {
     const double *W = (k < N - 1) ? pr.Qd : pr.QNd;
+    double *Qk = &lq.Qf[(size_t)k * nx * nx];
     for (int i = 0; i < nx; ++i) {
       lq.q[(size_t)k * nx + i] = W[i] * (X[(size_t)k * nx + i] - goal_state(qgoal, n, i));
-      lq.Qh[(size_t)k * nx + i] = W[i] + rho;
+      Qk[i * nx + i] = W[i] + rho;
+    }
+    if (has_task(pr)) {
+      // Gauss-Newton terms of the tip tracking cost: gradient J^T W (p - pref),
+      // Hessian J^T W J (the residual's second derivative is dropped).
+      const double *We = (k < N - 1) ? pr.Wee : pr.WeeN;
+      std::vector<double> p(3), J((size_t)3 * n);
+      tip_jacobian(rb, X + (size_t)k * nx, p.data(), J.data());
+      for (int c = 0; c < 3; ++c) {
+        const double res = p[c] - pr.pref[(size_t)k * 3 + c];
+        for (int i = 0; i < n; ++i) lq.q[(size_t)k * nx + i] += J[c * n + i] * We[c] * res;
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) Qk[i * nx + j] += J[c * n + i] * We[c] * J[c * n + j];
+      }
     }
   }
   for (int k = 0; k < N - 1; ++k)
@@ -532,7 +592,7 @@ void assemble_kkt_parts(const Lq &lq, std::vector<double> &G, std::vector<double
   for (int k = 0; k < N; ++k) {
     for (int i = 0; i < nx; ++i) {
       const size_t o = off_x(lq, k) + i;
-      G[o * nz + o] = lq.Qh[(size_t)k * nx + i];
+      for (int j = 0; j < nx; ++j) G[o * nz + off_x(lq, k) + j] = lq.Qf[((size_t)k * nx + i) * nx + j];
       g[o] = lq.q[(size_t)k * nx + i];
     }
     if (k < N - 1)
@@ -603,13 +663,18 @@ void ct_times(const Lq &lq, const double *lam, double *out) {
 // Eq. (4), last formula: dZ = -G^-1 (g - C^T lambda).
 void recover_step(const Lq &lq, const double *lam, double *dZ) {
   const int nx = lq.nx, nu = lq.nu, N = lq.N;
-  std::vector<double> ctl(nz_of(lq));
+  std::vector<double> ctl(nz_of(lq)), Qc((size_t)nx * nx), v(nx);
   ct_times(lq, lam, ctl.data());
   for (int k = 0; k < N; ++k) {
-    for (int i = 0; i < nx; ++i) {
-      const size_t o = off_x(lq, k) + i;
-      dZ[o] = -(lq.q[(size_t)k * nx + i] - ctl[o]) / lq.Qh[(size_t)k * nx + i];
+    // dx_k = -Q_k^-1 (q_k - [C^T lambda]_k), Q_k SPD.
+    for (int i = 0; i < nx; ++i) v[i] = -(lq.q[(size_t)k * nx + i] - ctl[off_x(lq, k) + i]);
+    std::copy(&lq.Qf[(size_t)k * nx * nx], &lq.Qf[(size_t)(k + 1) * nx * nx], Qc.begin());
+    if (!cholesky(Qc.data(), nx)) {
+      for (int i = 0; i < nx; ++i) v[i] = std::nan("");
+    } else {
+      cholesky_solve(Qc.data(), nx, v.data());
     }
+    for (int i = 0; i < nx; ++i) dZ[off_x(lq, k) + i] = v[i];
     if (k < N - 1)
       for (int i = 0; i < nu; ++i) {
         const size_t o = off_u(lq, k) + i;
@@ -625,7 +690,8 @@ double kkt_residual(const Lq &lq, const double *dZ, const double *lam) {
   const size_t nz = nz_of(lq), nc = (size_t)lq.N * lq.nx;
   double res = 0.0;
   for (size_t i = 0; i < nz; ++i) {
-    double s = G[i * nz + i] * dZ[i] + g[i];
+    double s = g[i];
+    for (size_t j = 0; j < nz; ++j) s += G[i * nz + j] * dZ[j];
     for (size_t j = 0; j < nc; ++j) s -= C[j * nz + i] * lam[j];
     res = std::fmax(res, std::fabs(s));
   }
@@ -648,9 +714,10 @@ struct Schur {
   bool ok;
 };
 
-// theta_k, phi_k, zeta_k of Eq. (5) with diagonal Q_k, R placed into the block
-// tridiagonal S~ and gamma~ of Eq. (6) (signs per reading R2/R3), then the
-// stair preconditioner of Eq. (6) block by block.
+// theta_k, phi_k, zeta_k of Eq. (5), with the inverse Q_k^-1 of each (possibly
+// dense) state Hessian block and diagonal R, placed into the block tridiagonal
+// S~ and gamma~ of Eq. (6) (signs per reading R2/R3), then the stair
+// preconditioner of Eq. (6) block by block.
 Schur build_schur(const Lq &lq) {
   Schur s;
   const int nx = lq.nx, nu = lq.nu, N = lq.N;
@@ -665,33 +732,42 @@ Schur build_schur(const Lq &lq) {
   auto Pat = [&](int bi, int bj, int i, int j) -> double & {
     return s.P[((size_t)bi * nx + i) * dim + (size_t)bj * nx + j];
   };
+  // Q_k^-1 for every knot.
+  std::vector<double> Qi((size_t)N * nx * nx, 0.0);
+  for (int k = 0; k < N; ++k)
+    if (!invert(&lq.Qf[(size_t)k * nx * nx], nx, &Qi[(size_t)k * nx * nx])) s.ok = false;
   // Block (0,0) = Q_0^-1 and gamma~_0 = c_0 + Q_0^-1 q_0.
   for (int i = 0; i < nx; ++i) {
-    Sat(0, 0, i, i) = 1.0 / lq.Qh[i];
-    s.gamma[i] = lq.c0[i] + lq.q[i] / lq.Qh[i];
+    double t = lq.c0[i];
+    for (int j = 0; j < nx; ++j) {
+      Sat(0, 0, i, j) = Qi[i * nx + j];
+      t += Qi[i * nx + j] * lq.q[j];
+    }
+    s.gamma[i] = t;
   }
   std::vector<double> theta((size_t)N * nx * nx, 0.0), phi((size_t)(N - 1) * nx * nx, 0.0);
+  std::vector<double> AQ((size_t)nx * nx);
   for (int k = 0; k < N - 1; ++k) {
     const double *A = &lq.A[(size_t)k * nx * nx];
     const double *B = &lq.B[(size_t)k * nx * nu];
-    const double *Qk = &lq.Qh[(size_t)k * nx];
-    const double *Qk1 = &lq.Qh[(size_t)(k + 1) * nx];
+    const double *Qik = &Qi[(size_t)k * nx * nx];
+    const double *Qik1 = &Qi[(size_t)(k + 1) * nx * nx];
     double *th = &theta[(size_t)(k + 1) * nx * nx];
     double *ph = &phi[(size_t)k * nx * nx];
+    matmul(A, Qik, AQ.data(), nx, nx, nx);          // A_k Q_k^-1
     for (int i = 0; i < nx; ++i)
       for (int j = 0; j < nx; ++j) {
-        double t = 0.0;
-        for (int m = 0; m < nx; ++m) t += A[i * nx + m] * A[j * nx + m] / Qk[m];
+        double t = Qik1[i * nx + j];
+        for (int m = 0; m < nx; ++m) t += AQ[i * nx + m] * A[j * nx + m];
         for (int m = 0; m < nu; ++m) t += B[i * nu + m] * B[j * nu + m] / lq.Rh[m];
-        if (i == j) t += 1.0 / Qk1[i];
         th[i * nx + j] = t;                         // theta_k
-        ph[i * nx + j] = -A[i * nx + j] / Qk[j];    // phi_k = -A_k Q_k^-1
+        ph[i * nx + j] = -AQ[i * nx + j];           // phi_k = -A_k Q_k^-1
       }
     for (int i = 0; i < nx; ++i) {
       double z = 0.0;                               // zeta_k
-      for (int m = 0; m < nx; ++m) z -= A[i * nx + m] * lq.q[(size_t)k * nx + m] / Qk[m];
+      for (int m = 0; m < nx; ++m) z -= AQ[i * nx + m] * lq.q[(size_t)k * nx + m];
       for (int m = 0; m < nu; ++m) z -= B[i * nu + m] * lq.r[(size_t)k * nu + m] / lq.Rh[m];
-      z += lq.q[(size_t)(k + 1) * nx + i] / Qk1[i];
+      for (int m = 0; m < nx; ++m) z += Qik1[i * nx + m] * lq.q[(size_t)(k + 1) * nx + m];
       s.gamma[(size_t)(k + 1) * nx + i] = lq.e[(size_t)k * nx + i] + z;
     }
     for (int i = 0; i < nx; ++i)
@@ -704,7 +780,7 @@ Schur build_schur(const Lq &lq) {
   // Stair preconditioner: diagonal blocks D_k^-1 (D_0^-1 = Q_0, D_{k+1}^-1 =
   // theta_k^-1), off-diagonal blocks -D_{k+1}^-1 phi_k D_k^-1.
   std::vector<double> Dinv((size_t)N * nx * nx, 0.0);
-  for (int i = 0; i < nx; ++i) Dinv[i * nx + i] = lq.Qh[i];
+  for (int i = 0; i < nx * nx; ++i) Dinv[i] = lq.Qf[i];   // (Q_0^-1)^-1
   for (int k = 1; k < N; ++k)
     if (!invert(&theta[(size_t)k * nx * nx], nx, &Dinv[(size_t)k * nx * nx])) s.ok = false;
   std::vector<double> t1((size_t)nx * nx), t2((size_t)nx * nx);
@@ -774,7 +850,7 @@ bool solve_riccati(const Lq &lq, double *dZ, double *lam) {
   std::vector<double> K((size_t)(N > 1 ? N - 1 : 0) * nu * nx, 0.0), d((size_t)(N > 1 ? N - 1 : 0) * nu, 0.0);
   double *PN = &P[(size_t)(N - 1) * nx * nx];
   for (int i = 0; i < nx; ++i) {
-    PN[i * nx + i] = lq.Qh[(size_t)(N - 1) * nx + i];
+    for (int j = 0; j < nx; ++j) PN[i * nx + j] = lq.Qf[((size_t)(N - 1) * nx + i) * nx + j];
     p[(size_t)(N - 1) * nx + i] = lq.q[(size_t)(N - 1) * nx + i];
   }
   std::vector<double> PA((size_t)nx * nx), PB((size_t)nx * nu), H((size_t)nu * nu), Gux((size_t)nu * nx),
@@ -847,7 +923,7 @@ bool solve_riccati(const Lq &lq, double *dZ, double *lam) {
     }
     for (int i = 0; i < nx; ++i) {
       for (int j = 0; j < nx; ++j) {
-        double t = (i == j) ? lq.Qh[(size_t)k * nx + i] : 0.0;
+        double t = lq.Qf[((size_t)k * nx + i) * nx + j];
         for (int m = 0; m < nu; ++m) t += Kk[m * nx + i] * lq.Rh[m] * Kk[m * nx + j];
         for (int m = 0; m < nx; ++m) t += Acl[m * nx + i] * PAcl[m * nx + j];
         Pk[i * nx + j] = t;
@@ -906,6 +982,13 @@ bool cost_and_defect(const orc_robot &rb, const orc_problem &pr, const double *x
     for (int i = 0; i < nx; ++i) {
       const double d = X[(size_t)k * nx + i] - goal_state(qgoal, n, i);
       cost += 0.5 * W[i] * d * d;
+    }
+    if (has_task(pr)) {
+      const double *We = (k < N - 1) ? pr.Wee : pr.WeeN;
+      const V3<double> p = tip_position<double>(rb, X + (size_t)k * nx);
+      const double d[3] = {p.x - pr.pref[(size_t)k * 3 + 0], p.y - pr.pref[(size_t)k * 3 + 1],
+                           p.z - pr.pref[(size_t)k * 3 + 2]};
+      for (int c = 0; c < 3; ++c) cost += 0.5 * We[c] * d[c] * d[c];
     }
     if (k < N - 1)
       for (int i = 0; i < nu; ++i) cost += 0.5 * pr.Rd[i] * U[(size_t)k * nu + i] * U[(size_t)k * nu + i];
@@ -982,6 +1065,22 @@ int orc_lq(const orc_robot *rb, const orc_problem *pr, double rho, const double 
   std::memcpy(q, lq.q.data(), sizeof(double) * lq.q.size());
   std::memcpy(r, lq.r.data(), sizeof(double) * lq.r.size());
   std::memcpy(c0, lq.c0.data(), sizeof(double) * lq.c0.size());
+  return lq.ok ? 0 : -1;
+}
+
+// Tip position p[3] (base frame) and Jacobian J[3][n] at joint angles q.
+int orc_tip(const orc_robot *rb, const double *q, double *p, double *J) {
+  if (!rb || !q || !p || !J || rb->model != 0) return -1;
+  tip_jacobian(*rb, q, p, J);
+  return 0;
+}
+
+// State Hessian blocks Q_k [N][nx][nx] of the QP at (X, U) (diagonal Q plus rho,
+// plus the Gauss-Newton tip tracking term when the problem has one).
+int orc_lq_hessian(const orc_robot *rb, const orc_problem *pr, double rho, const double *xs, const double *qgoal,
+                   const double *X, const double *U, double *Qf) {
+  Lq lq = build_lq(*rb, *pr, rho, xs, qgoal, X, U);
+  std::copy(lq.Qf.begin(), lq.Qf.end(), Qf);
   return lq.ok ? 0 : -1;
 }
 
@@ -1066,7 +1165,9 @@ int orc_kkt_from_lq(int nx, int nu, int N, const double *A, const double *B, con
   lq.e.assign(e, e + (size_t)(N - 1) * nx);
   lq.q.assign(q, q + (size_t)N * nx);
   lq.r.assign(r, r + (size_t)(N - 1) * nu);
-  lq.Qh.assign(Qh, Qh + (size_t)N * nx);
+  lq.Qf.assign((size_t)N * nx * nx, 0.0);
+  for (int k = 0; k < N; ++k)
+    for (int i = 0; i < nx; ++i) lq.Qf[((size_t)k * nx + i) * nx + i] = Qh[(size_t)k * nx + i];
   lq.Rh.assign(Rh, Rh + nu);
   lq.c0.assign(c0, c0 + nx);
   const bool ok = (mode == 2) ? solve_riccati(lq, dZ, lam) : solve_kkt_dense(lq, dZ, lam);

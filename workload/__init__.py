@@ -49,6 +49,10 @@ class Solve:
     gravity: float = GRAVITY
     spring_k: float = 0.0
     fext: tuple = (0.0, 0.0, 0.0)   # external force on the tip of the last link (base frame), N
+    # Task-space tracking of the tip (None: joint-space costs only).
+    Wee: np.ndarray | None = None   # [3] stage weights on the tip position error
+    WeeN: np.ndarray | None = None  # [3] terminal weights
+    pref: np.ndarray | None = None  # [N, 3] reference tip positions, base frame
 
     @property
     def nx(self) -> int:
@@ -98,6 +102,50 @@ def uneven_batch(seed: int, M: int = 128, dofs=(3, 6, 7), horizons=(16, 32, 64, 
         N = int(g.choice(horizons))
         out.append(chain_solve(seed, i, n=n, N=N, dt=dt))
     return out
+
+
+# Task-space (figure-8) tracking weights: a light joint-posture and velocity
+# regulariser, the tip position weighted per axis.
+TS_Q_POS, TS_Q_VEL, TS_QN_VEL = 1e-1, 1e-1, 1.0
+TS_W_STAGE, TS_W_TERMINAL = 1e2, 1e3
+TS_PERIOD_S = 2.0
+
+
+def figure8_solve(seed: int, i: int, n: int = 7, N: int = 32, dt: float = DEFAULT_DT, t0: float = 0.0) -> Solve:
+    """Solve ``i`` of the chain family tracking a figure-8 with the tip.
+
+    The chain, start state and posture goal are those of :func:`chain_solve`.
+    Extra draws from ``PCG64(SeedSequence([seed, i, 4]))``: the azimuth of the
+    figure's centre U[-pi, pi] and its phase U[0, 2 pi]. With reach L (the sum
+    of the link lengths), the centre sits at horizontal distance 0.35 L and
+    height 0.45 L; the figure (a lemniscate of Gerono, amplitude 0.1 L, period
+    2 s) lies in the vertical plane through the centre, tangent to the circle
+    around the base:  pref(t) = c + 0.1 L (sin th e_t + sin th cos th e_z),
+    th = 2 pi t / T + phase, t = t0 + k dt.  Weights: Q = 1e-1 on angles (towards
+    the posture goal) and 1e-1 on velocities, Q_N = 1e-1 / 1, R = 1e-3, tip
+    weights 1e2 per axis at every stage and 1e3 at the last knot.
+    """
+    s = chain_solve(seed, i, n=n, N=N, dt=dt)
+    g = _rng(seed, i, 4)
+    az = g.uniform(-np.pi, np.pi)
+    phase = g.uniform(0.0, 2.0 * np.pi)
+    L = float(np.sum(s.links[:, 0]))
+    c = np.array([0.35 * L * np.cos(az), 0.35 * L * np.sin(az), 0.45 * L])
+    e_t = np.array([-np.sin(az), np.cos(az), 0.0])
+    e_z = np.array([0.0, 0.0, 1.0])
+    th = 2.0 * np.pi * (t0 + dt * np.arange(N)) / TS_PERIOD_S + phase
+    a = 0.1 * L
+    s.pref = c + a * (np.sin(th)[:, None] * e_t + (np.sin(th) * np.cos(th))[:, None] * e_z)
+    s.Qd = np.concatenate([np.full(n, TS_Q_POS), np.full(n, TS_Q_VEL)])
+    s.QNd = np.concatenate([np.full(n, TS_Q_POS), np.full(n, TS_QN_VEL)])
+    s.Wee = np.full(3, TS_W_STAGE)
+    s.WeeN = np.full(3, TS_W_TERMINAL)
+    return s
+
+
+def figure8_batch(seed: int, M: int, n: int = 7, N: int = 32, dt: float = DEFAULT_DT) -> list[Solve]:
+    """``M`` seeded chains tracking figure-8s with the tip."""
+    return [figure8_solve(seed, i, n=n, N=N, dt=dt) for i in range(M)]
 
 
 def double_integrator_solve(seed: int, i: int, n: int = 3, N: int = 8, dt: float = 0.05,
