@@ -79,6 +79,16 @@ typedef struct {
  * One problem of Eq. (1): horizon, Euler time step h and the diagonal tracking
  * weights Q (stages 0..N-2), R and Q_N (knot N-1). The tracked state is
  * [q_goal; 0]. Host memory, copied at create time.
+ *
+ * Optional task-space term (the end-effector tracking of the paper's
+ * experiments, Sec. IV): with Wee_diag and WeeN_diag both non-NULL, knot k
+ * also costs 1/2 (p(q_k) - pref_k)^T diag(W) (p(q_k) - pref_k), p the position
+ * of the tip of the last link in the base frame, W = Wee_diag for k < N-1 and
+ * WeeN_diag at the last knot, pref set with gato_set_tip_reference (zero until
+ * then). The QP uses the exact gradient and the Gauss-Newton Hessian J^T W J
+ * of this term, so each Q_k gets a dense joint block. Serial chains only, at
+ * most 2 knots per lane group (N <= 64 for 6-7 DoF, 128 for 3 DoF), grouped
+ * dispatch only. Both NULL: no such term (zero-initialise the struct).
  */
 typedef struct {
   int N;               /* knot points, 2..GATO_MAX_KNOTS */
@@ -86,6 +96,8 @@ typedef struct {
   const double *Q_diag;  /* [2 n_dof], > 0 */
   const double *R_diag;  /* [n_dof], > 0 */
   const double *QN_diag; /* [2 n_dof], > 0 */
+  const double *Wee_diag;  /* [3], >= 0, or NULL */
+  const double *WeeN_diag; /* [3], >= 0, or NULL */
 } gato_problem;
 
 /*
@@ -114,7 +126,8 @@ typedef struct {
                           Hessian; the initial per-solve value (see gato_set_rho) */
   int schur_fp64;      /* 1: Schur complement, PCG vectors and dot products in
                           FP64; 0: all FP32 (see the toggles below) */
-  int warm_lambda;     /* 1: PCG starts from the solve's previous multipliers */
+  int warm_lambda;     /* 1: PCG starts from the solve's previous multipliers (previous SQP
+                          iteration, or the previous call's last); 0: from zero */
   int fp64_block_inv;  /* schur_fp64 = 0 only: FP64 diagonal-block inversion */
   int fp64_dot;        /* schur_fp64 = 0 only: FP64 PCG inner-product accumulation */
   int rho_adapt;       /* 1: after each SQP iteration a solve's rho is divided by 3
@@ -345,6 +358,16 @@ int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, 
  * Synchronous. Errors: GATO_EINVAL, GATO_EDEVICE.
  */
 int gato_set_external_force(gato_batch *b, const double *h_f);
+
+/*
+ * Reference tip positions of the task-space term: d_pref [M][N_max][3]
+ * (device, base frame, knot k of solve i at (i N_max + k) 3) is copied into
+ * the batch on its stream, so the caller may reuse the buffer once the stream
+ * passes the copy. Read by every later solve, step and serving launch (not
+ * shifted with the warm start). Errors: GATO_EINVAL (NULL arguments, or a
+ * batch without task-space solves), GATO_EDEVICE.
+ */
+int gato_set_tip_reference(gato_batch *b, const float *d_pref);
 
 /*
  * Per-solve damping rho (Sec. IV-C samples rho across the batch): h_rho[M]

@@ -38,7 +38,8 @@ class _Robot(C.Structure):
 
 class _Problem(C.Structure):
     _fields_ = [("N", C.c_int), ("dt", C.c_double), ("Q_diag", C.POINTER(C.c_double)),
-                ("R_diag", C.POINTER(C.c_double)), ("QN_diag", C.POINTER(C.c_double))]
+                ("R_diag", C.POINTER(C.c_double)), ("QN_diag", C.POINTER(C.c_double)),
+                ("Wee_diag", C.POINTER(C.c_double)), ("WeeN_diag", C.POINTER(C.c_double))]
 
 
 class _Params(C.Structure):
@@ -69,7 +70,8 @@ EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "
            "gato_set_external_force", "gato_set_dispatch",
            "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_set_rho", "gato_get_rho",
            "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
-           "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_serve_run", "gato_last_error")
+           "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_serve_run", "gato_set_tip_reference",
+           "gato_last_error")
 
 _lib = None
 
@@ -115,6 +117,7 @@ def lib() -> C.CDLL:
         L.gato_serve_ctx_query.argtypes = [vp]
         L.gato_serve_ctx_trajectories.argtypes = [vp, vp, vp]
         L.gato_get_rho.argtypes = [vp, C.POINTER(C.c_double)]
+        L.gato_set_tip_reference.argtypes = [vp, vp]
         L.gato_serve_run.argtypes = [vp, ip, ip, ip, vp, vp, vp, vp, ip, C.c_size_t, vp, vp, vp, vp, C.POINTER(ip)]
         L.gato_buckets.argtypes = [vp, C.POINTER(Bucket), ip, C.POINTER(ip)]
         L.gato_set_mapping.argtypes = [vp, ip, ip, ip]
@@ -178,6 +181,8 @@ class Problem:
     Q_diag: np.ndarray
     R_diag: np.ndarray
     QN_diag: np.ndarray
+    Wee_diag: np.ndarray | None = None    # [3] tip tracking weights (stages), or None
+    WeeN_diag: np.ndarray | None = None   # [3] at the last knot
 
 
 def rbd_flops(n_dof: int):
@@ -248,10 +253,18 @@ class Batch:
             link = _f64(r.link if r.link is not None else np.zeros((r.n_dof, 5))).reshape(-1)
             Q, R, QN = _f64(p.Q_diag), _f64(p.R_diag), _f64(p.QN_diag)
             keep += [link, Q, R, QN]
+            We = WeN = None
+            if getattr(p, "Wee_diag", None) is not None:
+                We, WeN = _f64(p.Wee_diag).reshape(3), _f64(p.WeeN_diag).reshape(3)
+                keep += [We, WeN]
             rob[i] = _Robot(int(r.model), int(r.n_dof), link.ctypes.data_as(C.POINTER(C.c_double)),
                             float(r.gravity), float(r.spring_k))
             prob[i] = _Problem(int(p.N), float(p.dt), Q.ctypes.data_as(C.POINTER(C.c_double)),
                                R.ctypes.data_as(C.POINTER(C.c_double)), QN.ctypes.data_as(C.POINTER(C.c_double)))
+            if We is not None:
+                prob[i].Wee_diag = We.ctypes.data_as(C.POINTER(C.c_double))
+                prob[i].WeeN_diag = WeN.ctypes.data_as(C.POINTER(C.c_double))
+        self.task = any(getattr(p, "Wee_diag", None) is not None for p in problems)
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         handle = C.c_void_p()
         prm = self.params.c()
@@ -267,12 +280,26 @@ class Batch:
     def from_solves(cls, solves, params: Params | None = None, stream=None) -> "Batch":
         """Builds a batch from objects with the fields of workload.Solve."""
         robots = [Robot(s.n, s.links, s.model, s.gravity, s.spring_k) for s in solves]
-        problems = [Problem(s.N, s.dt, s.Qd, s.Rd, s.QNd) for s in solves]
+        problems = [Problem(s.N, s.dt, s.Qd, s.Rd, s.QNd, getattr(s, "Wee", None), getattr(s, "WeeN", None))
+                    for s in solves]
         b = cls(robots, problems, params, stream)
         fe = np.array([getattr(s, "fext", (0.0, 0.0, 0.0)) for s in solves], np.float64)
         if np.any(fe != 0.0):
             b.set_external_force(fe)
+        if b.task:
+            import torch
+            pref = np.zeros((b.M, b.N_max, 3), np.float32)
+            for i, s in enumerate(solves):
+                if getattr(s, "pref", None) is not None:
+                    pref[i, :s.N] = s.pref
+            b.set_tip_reference(torch.from_numpy(pref).cuda())
         return b
+
+    def set_tip_reference(self, pref):
+        """gato_set_tip_reference: reference tip positions, float32 cuda tensor [M, N_max, 3]."""
+        self._chk(pref, (self.M, self.N_max, 3))
+        _check(lib().gato_set_tip_reference(self._h, _dptr(pref)))
+        self._pref = pref          # keep it alive until the stream has copied it
 
     def close(self):
         if getattr(self, "_h", None):

@@ -23,6 +23,7 @@ hipError_t launch_sqp_mixed_f32(int grid, const KArgs &a, hipStream_t s);
 hipError_t launch_sqp_mixed_f64(int grid, const KArgs &a, hipStream_t s);
 
 hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s) {
+  if (a.pref) return launch_sqp_task(nd, kpt, f64, grid, a, s);   // a batch with task-space solves
   switch (nd) {
     case 3: return launch_sqp_n3(kpt, f64, grid, a, s);
     case 6: return launch_sqp_n6(kpt, f64, grid, a, s);
@@ -101,6 +102,8 @@ struct gato_batch {
   size_t stats_cap = 0;
   unsigned *d_plant_status = nullptr;  // [M], used when the caller passes none
   double *d_rho = nullptr;             // [M] per-solve damping
+  bool task = false;                   // some solve has a tip tracking term (task-space kernels)
+  float *d_pref = nullptr;             // [M][N_max][3] reference tip positions
   // Launch groups: solves of one (n, kpt) shape, longest horizon first.
   struct Group {
     int n, kpt, count;
@@ -268,12 +271,33 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
       d.Wr[j] = (float)q.R_diag[j];
       d.Ri[j] = 1.0 / q.R_diag[j];
     }
+    if ((q.Wee_diag == nullptr) != (q.WeeN_diag == nullptr))
+      return fail(GATO_EINVAL, who + "Wee_diag and WeeN_diag must both be set or both be NULL");
+    if (q.Wee_diag) {
+      if (r.model != GATO_MODEL_SERIAL_CHAIN) return fail(GATO_EINVAL, who + "tip tracking needs a serial chain");
+      for (int c = 0; c < 3; ++c) {
+        if (!(std::isfinite(q.Wee_diag[c]) && q.Wee_diag[c] >= 0.0) ||
+            !(std::isfinite(q.WeeN_diag[c]) && q.WeeN_diag[c] >= 0.0))
+          return fail(GATO_EINVAL, who + "tip weights must be finite and >= 0");
+        d.We[c] = (float)q.Wee_diag[c];
+        d.WeN[c] = (float)q.WeeN_diag[c];
+      }
+      d.task = 1;
+    }
     n_max = std::max(n_max, n);
     N_max = std::max(N_max, q.N);
   }
 
+  bool task = false;
+  for (const auto &d : desc) task = task || d.task;
+  if (task)
+    for (int i = 0; i < M; ++i)
+      if (desc[i].kpt > gato::kTaskKptMax)
+        return fail(GATO_EUNSUPPORTED, "solve " + std::to_string(i) +
+                                           ": batches with tip tracking are compiled for N <= 64 (6-7 DoF)");
   gato_batch *b = new gato_batch();
   b->M = M;
+  b->task = task;
   b->n_max = n_max;
   b->N_max = N_max;
   b->p = prm;
@@ -318,6 +342,12 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(plant status)"); }
   e = hipMalloc((void **)&b->d_rho, M * sizeof(double));
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(rho)"); }
+  if (task) {
+    const size_t pb = (size_t)M * N_max * 3 * sizeof(float);
+    e = hipMalloc((void **)&b->d_pref, pb);
+    if (e == hipSuccess) e = hipMemset(b->d_pref, 0, pb);
+    if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(tip reference)"); }
+  }
   {
     const std::vector<double> r0(M, prm.rho);
     e = hipMemcpy(b->d_rho, r0.data(), M * sizeof(double), hipMemcpyHostToDevice);
@@ -349,6 +379,7 @@ void gato_batch_destroy(gato_batch *b) {
   if (b->d_stats) (void)hipFree(b->d_stats);
   if (b->d_plant_status) (void)hipFree(b->d_plant_status);
   if (b->d_rho) (void)hipFree(b->d_rho);
+  if (b->d_pref) (void)hipFree(b->d_pref);
   delete b;
 }
 
@@ -384,10 +415,13 @@ gato::KArgs base_args(gato_batch *b) {
   a.rho_adapt = b->p.rho_adapt;
   a.fp64_inv = b->p.fp64_block_inv;
   a.fp64_dot = b->p.fp64_dot;
+  a.pref = b->task ? b->d_pref : nullptr;
   return a;
 }
 
+// (The mixed-shape kernel has no task-space variant.)
 bool use_mixed(const gato_batch *b) {
+  if (b->task) return false;
   return b->dispatch == GATO_DISPATCH_MIXED || (b->dispatch == GATO_DISPATCH_AUTO && b->groups.size() > 1);
 }
 
@@ -521,6 +555,7 @@ int gato_debug_lq(gato_batch *b, const float *d_xs, const float *d_goal, const f
   int rc = check_io(b, d_xs, d_goal, d_X, d_U);
   if (rc) return rc;
   if (!d_A || !d_B || !d_e) return fail(GATO_EINVAL, "output buffers must not be NULL");
+  if (b->task) return fail(GATO_EUNSUPPORTED, "stage entry points take joint-space batches only");
   gato::KArgs a = base_args(b);
   a.xs = d_xs;
   a.goal = d_goal;
@@ -540,6 +575,7 @@ int gato_debug_kkt(gato_batch *b, const float *d_A, const float *d_B, const floa
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (!d_A || !d_B || !d_e || !d_q || !d_r || !d_c0 || !d_dX || !d_dU || !d_lambda)
     return fail(GATO_EINVAL, "buffers must not be NULL");
+  if (b->task) return fail(GATO_EUNSUPPORTED, "stage entry points take joint-space batches only");
   gato::KArgs a = base_args(b);
   a.iters = 1;
   a.mode = gato::kModeKkt;
@@ -596,6 +632,8 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
   a.Xout = d_Xout;
   a.Uout = d_Uout;
   hipStream_t st = hip_stream ? (hipStream_t)hip_stream : b->stream;
+  if (b->task && b->groups.size() != 1)
+    return fail(GATO_EUNSUPPORTED, "serving launches of tip tracking batches need one (n, kpt) shape");
   hipError_t e = b->groups.size() == 1
                      ? gato::launch_sqp(b->groups[0].n, b->groups[0].kpt, b->p.schur_fp64 != 0, n_req, a, st)
                      : launch_mixed(b, n_req, a, st);
@@ -894,6 +932,15 @@ int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, 
   return GATO_OK;
 }
 
+int gato_set_tip_reference(gato_batch *b, const float *d_pref) {
+  if (!b || !d_pref) return fail(GATO_EINVAL, "batch and reference must not be NULL");
+  if (!b->task) return fail(GATO_EINVAL, "the batch has no tip tracking term");
+  const size_t pb = (size_t)b->M * b->N_max * 3 * sizeof(float);
+  hipError_t e = hipMemcpyAsync(b->d_pref, d_pref, pb, hipMemcpyDeviceToDevice, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(tip reference)");
+  return GATO_OK;
+}
+
 int gato_set_external_force(gato_batch *b, const double *h_f) {
   if (!b || !h_f) return fail(GATO_EINVAL, "batch and forces must not be NULL");
   for (int i = 0; i < 3 * b->M; ++i)
@@ -936,6 +983,8 @@ int gato_set_dispatch(gato_batch *b, int mode) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (mode != GATO_DISPATCH_AUTO && mode != GATO_DISPATCH_GROUPED && mode != GATO_DISPATCH_MIXED)
     return fail(GATO_EINVAL, "unknown dispatch mode");
+  if (b->task && mode == GATO_DISPATCH_MIXED)
+    return fail(GATO_EUNSUPPORTED, "the mixed-shape kernel has no tip tracking variant");
   b->dispatch = mode;
   ++b->mapping_gen;
   return GATO_OK;
@@ -961,6 +1010,8 @@ int gato_buckets(const gato_batch *b, gato_bucket *out, int cap, int *n_out) {
 int gato_set_mapping(gato_batch *b, int n_dof, int N, int kpt) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (!kpt_allowed(n_dof, N, kpt)) return fail(GATO_EINVAL, "kpt must be 1, 2 or 4 and cover N");
+  if (b->task && kpt > gato::kTaskKptMax)
+    return fail(GATO_EUNSUPPORTED, "tip tracking kernels are compiled for kpt 1 and 2");
   bool any = false;
   for (auto &d : b->desc)
     if (d.n == n_dof && d.N == N) {
@@ -978,6 +1029,7 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
   int rc = check_io(b, d_xs, d_goal, d_X, d_U);
   if (rc) return rc;
   if (n_iters < 1 || reps < 1) return fail(GATO_EINVAL, "n_iters and reps must be >= 1");
+  if (b->task) return fail(GATO_EUNSUPPORTED, "the autotuner times the mixed-shape kernel (no tip tracking variant)");
   hipStream_t s = b->stream;
   hipError_t e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "synchronize");

@@ -25,6 +25,9 @@ struct SolveDesc {
   double Qd[16];      // diagonal of Q (the kernel forms 1 / (Q + rho) per iteration)
   double QNd[16];     // diagonal of Q_N
   double Ri[8];       // 1 / R
+  float We[3], WeN[3];  // tip tracking weights (stages, last knot); task-space solves only
+  int task;             // the solve has a tip tracking term
+  int pad1;
   int64_t ws_off;     // byte offset of this solve's workspace
   int64_t offA, offB, offD, offT;  // byte offsets inside it: A_k, B_k and the inverse
                                    // diagonal blocks (float); Schur diagonal rows (double)
@@ -58,6 +61,7 @@ struct KArgs {
   int M;                     // solves in the batch: solve indices from `order` outside 0..M-1 are skipped
   int sid_base;              // solve index of blockIdx.x == 0
   const int *order;          // optional block -> solve map (longest first), or null
+  const float *pref;         // [M][N_max][3] reference tip positions (task-space kernels)
   // Stage entry points.
   const float *inA, *inB, *ine, *inq, *inr, *inc0;
   float *outA, *outB, *oute;

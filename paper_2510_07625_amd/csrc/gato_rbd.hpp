@@ -237,6 +237,27 @@ __host__ __device__ inline void rnea(const Chain &ch, const T *q, const T *cq, c
 }
 
 // ---------------------------------------------------------------------------
+// Position of the tip (Lt along +z of the last link) in the base frame: the
+// offset is carried from the last frame back to the base, one joint rotation
+// and one link offset at a time. With T a dual number seeded on q_j it also
+// gives column j of the tip Jacobian.
+// ---------------------------------------------------------------------------
+template <int ND, class T>
+__host__ __device__ inline void tip_position(const Chain &ch, const T *q, T *p) {
+  p[0] = cst<T>(0.f);
+  p[1] = cst<T>(0.f);
+  p[2] = cst<T>(ch.Lt);
+#pragma unroll
+  for (int i = ND - 1; i >= 0; --i) {
+    T s, c;
+    sin_cos(q[i], &s, &c);
+    if (i & 1) rot_R<true>(c, s, p[0], p[1], p[2]);
+    else rot_R<false>(c, s, p[0], p[1], p[2]);
+    if (i > 0) p[2] = p[2] + cst<T>(ch.Lp[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Joint-space inertia by composite rigid bodies. Each composite is kept as mass
 // m, first moment h = m c and rotational inertia I (about the joint, symmetric,
 // stored xx yy zz xy xz yz) in its own frame. Only the lower triangle is used

@@ -19,13 +19,26 @@
 //      arrangement: the inner products of an iteration are reduced together
 //      and share a barrier with the vector exchange, so an iteration needs two
 //      workgroup barriers. Rows of S~ and P stay in registers; vectors are
-//      exchanged through LDS.
+//      exchanged through LDS. (The all-FP32 and task-space variants run the
+//      standard arrangement.)
 //   5. Step dZ = -G^-1 (g - C^T lambda) (Eq. (4)).
 //   6. Line search (Eqs. (3), (7)): lane (alpha, knot) evaluates one trial
 //      knot; a fixed-order reduction gives each candidate's merit.
 // The Schur rows, gamma~, the block inverses, the PCG vectors and its inner
 // products use Real (double; float for the all-FP32 variant). Dynamics, line
 // search and the preconditioner blocks use float.
+//
+// Task-space variant (TS): a tip tracking term 1/2 |p(q_k) - pref_k|^2_W per
+// knot makes the joint block of Q_k dense, H_k = diag(Q_q + rho) + J^T W J
+// (Gauss-Newton). Phase 1 then also factors H_k = L_k L_k^T and rewrites the
+// QP in the variables y_k = T_k^-1 x_k, T_k = blkdiag(L_k^-T, I), whose state
+// Hessian is diagonal again: A_k -> T_{k+1}^-1 A_k T_k, e_k -> T_{k+1}^-1 e_k,
+// q_k -> T_k^T q_k, c_0 -> T_0^-1 c_0 (B_k is unchanged, its joint rows are
+// zero). The Schur complement of the rewritten QP is congruent to that of
+// Eq. (5) under blkdiag(T_k^-1), and so is the stair preconditioner of
+// Eq. (6), so PCG takes the same iterates (multipliers scaled by T_k^T) and
+// the same stopping value as on the dense-Q_k system; phases 2-4 run
+// unchanged, and phase 5 maps the step and the multipliers back.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -91,6 +104,32 @@ struct Smem {
   float Dinv[LB][NX * NX]; // inverse diagonal blocks of S~
   float Poff[LB][NX * NX]; // P_{k+1,k}
 };
+
+// LDS of the task-space variant, placed after Smem.
+template <int ND, int KPT>
+struct TsSmem {
+  static constexpr int KN = KPT * Shape<ND>::SLOTS;
+  static constexpr int NL = Shape<ND>::NL;
+  double Lc[KN][NL];     // Cholesky factor L_k of the joint block H_k (packed rows)
+  double Li[KN][NL];     // L_k^-1 (packed rows)
+  double tq[KN][8];      // joint-block vectors exchanged inside a lane group
+  double mt[KN];         // tip tracking cost of each knot at the current iterate
+  float Jt[KN][3][8];    // tip Jacobian J_k (column per joint)
+  float pr[KN][4];       // reference tip positions
+  float pe[KN][4];       // p(q_k) - pref_k at the current iterate
+};
+
+template <int ND, int KPT, class Real>
+constexpr size_t ts_offset() {
+  return (sizeof(Smem<ND, KPT, Real>) + 15) & ~(size_t)15;
+}
+template <int ND, int KPT, class Real, bool TS>
+constexpr size_t smem_bytes() {
+  return TS ? ts_offset<ND, KPT, Real>() + sizeof(TsSmem<ND, KPT>) : sizeof(Smem<ND, KPT, Real>);
+}
+
+// Packed lower-triangular storage, row i holding columns 0..i.
+__device__ __forceinline__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -186,13 +225,15 @@ __device__ __forceinline__ void block_sum(double (*red)[3][kBlock / 64], int &bu
   buf ^= 1;
 }
 
-template <int ND, int KPT, class Real>
+template <int ND, int KPT, class Real, bool TS = false>
 __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
   using Sh = Shape<ND>;
   constexpr int NX = Sh::NX, NU = Sh::NU, G = Sh::G, SLOTS = Sh::SLOTS;
   constexpr bool kLds = BlockStore<ND, KPT>::kLds;
   using SM = Smem<ND, KPT, Real>;
   SM &sm = *reinterpret_cast<SM *>(smem_raw);
+  // Only dereferenced by the task-space variant, whose LDS holds it.
+  TsSmem<ND, KPT> &ts = *reinterpret_cast<TsSmem<ND, KPT> *>(smem_raw + ts_offset<ND, KPT, Real>());
   const SolveDesc &D = a.desc[sid];
   const Chain &ch = D.chain;
   const int tid = threadIdx.x;
@@ -248,6 +289,13 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     sm.xs[tid] = in ? a.xs[(size_t)rid * a.nx_max + tid] : 0.f;
     sm.xg[tid] = (in && tid < ND) ? a.goal[(size_t)rid * a.nu_max + tid] : 0.f;
   }
+  if constexpr (TS) {
+    // Reference tip positions of this request's horizon (not shifted).
+    for (int t = tid; t < N * 4; t += kBlock) {
+      const int k = t / 4, c = t % 4;
+      ts.pr[k][c] = c < 3 ? a.pref[((size_t)sid * a.N_max + k) * 3 + c] : 0.f;
+    }
+  }
   if (tid == 0) {
     sm.bad[0] = 0;
     sm.bad[1] = 0;
@@ -277,10 +325,17 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // where they would stay live across every phase and spill.
     int lane = lane0, slot = slot0;
     asm volatile("" : "+v"(lane), "+v"(slot));
+    // Without warm starts every PCG solve starts from zero.
+    if (!a.warm && it > 0) {
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) lam[p] = (Real)0;
+    }
     // Q^-1 and Q_N^-1 for this iteration's rho (first read after phase 1's barrier).
+    // (Task-space variant: the joint block of the rewritten Q_k is the identity.)
     if (tid < G) {
-      sm.Qi[tid] = tid < NX ? 1.0 / (D.Qd[tid] + rho) : 0.0;
-      sm.Qni[tid] = tid < NX ? 1.0 / (D.QNd[tid] + rho) : 0.0;
+      const bool unit = TS && tid < ND;
+      sm.Qi[tid] = tid < NX ? (unit ? 1.0 : 1.0 / (D.Qd[tid] + rho)) : 0.0;
+      sm.Qni[tid] = tid < NX ? (unit ? 1.0 : 1.0 / (D.QNd[tid] + rho)) : 0.0;
     }
     int &bad_flag = sm.bad[it & 1];
     unsigned long long *clk = (a.clk && tid == 0) ? a.clk + ((size_t)sid * a.iters + it) * 8 : nullptr;
@@ -378,6 +433,82 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         }
         sm.mp0[N - 1] = (double)cost + (double)a.mu * (double)viol;
       }
+      if constexpr (TS) {
+        // Tip position and Jacobian at every knot (lane j: one dual-number pass
+        // seeded on q_j), then H_k = diag(Q_q + rho) + J^T W J, its Cholesky
+        // factor L_k (column by column, lane i holding row i) and L_k^-1
+        // (lane j forming column j by forward substitution).
+        for (int k = slot; k < N; k += SLOTS) {
+          const float *We = (k < N - 1) ? D.We : D.WeN;
+          const double *Qd = (k < N - 1) ? D.Qd : D.QNd;
+          if (lane < ND) {
+            dual<float> qv[ND], pt[3];
+#pragma unroll
+            for (int i = 0; i < ND; ++i) qv[i] = dual<float>{sm.X[k][i], i == lane ? 1.f : 0.f};
+            tip_position<ND>(ch, qv, pt);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ts.Jt[k][c][lane] = pt[c].d;
+            if (lane == 0) {
+              double tc = 0.0;
+#pragma unroll
+              for (int c = 0; c < 3; ++c) {
+                const float d = pt[c].v - ts.pr[k][c];
+                ts.pe[k][c] = d;
+                tc += 0.5 * (double)We[c] * (double)d * (double)d;
+              }
+              ts.mt[k] = tc;
+              if (!isfinite(tc)) bad_flag = 1;
+            }
+          }
+          wave_sync();
+          double hr[ND], lr[ND];
+#pragma unroll
+          for (int j = 0; j < ND; ++j) {
+            double t = (j == lane) ? Qd[j] + rho : 0.0;
+            if (lane < ND) {
+#pragma unroll
+              for (int c = 0; c < 3; ++c) t += (double)We[c] * (double)ts.Jt[k][c][lane] * (double)ts.Jt[k][c][j];
+            }
+            hr[j] = t;
+            lr[j] = 0.0;
+          }
+#pragma unroll
+          for (int c = 0; c < ND; ++c) {
+            if (lane == c) ts.tq[k][0] = hr[c];
+            wave_sync();
+            const double piv = ts.tq[k][0];
+            wave_sync();
+            if (lane == 0 && !(piv > 0.0)) bad_flag = 1;
+            const double dinv = 1.0 / sqrt(piv);
+            const double l = (lane >= c && lane < ND) ? hr[c] * dinv : 0.0;   // L[lane][c]
+            lr[c] = l;
+            if (lane < ND) ts.tq[k][lane] = l;
+            wave_sync();
+#pragma unroll
+            for (int j = c + 1; j < ND; ++j) hr[j] -= l * ts.tq[k][j];
+            wave_sync();
+          }
+          if (lane < ND) {
+#pragma unroll
+            for (int j = 0; j < ND; ++j)
+              if (j <= lane) ts.Lc[k][tri(lane, j)] = lr[j];
+          }
+          wave_sync();
+          if (lane < ND) {
+            // Column `lane` of L^-1: rows lane..ND-1 of the solution of L x = e_lane.
+            double x[ND];
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+              double t = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+              for (int m = 0; m < i; ++m)
+                if (m >= lane) t -= ts.Lc[k][tri(i, m)] * x[m];
+              x[i] = (i >= lane) ? t / ts.Lc[k][tri(i, i)] : 0.0;
+              if (i >= lane) ts.Li[k][tri(i, lane)] = x[i];
+            }
+          }
+        }
+      }
       if (a.mode == kModeLq) {
         __syncthreads();
         const size_t ao = (size_t)sid * (a.N_max - 1) * a.nx_max * a.nx_max;
@@ -423,6 +554,85 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // The other parity's flag was last read before the previous iteration's
     // closing barrier; clear it for the next iteration.
     if (tid == 0) sm.bad[(it + 1) & 1] = 0;
+    if constexpr (TS) {
+      for (int t = tid; t < N; t += kBlock) sm.mp0[t] += ts.mt[t];
+      // Rewrite the QP in y_k = T_k^-1 x_k, lane `lane` owning state row `lane`.
+      // The joint rows of A_k are [I, hI] by construction of the Euler step.
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) {
+        const int k = slot + p * SLOTS;
+        if (k < N) {
+          const double *Lk = ts.Lc[k];
+          const double *Lik = ts.Li[k];
+          const double *L1 = ts.Lc[k < N - 1 ? k + 1 : k];
+          if (k < N - 1 && lane < NX) {
+            float *Ar = Ablk(k) + lane * NX;
+            if (lane < ND) {
+              // Row `lane` of [L_{k+1}^T L_k^-T, h L_{k+1}^T].
+#pragma unroll
+              for (int c = 0; c < ND; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int m = 0; m <= c; ++m)
+                  if (m >= lane) t += L1[tri(m, lane)] * Lik[tri(c, m)];
+                Ar[c] = (float)t;
+                Ar[ND + c] = c >= lane ? (float)((double)h * L1[tri(c, lane)]) : 0.f;
+              }
+            } else {
+              // Velocity row: its joint columns times L_k^-T.
+              float ar[ND];
+#pragma unroll
+              for (int m = 0; m < ND; ++m) ar[m] = Ar[m];
+#pragma unroll
+              for (int c = 0; c < ND; ++c) {
+                double t = 0.0;
+#pragma unroll
+                for (int m = 0; m <= c; ++m) t += (double)ar[m] * Lik[tri(c, m)];
+                Ar[c] = (float)t;
+              }
+            }
+          }
+          double ev = 0.0, cv = 0.0;
+          if (lane < ND) {
+            const float *We = (k < N - 1) ? D.We : D.WeN;
+            double g = (double)sm.qg[k][lane];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g += (double)ts.Jt[k][c][lane] * (double)We[c] * (double)ts.pe[k][c];
+            ts.tq[k][lane] = g;
+#pragma unroll
+            for (int m = 0; m < ND; ++m) {
+              if (m >= lane) {
+                if (k < N - 1) ev += L1[tri(m, lane)] * (double)sm.e[k][m];
+                if (k == 0) cv += Lk[tri(m, lane)] * (double)sm.c0[m];
+              }
+            }
+          }
+          wave_sync();
+          if (lane < ND) {
+            double qh = 0.0;
+#pragma unroll
+            for (int m = 0; m < ND; ++m)
+              if (m <= lane) qh += Lik[tri(lane, m)] * ts.tq[k][m];
+            sm.qg[k][lane] = (float)qh;
+            if (k < N - 1) sm.e[k][lane] = (float)ev;
+            if (k == 0) sm.c0[lane] = (float)cv;
+          }
+          wave_sync();
+          // Warm-start multipliers: lambda^ = T_k^T lambda.
+          if (lane < ND) ts.tq[k][lane] = (double)lam[p];
+          wave_sync();
+          if (lane < ND) {
+            double t = 0.0;
+#pragma unroll
+            for (int m = 0; m < ND; ++m)
+              if (m <= lane) t += Lik[tri(lane, m)] * ts.tq[k][m];
+            lam[p] = (Real)t;
+          }
+          wave_sync();
+        }
+      }
+      __syncthreads();
+    }
     if (clk) clk[1] = wall_clock64();
 
     // ================= 2. Schur complement rows and diagonal-block inverses.
@@ -575,19 +785,23 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // keep it, and publish it so that knot k-1 can read its column.
     // Preconditioner blocks are stored in FP32 and applied in Real arithmetic:
     // a fixed linear operator, as the pipelined recurrences require.
-    // With kFactP (several knots per lane group, where registers are short)
-    // the off-diagonal blocks are not formed: P w = D^-1 (w - O D^-1 w), with O
-    // the off-diagonal blocks of S~ that the S~ product already holds.
-    constexpr bool kFactP = KPT > 1;
+    // With kFactP (several knots per lane group, where registers are short,
+    // and the task-space variant) the off-diagonal blocks are not formed:
+    // P w = D^-1 (w - O D^-1 w), with O the off-diagonal blocks of S~ that the
+    // S~ product already holds.
+    constexpr bool kFactP = KPT > 1 || TS;
     constexpr int KP = kFactP ? 1 : KPT;
     // (Held in FP32 and converted at use: Real-held rows would save the
-    // conversions but spill inside the PCG loop.)
-    using PT = float;
+    // conversions but spill inside the PCG loop. The task-space variant keeps
+    // D^-1 in Real: its S~ is far worse conditioned, P ~ S~^-1 with it, and
+    // rounding P to FP32 perturbs its smallest directions enough to slow PCG
+    // and leave a larger error at the same stopping value.)
+    using PT = std::conditional_t<TS, Real, float>;
     PT Pm[KP][NX], Pp[KP][NX], Pdf[KPT][NX];
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {
 #pragma unroll
-      for (int m = 0; m < NX; ++m) Pdf[p][m] = (PT)(float)Pd[p][m];
+      for (int m = 0; m < NX; ++m) Pdf[p][m] = TS ? (PT)Pd[p][m] : (PT)(float)Pd[p][m];
     }
     if constexpr (!kFactP) {
 #pragma unroll
@@ -816,11 +1030,14 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     const int max_it = a.pcg_max_iter > 0 ? a.pcg_max_iter : N * NX;
     Real gma = 0, stop = 0;
     int its = 0;
-    if constexpr (sizeof(Real) == 4) {
-      // All-FP32 variant: the standard (Hestenes-Stiefel) arrangement, whose
-      // directly computed p^T S~ p tolerates the rounding of FP32 vectors.
+    if constexpr (sizeof(Real) == 4 || TS) {
+      // All-FP32 and task-space variants: the standard (Hestenes-Stiefel)
+      // arrangement, whose directly computed p^T S~ p tolerates the rounding
+      // of FP32 vectors, and which on the worse-conditioned task-space systems
+      // is also the faster one (fewer live registers than the pipelined
+      // recurrences next to the variant's own state).
       // Acc: the accumulation type of the inner products (double when FP64
-      // accumulation is asked for; vectors and updates stay FP32).
+      // accumulation is asked for, and for FP64 vectors).
       auto run = [&](auto tag) {
         using Acc = decltype(tag);
         Acc sums[3] = {0, 0, 0};
@@ -870,7 +1087,8 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         gma = (g > stop_a) ? (Real)1 : (Real)0;
         stop = 0;
       };
-      if (a.fp64_dot) run(double{});
+      if constexpr (sizeof(Real) == 8) run(double{});
+      else if (a.fp64_dot) run(double{});
       else run(float{});
     } else {
       share_S(u);
@@ -982,6 +1200,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         const float dx = (float)(-qown[p] * sx);
         sm.dX[k][lane] = dx;
         if (!isfinite(dx)) bad_flag = 1;
+        if constexpr (TS) {
+          if (lane < ND) ts.tq[k][lane] = (double)(-qown[p] * sx);
+        }
         if (lane < NU && k < N - 1) {
           const float *B = Bblk(k);
           Real su = (Real)sm.rg[k][lane];
@@ -990,6 +1211,39 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           const float du = (float)(-(Real)D.Ri[lane] * su);
           sm.dU[k][lane] = du;
           if (!isfinite(du)) bad_flag = 1;
+        }
+      }
+    }
+    if constexpr (TS) {
+      // Back to x: dx_k = T_k dy_k (joint rows L_k^-T dy), lambda = T_k^-T lambda^.
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) {
+        const int k = slot + p * SLOTS;
+        if (k < N) {
+          const double *Lk = ts.Lc[k];
+          const double *Lik = ts.Li[k];
+          wave_sync();
+          double t = 0.0;
+          if (lane < ND) {
+#pragma unroll
+            for (int m = 0; m < ND; ++m)
+              if (m >= lane) t += Lik[tri(m, lane)] * ts.tq[k][m];
+          }
+          wave_sync();
+          if (lane < ND) {
+            const float dx = (float)t;
+            sm.dX[k][lane] = dx;
+            if (!isfinite(dx)) bad_flag = 1;
+            ts.tq[k][lane] = (double)lam[p];
+          }
+          wave_sync();
+          if (lane < ND) {
+            double l = 0.0;
+#pragma unroll
+            for (int m = 0; m < ND; ++m)
+              if (m <= lane) l += Lk[tri(lane, m)] * ts.tq[k][m];
+            lam[p] = (Real)l;
+          }
         }
       }
     }
@@ -1032,6 +1286,15 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         const float d0 = q[j] - sm.xg[j], d1 = qd[j] - sm.xg[ND + j];
         cost += 0.5f * D.Wq[j] * d0 * d0 + 0.5f * D.Wq[ND + j] * d1 * d1 + 0.5f * D.Wr[j] * uu[j] * uu[j];
       }
+      if constexpr (TS) {
+        float pt[3];
+        tip_position<ND>(ch, q, pt);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float d = pt[c] - ts.pr[k][c];
+          cost += 0.5f * D.We[c] * d * d;
+        }
+      }
       sm.mp[i][k] = (double)cost + (double)a.mu * (double)viol;
     }
     for (int i = tid; i < n_alpha; i += kBlock) {
@@ -1041,6 +1304,17 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         const float d = (sm.X[N - 1][j] + al * sm.dX[N - 1][j]) - sm.xg[j];
         cost += 0.5f * D.Wn[j] * d * d;
         viol += fabsf(sm.xs[j] - (sm.X[0][j] + al * sm.dX[0][j]));
+      }
+      if constexpr (TS) {
+        float q[ND], pt[3];
+#pragma unroll
+        for (int j = 0; j < ND; ++j) q[j] = sm.X[N - 1][j] + al * sm.dX[N - 1][j];
+        tip_position<ND>(ch, q, pt);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float d = pt[c] - ts.pr[N - 1][c];
+          cost += 0.5f * D.WeN[c] * d * d;
+        }
       }
       sm.mp[i][N - 1] = (double)cost + (double)a.mu * (double)viol;
     }
@@ -1111,12 +1385,13 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   }
 }
 
-template <int ND, int KPT, class Real>
+template <int ND, int KPT, class Real, bool TS = false>
 __global__ __launch_bounds__(kBlock) void sqp_kernel(KArgs a) {
-  __shared__ __align__(16) char smem[sizeof(Smem<ND, KPT, Real>)];
+  static_assert(smem_bytes<ND, KPT, Real, TS>() <= 160 * 1024, "LDS of one workgroup exceeds 160 KB");
+  __shared__ __align__(16) char smem[smem_bytes<ND, KPT, Real, TS>()];
   const int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
   if (sid < 0 || sid >= a.M) return;   // a caller-provided slot out of range: nothing to do
-  sqp_solve<ND, KPT, Real>(a, sid, smem);
+  sqp_solve<ND, KPT, Real, TS>(a, sid, smem);
 }
 
 // Mixed-shape kernel: every workgroup reads its solve's (n, kpt) and runs the
