@@ -10,13 +10,14 @@ timed loop). Inputs are synthetic and resident in HBM before timing starts.
 
 Also measured: the batch-size sweep M in {1, 16, 32, 64, 128, 256} for the
 batched launch and for the plain form (M one-solve launches in order), per-call
-latency p50/p99 from HIP events, the trajectory error against the FP64 oracle
-on sampled solves, the roofline position of the fused kernel, every precision
-setting (throughput, trajectory and KKT-solution error), the uneven batch
-(mixed DoF and horizon, per-shape against mixed-shape launch, autotuned,
-graph-captured), the closed-loop disturbance batch (RK4 plant, torque
-impulses, ticks replayed in the oracle), the served MPC loop at several
-Poisson arrival rates (Python and native request loops), and the oracle's CPU throughput on a bounded sample.
+latency p50/p99 from HIP events, the roofline position of the fused kernel,
+every precision setting, the uneven batch (mixed DoF and horizon, per-shape
+against mixed-shape launch, autotuned, graph-captured), the task-space batch
+(figure-8 tip tracking), the closed-loop disturbance batch (RK4 plant, torque
+impulses), the served MPC loop at several Poisson arrival rates (Python and
+native request loops), and the oracle's CPU throughput on a bounded sample
+(the only part that runs the oracle; the accuracy figures against it come
+from tests/accuracy_report.py).
 
 Prints one JSON line.
 """
@@ -155,79 +156,22 @@ def end_to_end_ms(g, torch, M, reps, params, seed=0):
     return ms
 
 
-def accuracy(g, res, params, sample=4):
-    """Max relative trajectory error of sampled solves, the oracle replaying the
-    GPU's accepted steps: against the exact FP64 oracle (dense KKT LU), and
-    against the FP64 oracle running the same method (Schur + PCG at the same
-    tolerance and warm start). The last figure, the FP64 method against the
-    exact oracle, is the truncation of the PCG tolerance itself."""
-    import oracle
-
-    def rel(X, U, ref):
-        return max(np.abs(X - ref.X).max() / np.abs(ref.X).max(), np.abs(U - ref.U).max() / np.abs(ref.U).max())
-
-    e_exact, e_pcg, e_method = [], [], []
-    idx = np.linspace(0, res["M"] - 1, min(sample, res["M"])).astype(int)
-    for i in idx:
-        s = res["solves"][i]
-        al = res["stats"][i]["alpha"].astype(np.float64)
-        common = dict(sqp_iters=params.sqp_iters, mu=params.mu, beta=params.beta, n_alpha=params.n_alpha)
-        exact = oracle.sqp(s, oracle.Params(kkt_mode=0, **common), alpha_replay=al)
-        meth = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=params.pcg_tol, warm_lambda=params.warm_lambda,
-                                           **common), alpha_replay=al)
-        e_exact.append(rel(res["X"][i], res["U"][i], exact))
-        e_pcg.append(rel(res["X"][i], res["U"][i], meth))
-        e_method.append(rel(meth.X, meth.U, exact))
-    return dict(max_rel_traj_err_vs_fp64_oracle=float(max(e_exact)),
-                max_rel_traj_err_vs_fp64_same_method=float(max(e_pcg)),
-                fp64_same_method_vs_exact=float(max(e_method)), solves_checked=[int(i) for i in idx])
-
-
 PRECISIONS = (dict(schur_fp64=1), dict(schur_fp64=0), dict(schur_fp64=0, fp64_block_inv=1),
               dict(schur_fp64=0, fp64_dot=1), dict(schur_fp64=0, fp64_block_inv=1, fp64_dot=1))
 
 
-def kkt_error(g, torch, params, n_solves=3, seed=12):
-    """KKT-solution error on identical QP data: the oracle's FP64 LQ data at the
-    initial guess, rounded once to FP32, solved by the GPU (Schur + PCG) and by
-    the oracle's dense LU; max over solves of ||dZ_gpu - dZ_ora||_inf / ||dZ_ora||_inf."""
-    import oracle
-    import workload as w
-    solves = [w.chain_solve(seed, i) for i in range(n_solves)]
-    n, N = solves[0].n, solves[0].N
-    nx, nu, M = 2 * n, n, n_solves
-    f32 = lambda a: np.asarray(a, np.float64).astype(np.float32)
-    data = [{k: f32(v) for k, v in oracle.lq(s, s.X0, s.U0).items()} for s in solves]
-    dev = lambda key, shape: torch.from_numpy(np.stack([d[key] for d in data]).reshape(shape)).cuda()
-    b = g.Batch.from_solves(solves, params)
-    dX, dU, _, its = (t.cpu().numpy() for t in b.debug_kkt(
-        dev("A", (M, N - 1, nx, nx)), dev("B", (M, N - 1, nx, nu)), dev("e", (M, N - 1, nx)),
-        dev("q", (M, N, nx)), dev("r", (M, N - 1, nu)), dev("c0", (M, nx))))
-    b.close()
-    worst = 0.0
-    for i, s in enumerate(solves):
-        d = {k: v.astype(np.float64) for k, v in data[i].items()}
-        Qh = np.array([(s.Qd if k < N - 1 else s.QNd) for k in range(N)])
-        rX, rU, _, _ = oracle.kkt_from_lq(d["A"], d["B"], d["e"], d["q"], d["r"], d["c0"], Qh, s.Rd)
-        ref = np.concatenate([rX.ravel(), rU.ravel()])
-        got = np.concatenate([dX[i].ravel(), dU[i].ravel()])
-        worst = max(worst, float(np.abs(got - ref).max() / np.abs(ref).max()))
-    return worst, int(its.max())
-
-
-def precision_report(g, torch, M, steps, pcg_tol, sample=2):
-    """Per precision setting: solves/s of the headline batch, trajectory error of
-    sampled solves against the FP64 oracle, KKT-solution error on identical QP data."""
+def precision_report(g, torch, M, steps, pcg_tol):
+    """Per precision setting: solves/s of the headline batch and its PCG work.
+    (The errors of each setting against the FP64 oracle come from
+    tests/accuracy_report.py.)"""
     out = []
     for kw in PRECISIONS:
         params = g.Params(sqp_iters=10, pcg_tol=pcg_tol, **kw)
         r = run_batched(g, torch, M, steps, 2, params)
         km = np.asarray(r["kernel_ms"])
-        acc = accuracy(g, r, params, sample=sample)
-        kkt, its = kkt_error(g, torch, g.Params(pcg_tol=pcg_tol, **kw))
         out.append(dict(precision=params.precision(), solves_per_s=M / (km.mean() * 1e-3),
-                        max_rel_traj_err=acc["max_rel_traj_err_vs_fp64_oracle"], kkt_rel_err=kkt,
-                        kkt_pcg_iters=its, pcg_iters_per_solve=float(r["stats"]["pcg_iters"].sum(axis=1).mean())))
+                        pcg_iters_per_solve=float(r["stats"]["pcg_iters"].sum(axis=1).mean()),
+                        status_bits_set=int((r["stats"]["status"] != 0).sum())))
         print(f"# precision {out[-1]}", file=sys.stderr, flush=True)
     return out
 
@@ -275,19 +219,56 @@ def uneven_report(g, torch, M=128, steps=3, seed=0):
     return out
 
 
-def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, oracle_ticks=150, seed=0,
-                       pcg_tol=1e-5):
+def task_space_report(g, torch, M=256, N=32, iters=10, steps=10, seed=0, pcg_tol=1e-5, pcg_max_iter=1000):
+    """Task-space batch: M 7-DoF chains tracking figure-8s with the tip (Gauss-
+    Newton tip cost, dense joint blocks of Q_k), N knots, `iters` SQP
+    iterations per call from the same initial guess, PCG tolerance `pcg_tol`
+    with its cap raised to `pcg_max_iter` (these systems need more than the
+    N nx iterations of exact arithmetic). Reports solves/s, the PCG work and
+    the tip's distance to the figure before and after."""
+    import workload as w
+    solves = w.figure8_batch(seed, M, N=N)
+    params = g.Params(sqp_iters=iters, pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter)
+    b = g.Batch.from_solves(solves, params)
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    X, U = X0.clone(), U0.clone()
+    st = b.stats_buffer(iters)
+    ms = []
+    for r in range(steps + 2):
+        X.copy_(X0)
+        U.copy_(U0)
+        b.reset_warm_start()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.step(xs, goal, X, U, iters, st)
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= 2:
+            ms.append(e0.elapsed_time(e1))
+    stats = g.Batch.decode_stats(st, M, iters)
+    pref = np.stack([s.pref for s in solves])
+    d0 = np.linalg.norm(b.tip_positions(X0).cpu().numpy() - pref, axis=2)
+    d1 = np.linalg.norm(b.tip_positions(X).cpu().numpy() - pref, axis=2)
+    b.close()
+    p50, p99 = _pcts(ms)
+    out = dict(M=M, N=N, sqp_iters=iters, pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter,
+               solves_per_s=M / (np.mean(ms) * 1e-3), p50_ms=p50, p99_ms=p99,
+               pcg_iters_per_solve=float(stats["pcg_iters"].sum(axis=1).mean()),
+               pcg_cap_hits=int((stats["status"] & g.ST_PCG_MAXITER).astype(bool).sum()),
+               nonfinite=int((stats["status"] & g.ST_NONFINITE).astype(bool).sum()),
+               tip_error_m=dict(start_mean=float(d0.mean()), end_mean=float(d1.mean()),
+                                end_last_knot=float(d1[:, -1].mean())))
+    print(f"# task space {out}", file=sys.stderr, flush=True)
+    return out
+
+
+def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, seed=0, pcg_tol=1e-5):
     """Closed-loop disturbance batch: M 7-DoF N-knot MPC instances stepped `ticks`
     control ticks at dt = 0.01 s, plant RK4 with 10 sub-steps of 1 ms, a torque
     impulse N(0, 5^2) N m per joint for one tick at ticks 100, 200, ..., 900,
-    `iters` SQP iterations per tick. Reports solves/s and the tracking error;
-    replays sampled ticks of `sample` instances in the FP64 oracle from the same
-    plant state and warm start; runs the FP64 oracle's own closed loop for those
-    instances over the first `oracle_ticks` ticks (report only: the FP32 and
-    FP64 loops may drift apart)."""
-    import dataclasses
-    from concurrent.futures import ThreadPoolExecutor
-    import oracle
+    `iters` SQP iterations per tick. Reports solves/s and the tracking error.
+    (Ticks replayed in the FP64 oracle, and the oracle's own closed loop, come
+    from tests/accuracy_report.py.)"""
     import workload as w
     from paper_2510_07625_amd import closed_loop
     solves = w.chain_batch(seed, M, N=N)
@@ -297,11 +278,9 @@ def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, ora
     rng = np.random.default_rng([seed, 5])
     kicks = {t: torch.from_numpy(rng.normal(0.0, 5.0, (M, 7)).astype(np.float32)).cuda()
              for t in range(100, ticks, 100)}
-    idx = np.linspace(0, M - 1, sample).astype(int)
-    rec = sorted({0, 100, 101, ticks // 2, ticks - 1} & set(range(ticks)))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run = closed_loop.run(b, xs, goal, ticks, n_iters=iters, disturbance=kicks.get, record_ticks=rec)
+    run = closed_loop.run(b, xs, goal, ticks, n_iters=iters, disturbance=kicks.get)
     wall = time.perf_counter() - t0
     b.close()
     q = run.states.cpu().numpy()[:, :, :7].astype(np.float64)
@@ -309,40 +288,6 @@ def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, ora
     track = np.linalg.norm(q - qg[None], axis=2)              # [ticks + 1, M]
     mean_track = track.mean(axis=1)
     dev_ms = float(np.sum(run.tick_ms))
-    # Ticks replayed in the exact FP64 oracle (Riccati, pinned against the dense KKT solve).
-    errs = []
-    for t in rec:
-        R = run.records[t]
-        for i in idx:
-            s = solves[i]
-            Xw = R["X_prev"][i].astype(np.float64)[np.minimum(np.arange(N) + 1, N - 1)]
-            Uw = R["U_prev"][i].astype(np.float64)[np.minimum(np.arange(N - 1) + 1, N - 2)]
-            st = dataclasses.replace(s, xs=R["xs"][i].astype(np.float64))
-            ref = oracle.sqp(st, oracle.Params(sqp_iters=iters, kkt_mode=2), X=Xw, U=Uw,
-                             alpha_replay=R["stats"][i]["alpha"].astype(np.float64))
-            errs.append(max(np.abs(R["X"][i] - ref.X).max() / np.abs(ref.X).max(),
-                            np.abs(R["U"][i] - ref.U).max() / np.abs(ref.U).max()))
-
-    # The oracle's own closed loop for the sampled instances (bounded).
-    def oracle_loop(i):
-        s = solves[i]
-        x, X, U = s.xs.copy(), s.X0.copy(), s.U0.copy()
-        out = [np.linalg.norm(x[:7] - s.qgoal)]
-        for t in range(oracle_ticks):
-            Xw, Uw = X[np.minimum(np.arange(N) + 1, N - 1)], U[np.minimum(np.arange(N - 1) + 1, N - 2)]
-            r = oracle.sqp(dataclasses.replace(s, xs=x), oracle.Params(sqp_iters=iters, kkt_mode=2), X=Xw, U=Uw)
-            X, U = r.X, r.U
-            tau = U[0] + (kicks[t][i].cpu().numpy().astype(np.float64) if t in kicks else 0.0)
-            x = oracle.plant_rk4(s, x, tau, 0.01, 10)
-            out.append(np.linalg.norm(x[:7] - s.qgoal))
-        return np.array(out)
-
-    oracle.lib()
-    t1 = time.perf_counter()
-    with ThreadPoolExecutor(len(idx)) as ex:
-        otrack = np.stack(list(ex.map(oracle_loop, idx)), axis=1)
-    o_wall = time.perf_counter() - t1
-    gtrack = track[:oracle_ticks + 1, idx]
     p50, p99 = _pcts(run.tick_ms)
     out = dict(M=M, N=N, ticks=ticks, sqp_iters_per_tick=iters, pcg_tol=pcg_tol,
                solves_per_s=M * ticks / (dev_ms * 1e-3), wall_solves_per_s=M * ticks / wall,
@@ -350,12 +295,7 @@ def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, ora
                tracking_error_rad=dict(mean=float(mean_track.mean()), final=float(mean_track[-1]),
                                        before_kicks=[float(mean_track[t]) for t in range(100, ticks, 100)],
                                        peak_after_kicks=[float(mean_track[t + 1:t + 100].max())
-                                                         for t in range(100, ticks, 100)]),
-               tick_replay_max_rel_err_vs_fp64_oracle=float(max(errs)), ticks_replayed=rec,
-               instances_replayed=[int(i) for i in idx],
-               oracle_loop=dict(ticks=oracle_ticks, wall_s=o_wall,
-                                max_abs_tracking_diff_rad=float(np.abs(otrack - gtrack).max()),
-                                mean_tracking_gpu=float(gtrack.mean()), mean_tracking_oracle=float(otrack.mean())))
+                                                         for t in range(100, ticks, 100)]))
     print(f"# closed loop {out}", file=sys.stderr, flush=True)
     return out
 
@@ -528,6 +468,7 @@ def main():
                     help="only the timed batched steps (no sweep, end-to-end, accuracy or CPU legs)")
     ap.add_argument("--no-precision", action="store_true", help="skip the per-precision-setting report")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch report")
+    ap.add_argument("--no-task-space", action="store_true", help="skip the task-space (figure-8) report")
     ap.add_argument("--heatmap", action="store_true",
                     help="also time one SQP iteration over M in 1..512 x N in 8..128 (6-DoF chains)")
     ap.add_argument("--hypotheses", action="store_true",
@@ -587,9 +528,9 @@ def main():
             a, b = _pcts(ms)
             plain.append(dict(M=m, solves_per_s=m / (np.mean(ms) * 1e-3), p50_ms=a, p99_ms=b))
     e2e = [float("nan")] if args.profile_run else end_to_end_ms(g, torch, M, 10, params)
-    acc = None if args.profile_run else accuracy(g, main_res, params)
     prec = [] if args.profile_run or args.no_precision else precision_report(g, torch, M, 5, args.pcg_tol)
     uneven = {} if args.profile_run or args.no_uneven else uneven_report(g, torch)
+    task = {} if args.profile_run or args.no_task_space else task_space_report(g, torch)
     hmap = heatmap(g, torch) if args.heatmap else []
     rsweep = rho_sweep(g, torch) if args.rho_sweep else []
     hyps = hypothesis_report(g, torch) if args.hypotheses else []
@@ -618,9 +559,9 @@ def main():
         "end_to_end_ms": dict(zip(("p50", "p99"), _pcts(e2e))),
         "sweep_batched": sweep,
         "sweep_plain": plain,
-        "accuracy": acc,
         "precision": prec,
         "uneven": uneven,
+        "task_space": task,
         "closed_loop": closed,
         "heatmap": hmap,
         "rho_sweep": rsweep,

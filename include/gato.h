@@ -370,6 +370,15 @@ int gato_set_external_force(gato_batch *b, const double *h_f);
 int gato_set_tip_reference(gato_batch *b, const float *d_pref);
 
 /*
+ * Tip positions (the end of the last link, base frame) of trajectories:
+ * d_X [M][N_max][nx_max] device (the boundary layout) -> d_p [M][N_max][3]
+ * device; zero beyond a solve's horizon and for the double-integrator model.
+ * FP32, the kinematics the task-space term uses. Stream-ordered on hip_stream
+ * (NULL: the batch's stream). Errors: GATO_EINVAL, GATO_EDEVICE.
+ */
+int gato_tip_positions(gato_batch *b, const float *d_X, float *d_p, void *hip_stream);
+
+/*
  * Per-solve damping rho (Sec. IV-C samples rho across the batch): h_rho[M]
  * (host, each finite and >= 0) replaces every solve's current rho; with
  * rho_adapt the kernels update it after every SQP iteration and

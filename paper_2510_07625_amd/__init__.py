@@ -71,7 +71,7 @@ EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "
            "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_set_rho", "gato_get_rho",
            "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
            "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_serve_run", "gato_set_tip_reference",
-           "gato_last_error")
+           "gato_tip_positions", "gato_last_error")
 
 _lib = None
 
@@ -118,6 +118,7 @@ def lib() -> C.CDLL:
         L.gato_serve_ctx_trajectories.argtypes = [vp, vp, vp]
         L.gato_get_rho.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_set_tip_reference.argtypes = [vp, vp]
+        L.gato_tip_positions.argtypes = [vp, vp, vp, vp]
         L.gato_serve_run.argtypes = [vp, ip, ip, ip, vp, vp, vp, vp, ip, C.c_size_t, vp, vp, vp, vp, C.POINTER(ip)]
         L.gato_buckets.argtypes = [vp, C.POINTER(Bucket), ip, C.POINTER(ip)]
         L.gato_set_mapping.argtypes = [vp, ip, ip, ip]
@@ -294,6 +295,15 @@ class Batch:
                     pref[i, :s.N] = s.pref
             b.set_tip_reference(torch.from_numpy(pref).cuda())
         return b
+
+    def tip_positions(self, X, stream=None):
+        """gato_tip_positions: tip positions [M, N_max, 3] of trajectories X [M, N_max, nx_max]."""
+        import torch
+        self._chk(X, (self.M, self.N_max, self.nx_max))
+        P = torch.empty((self.M, self.N_max, 3), dtype=torch.float32, device="cuda")
+        st = stream.cuda_stream if stream is not None else None
+        _check(lib().gato_tip_positions(self._h, _dptr(X), _dptr(P), C.c_void_p(st) if st else None))
+        return P
 
     def set_tip_reference(self, pref):
         """gato_set_tip_reference: reference tip positions, float32 cuda tensor [M, N_max, 3]."""

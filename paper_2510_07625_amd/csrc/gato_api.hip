@@ -932,6 +932,14 @@ int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, 
   return GATO_OK;
 }
 
+int gato_tip_positions(gato_batch *b, const float *d_X, float *d_p, void *hip_stream) {
+  if (!b || !d_X || !d_p) return fail(GATO_EINVAL, "batch and buffers must not be NULL");
+  hipError_t e = gato::launch_tips(b->d_desc, b->M, b->N_max, 2 * b->n_max, d_X, d_p,
+                                   hip_stream ? (hipStream_t)hip_stream : b->stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  return GATO_OK;
+}
+
 int gato_set_tip_reference(gato_batch *b, const float *d_pref) {
   if (!b || !d_pref) return fail(GATO_EINVAL, "batch and reference must not be NULL");
   if (!b->task) return fail(GATO_EINVAL, "the batch has no tip tracking term");

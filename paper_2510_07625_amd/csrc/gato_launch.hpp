@@ -20,6 +20,10 @@ constexpr int kTaskKptMax = 2;
 // Launches the closed-loop plant step (RK4, one thread per instance).
 hipError_t launch_plant(const PlantArgs &a, hipStream_t s);
 
+// Launches the tip kinematics of every knot: X [M][N_max][nx_max] -> P [M][N_max][3].
+hipError_t launch_tips(const SolveDesc *desc, int M, int N_max, int nx_max, const float *X, float *P,
+                       hipStream_t s);
+
 // Largest compiled knots-per-group value for n DoF (3 DoF: 64 lane groups
 // of 8, so 2 knots per group reach the maximum horizon).
 inline int kpt_max(int n) { return 2 * n > 8 ? 4 : 2; }

@@ -83,7 +83,36 @@ __global__ __launch_bounds__(64) void plant_kernel(PlantArgs a) {
   a.status[r] = bad ? GATO_ST_NONFINITE : 0u;
 }
 
+// Tip position of every knot of every solve, one thread per (solve, knot);
+// zero beyond a solve's horizon and for the double-integrator model.
+__global__ __launch_bounds__(256) void tip_kernel(const SolveDesc *desc, int M, int N_max, int nx_max,
+                                                  const float *X, float *P) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= M * N_max) return;
+  const int sid = t / N_max, k = t % N_max;
+  const SolveDesc &D = desc[sid];
+  float p[3] = {0.f, 0.f, 0.f};
+  if (k < D.N && D.chain.model == 0) {
+    const float *q = X + (size_t)t * nx_max;
+    switch (D.n) {
+      case 3: tip_position<3>(D.chain, q, p); break;
+      case 6: tip_position<6>(D.chain, q, p); break;
+      case 7: tip_position<7>(D.chain, q, p); break;
+      default: break;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) P[(size_t)t * 3 + c] = p[c];
+}
+
 }  // namespace
+
+hipError_t launch_tips(const SolveDesc *desc, int M, int N_max, int nx_max, const float *X, float *P,
+                       hipStream_t s) {
+  const int n = M * N_max;
+  hipLaunchKernelGGL(tip_kernel, dim3((n + 255) / 256), dim3(256), 0, s, desc, M, N_max, nx_max, X, P);
+  return hipGetLastError();
+}
 
 hipError_t launch_plant(const PlantArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(plant_kernel, dim3((a.n + 63) / 64), dim3(64), 0, s, a);
