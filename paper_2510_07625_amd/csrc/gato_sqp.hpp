@@ -780,28 +780,31 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     if (clk) clk[2] = wall_clock64();
 
     // ================= 3. Off-diagonal blocks of the stair preconditioner.
-    // The lanes of knot k (k >= 1) form row `lane` of
+    // Explicit form (the all-FP32 variant with one knot per lane group): the
+    // lanes of knot k (k >= 1) form row `lane` of
     //   P_{k,k-1} = -D_k^-1 phi_{k-1} D_{k-1}^-1,  phi_{k-1} = -A_{k-1} Q_{k-1}^-1,
-    // keep it, and publish it so that knot k-1 can read its column.
-    // Preconditioner blocks are stored in FP32 and applied in Real arithmetic:
-    // a fixed linear operator, as the pipelined recurrences require.
-    // With kFactP (several knots per lane group, where registers are short,
-    // and the task-space variant) the off-diagonal blocks are not formed:
+    // keep it, and publish it so that knot k-1 can read its column. Either
+    // form is a fixed linear operator, as the pipelined recurrences require.
+    // With kFactP (the FP64 variants, and several knots per lane group where
+    // registers are short) the off-diagonal blocks are not formed:
     // P w = D^-1 (w - O D^-1 w), with O the off-diagonal blocks of S~ that the
     // S~ product already holds.
-    constexpr bool kFactP = KPT > 1 || TS;
+    constexpr bool kFactP = KPT > 1 || TS || sizeof(Real) == 8;
     constexpr int KP = kFactP ? 1 : KPT;
-    // (Held in FP32 and converted at use: Real-held rows would save the
-    // conversions but spill inside the PCG loop. The task-space variant keeps
-    // D^-1 in Real: its S~ is far worse conditioned, P ~ S~^-1 with it, and
-    // rounding P to FP32 perturbs its smallest directions enough to slow PCG
-    // and leave a larger error at the same stopping value.)
-    using PT = std::conditional_t<TS, Real, float>;
+    // D^-1 rows: held in Real for one knot per lane group (FP64) and for the
+    // task-space variant, in FP32 (converted at use) otherwise. Rounding P to
+    // FP32 perturbs its smallest directions (P ~ S~^-1): on the headline batch
+    // the slowest solve then needs 9% more PCG iterations, on the far worse
+    // conditioned task-space systems 30-80% more, with a larger error at the
+    // same stopping value. With several knots per group, Real-held rows spill
+    // inside the PCG loop and cost more than they save.
+    constexpr bool kRealP = TS || (KPT == 1 && sizeof(Real) == 8);
+    using PT = std::conditional_t<kRealP, Real, float>;
     PT Pm[KP][NX], Pp[KP][NX], Pdf[KPT][NX];
 #pragma unroll
     for (int p = 0; p < KPT; ++p) {
 #pragma unroll
-      for (int m = 0; m < NX; ++m) Pdf[p][m] = TS ? (PT)Pd[p][m] : (PT)(float)Pd[p][m];
+      for (int m = 0; m < NX; ++m) Pdf[p][m] = kRealP ? (PT)Pd[p][m] : (PT)(float)Pd[p][m];
     }
     if constexpr (!kFactP) {
 #pragma unroll
