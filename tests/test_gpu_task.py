@@ -190,3 +190,23 @@ def test_task_space_restrictions_are_reported():
     long = [w.figure8_solve(8, 0, n=7, N=128)]
     with pytest.raises(g.GatoError):
         g.Batch.from_solves(long)
+
+
+def test_tip_positions_match_the_oracle_kinematics():
+    _say("tip positions")
+    solves = [w.figure8_solve(9, i, n=n, N=N) for i, (n, N) in enumerate([(7, 32), (6, 20), (3, 9)])]
+    b = g.Batch.from_solves(solves)
+    xs, goal, X, U = g.pack_inputs(solves)
+    rng = np.random.default_rng(9)
+    Xr = X.cpu().numpy()
+    Xr += rng.uniform(-1.5, 1.5, Xr.shape).astype(np.float32)
+    Xd = torch.from_numpy(Xr).cuda()
+    P = b.tip_positions(Xd).cpu().numpy().astype(np.float64)
+    b.close()
+    for i, s in enumerate(solves):
+        for k in range(b.N_max):
+            if k < s.N:
+                ref, _ = oracle.tip(s, Xr[i, k, :s.n].astype(np.float64))
+                assert np.abs(P[i, k] - ref).max() <= 2e-6 * max(1.0, np.abs(ref).max()), (i, k)
+            else:
+                assert not P[i, k].any()
