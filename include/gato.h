@@ -304,7 +304,8 @@ typedef struct gato_serve_ctx gato_serve_ctx;
  * when queue_limit > 0 requests already wait); whenever one of n_ctx launch
  * contexts is free it launches the oldest waiting request of every instance
  * that has nothing in flight, as many as memory_budget allows
- * (gato_workspace_bytes per request; 0: no limit), each re-solved for n_iters
+ * (gato_workspace_bytes per request; 0: no limit; a budget below one request
+ * is GATO_EINVAL), each re-solved for n_iters
  * SQP iterations from the instance's state h_state[instance] ([M][nx_max],
  * host, updated in place to the plan's x_1 when the result arrives) and its
  * previous plan shifted one knot. Outputs per request: h_latency_s (arrival

@@ -791,6 +791,8 @@ int gato_serve_run(gato_batch *b, int n_ctx, int n_iters, int R, const double *h
   }
   const int M = b->M, nx = 2 * b->n_max, nu = b->n_max;
   const size_t per_req = gato_workspace_bytes(b->n_max, b->N_max, &b->p);
+  if (memory_budget > 0 && memory_budget < per_req)
+    return fail(GATO_EINVAL, "memory_budget is below one request's workspace (nothing could launch)");
   std::vector<gato_serve_ctx *> ctx(n_ctx, nullptr);
   auto cleanup = [&]() {
     for (auto *c : ctx)

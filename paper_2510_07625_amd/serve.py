@@ -104,6 +104,8 @@ class Scheduler:
         self.ex = executor
         self.state = np.array(start_states, dtype=np.float64, copy=True)   # [P, nx] current start states
         self.budget = memory_budget if memory_budget is not None else 1 << 62
+        if self.budget < int(executor.bytes_per_request):
+            raise ValueError("memory budget below one request's workspace: nothing could ever launch")
         self.deadline = deadline_s
         self.queue_limit = queue_limit
         self.clock = clock or WallClock()
@@ -203,10 +205,13 @@ class NativeScheduler:
 
     def __init__(self, batch, start_states: np.ndarray, slots: int = 4, n_iters: int = 1,
                  memory_budget: int | None = None, deadline_s: float = 1e-3, queue_limit: int | None = None):
+        from . import workspace_bytes
         self.b = batch
         self.slots = int(slots)
         self.n_iters = int(n_iters)
         self.budget = int(memory_budget or 0)
+        if 0 < self.budget < workspace_bytes(batch.n_max, batch.N_max, batch.params):
+            raise ValueError("memory budget below one request's workspace: nothing could ever launch")
         self.deadline = deadline_s
         self.queue_limit = int(queue_limit or 0)
         self.state = np.zeros((batch.M, batch.nx_max), np.float32)

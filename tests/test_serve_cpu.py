@@ -110,6 +110,13 @@ def test_memory_admission_limits_requests_in_flight():
     assert rep.summary()["completed"] == len(reqs)
 
 
+def test_budget_below_one_request_is_rejected():
+    clock = FakeClock()
+    ex = FakeExecutor(clock, nbytes=1000)
+    with pytest.raises(ValueError):
+        Scheduler(ex, np.zeros((4, 4)), memory_budget=999, clock=clock)
+
+
 def test_queue_limit_rejects_and_deadline_is_accounted():
     reqs = _stream(200000, 0.01, 8, seed=2)
     rep, ex = _run(reqs, P=8, slots=1, queue_limit=4)
