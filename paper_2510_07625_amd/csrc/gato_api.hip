@@ -54,7 +54,7 @@ bool dof_supported(int n) { return n == 3 || n == 6 || n == 7; }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-  size_t offA, offB, offD, offT, total;
+  size_t offA, offB, offD, offT, offAT, total;
 };
 
 Layout layout_for(int n, int N) {
@@ -64,7 +64,8 @@ Layout layout_for(int n, int N) {
   l.offB = align256(l.offA + (size_t)(N - 1) * nx * nx * sizeof(float));
   l.offD = align256(l.offB + (size_t)(N - 1) * nx * nu * sizeof(float));
   l.offT = align256(l.offD + (size_t)N * nx * nx * sizeof(float));
-  l.total = align256(l.offT + (size_t)N * nx * nx * sizeof(double));
+  l.offAT = align256(l.offT + (size_t)N * nx * nx * sizeof(double));
+  l.total = align256(l.offAT + (size_t)(N - 1) * nx * nx * sizeof(float));
   return l;
 }
 
@@ -310,6 +311,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     desc[i].offB = (int64_t)l.offB;
     desc[i].offD = (int64_t)l.offD;
     desc[i].offT = (int64_t)l.offT;
+    desc[i].offAT = (int64_t)l.offAT;
     off += l.total;
   }
   b->ws_bytes = off;

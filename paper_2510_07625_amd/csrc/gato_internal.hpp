@@ -31,6 +31,7 @@ struct SolveDesc {
   int64_t ws_off;     // byte offset of this solve's workspace
   int64_t offA, offB, offD, offT;  // byte offsets inside it: A_k, B_k and the inverse
                                    // diagonal blocks (float); Schur diagonal rows (double)
+  int64_t offAT;                   // A_k^T (float), for column reads of A_k
 };
 
 enum KernelMode { kModeSqp = 0, kModeLq = 1, kModeKkt = 2 };

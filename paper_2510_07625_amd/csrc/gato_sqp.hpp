@@ -270,6 +270,11 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   // L2) when four knots per lane group would not fit them in registers.
   constexpr bool kThGlobal = KPT >= 4;
   auto Tblk = [&](int k) -> Real * { return reinterpret_cast<Real *>(ws + D.offT) + (size_t)k * NX * NX; };
+  // A_k^T in the workspace: the columns of A_k as contiguous rows, for the
+  // kernels that read them back where they are used (one vector load per
+  // four entries instead of a strided load per entry).
+  auto ATblk = [&](int k) -> float * { return reinterpret_cast<float *>(ws + D.offAT) + (size_t)k * NX * NX; };
+  constexpr bool kColsT = KPT >= 4 && sizeof(Real) == 8;
 
   // ---- Stage the iterate and the solve constants in LDS.
   // (With a warm-start shift, knot k starts from the previous knot k + shift,
@@ -403,6 +408,14 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             Ak[i * NX + lane] = (i == lane ? 1.f : 0.f) + (lane == ND + i ? h : 0.f);
             Ak[(ND + i) * NX + lane] = h * col[i] + (lane == ND + i ? 1.f : 0.f);
           }
+          if constexpr (kColsT) {
+            float *Atk = ATblk(k) + lane * NX;
+#pragma unroll
+            for (int i = 0; i < ND; ++i) {
+              Atk[i] = (i == lane ? 1.f : 0.f) + (lane == ND + i ? h : 0.f);
+              Atk[ND + i] = h * col[i] + (lane == ND + i ? 1.f : 0.f);
+            }
+          }
           if (lane < ND) {
             float mi[ND];
 #pragma unroll
@@ -534,7 +547,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       const size_t bo = (size_t)sid * (a.N_max - 1) * a.nx_max * a.nu_max;
       for (int t = tid; t < (N - 1) * NX * NX; t += kBlock) {
         const int k = t / (NX * NX), r = (t / NX) % NX, c = t % NX;
-        Ablk(k)[r * NX + c] = a.inA[ao + ((size_t)k * a.nx_max + r) * a.nx_max + c];
+        const float v = a.inA[ao + ((size_t)k * a.nx_max + r) * a.nx_max + c];
+        Ablk(k)[r * NX + c] = v;
+        if constexpr (kColsT) ATblk(k)[c * NX + r] = v;
       }
       for (int t = tid; t < (N - 1) * NX * NU; t += kBlock) {
         const int k = t / (NX * NU), r = (t / NU) % NX, c = t % NU;
@@ -643,6 +658,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // from the A blocks in the workspace where they are used (as the Schur rows
     // are), which frees 112 registers per lane; the FP32 variant has the room.
     constexpr bool kRowsGlobal = KPT >= 4 && sizeof(Real) == 8;
+    static_assert(kRowsGlobal == kColsT, "column reads of A_k need its transposed copy");
     constexpr int KR = kRowsGlobal ? 1 : KPT;
     float Am[KR][NX];     // row `lane` of A_{k-1}: S~_{k,k-1} = -A_{k-1} Q_{k-1}^-1
     float Ac[KR][NX];     // column `lane` of A_k: S~_{k,k+1} = -Q_k^-1 A_k^T
@@ -651,7 +667,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       else return Am[p][m];
     };
     auto ac = [&](int p, int m) -> float {
-      if constexpr (kRowsGlobal) return Ablk(slot + p * SLOTS)[m * NX + lane];
+      if constexpr (kRowsGlobal) return ATblk(slot + p * SLOTS)[lane * NX + m];
       else return Ac[p][m];
     };
     Real gam[KPT];
