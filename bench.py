@@ -486,7 +486,7 @@ def main():
         args.no_sweep = args.no_cpu = True
         args.serve_seconds = 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; solves shard across GPUs without any exchange, "
+        print(json.dumps({"error": "this benchmark runs on one GPU; solves shard across GPUs without any exchange, "
                                    "so a multi-GPU run is M/G independent copies of the 1-GPU run",
                           "n_gpus": args.gpus}))
         sys.exit(2)

@@ -1,6 +1,6 @@
 """Accuracy of the GPU path against the FP64 oracle on the benchmark's workloads.
 
-A report, not a test (pytest does not collect it): run it on the GPU machine as
+A report, not a test (pytest does not collect it): run it on an MI355X as
 ``python tests/accuracy_report.py`` and it prints one JSON line with
 
 * the headline launch (M = 256 7-DoF chains, N = 32, 10 SQP iterations, PCG
