@@ -87,8 +87,9 @@ typedef struct {
  * WeeN_diag at the last knot, pref set with gato_set_tip_reference (zero until
  * then). The QP uses the exact gradient and the Gauss-Newton Hessian J^T W J
  * of this term, so each Q_k gets a dense joint block. Serial chains only, at
- * most 2 knots per lane group (N <= 64 for 6-7 DoF, 128 for 3 DoF), grouped
- * dispatch only. Both NULL: no such term (zero-initialise the struct).
+ * most 2 knots per lane group (N <= 64 for 6-7 DoF, 128 for 3 DoF); a batch
+ * with such a term runs the task-space kernels for all its solves (no stage
+ * entry points). Both NULL: no such term (zero-initialise the struct).
  */
 typedef struct {
   int N;               /* knot points, 2..GATO_MAX_KNOTS */

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgato.so")
 ARCH = os.environ.get("GATO_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["sqp_mixed_f64.hip", "sqp_mixed_f32.hip", "sqp_n7.hip", "sqp_n6.hip", "sqp_n3.hip", "sqp_task.hip",
+SOURCES = ["sqp_mixed_f64.hip", "sqp_mixed_f32.hip", "sqp_n7.hip", "sqp_n6.hip", "sqp_n3.hip", "sqp_task.hip", "sqp_mixed_task.hip",
            "gato_api.hip",
            "gato_plant.hip", "gato_flops.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

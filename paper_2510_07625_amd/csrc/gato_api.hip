@@ -421,13 +421,12 @@ gato::KArgs base_args(gato_batch *b) {
   return a;
 }
 
-// (The mixed-shape kernel has no task-space variant.)
 bool use_mixed(const gato_batch *b) {
-  if (b->task) return false;
   return b->dispatch == GATO_DISPATCH_MIXED || (b->dispatch == GATO_DISPATCH_AUTO && b->groups.size() > 1);
 }
 
 hipError_t launch_mixed(const gato_batch *b, int grid, const gato::KArgs &a, hipStream_t s) {
+  if (b->task) return gato::launch_sqp_mixed_task(grid, b->p.schur_fp64 != 0, a, s);
   return b->p.schur_fp64 ? gato::launch_sqp_mixed_f64(grid, a, s) : gato::launch_sqp_mixed_f32(grid, a, s);
 }
 
@@ -634,8 +633,6 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
   a.Xout = d_Xout;
   a.Uout = d_Uout;
   hipStream_t st = hip_stream ? (hipStream_t)hip_stream : b->stream;
-  if (b->task && b->groups.size() != 1)
-    return fail(GATO_EUNSUPPORTED, "serving launches of tip tracking batches need one (n, kpt) shape");
   hipError_t e = b->groups.size() == 1
                      ? gato::launch_sqp(b->groups[0].n, b->groups[0].kpt, b->p.schur_fp64 != 0, n_req, a, st)
                      : launch_mixed(b, n_req, a, st);
@@ -995,8 +992,6 @@ int gato_set_dispatch(gato_batch *b, int mode) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (mode != GATO_DISPATCH_AUTO && mode != GATO_DISPATCH_GROUPED && mode != GATO_DISPATCH_MIXED)
     return fail(GATO_EINVAL, "unknown dispatch mode");
-  if (b->task && mode == GATO_DISPATCH_MIXED)
-    return fail(GATO_EUNSUPPORTED, "the mixed-shape kernel has no tip tracking variant");
   b->dispatch = mode;
   ++b->mapping_gen;
   return GATO_OK;
@@ -1041,7 +1036,6 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
   int rc = check_io(b, d_xs, d_goal, d_X, d_U);
   if (rc) return rc;
   if (n_iters < 1 || reps < 1) return fail(GATO_EINVAL, "n_iters and reps must be >= 1");
-  if (b->task) return fail(GATO_EUNSUPPORTED, "the autotuner times the mixed-shape kernel (no tip tracking variant)");
   hipStream_t s = b->stream;
   hipError_t e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "synchronize");
@@ -1091,7 +1085,7 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
     int best = 0;
     float best_ms = 0.f;
     for (int kpt : {1, 2, 4}) {
-      if (!kpt_allowed(n, N, kpt)) continue;
+      if (!kpt_allowed(n, N, kpt) || (b->task && kpt > gato::kTaskKptMax)) continue;
       for (int i : v) b->desc[i].kpt = kpt;
       e = hipMemcpy(b->d_desc, b->desc.data(), b->M * sizeof(SolveDesc), hipMemcpyHostToDevice);
       if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipMemcpy(desc)"); }

@@ -15,6 +15,8 @@ hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipSt
 
 // The same for the task-space variant (tip tracking costs): kpt 1 and 2.
 hipError_t launch_sqp_task(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
+// The mixed-shape kernel of the task-space variant.
+hipError_t launch_sqp_mixed_task(int grid, bool f64, const KArgs &a, hipStream_t s);
 constexpr int kTaskKptMax = 2;
 
 // Launches the closed-loop plant step (RK4, one thread per instance).

@@ -1417,32 +1417,40 @@ __global__ __launch_bounds__(kBlock) void sqp_kernel(KArgs a) {
 // matching specialisation, so a batch of uneven DoF and horizon is one launch.
 // The LDS footprint is the largest specialisation's; every specialisation
 // already runs one workgroup per CU, so occupancy is unchanged. (For 3 DoF,
-// two knots per 8-lane group already cover the maximum horizon.)
-template <class Real>
+// two knots per 8-lane group already cover the maximum horizon; the
+// task-space variant is compiled for one and two knots per group.)
+template <class Real, bool TS>
 constexpr size_t mixed_smem_bytes() {
   size_t m = 0;
-  const size_t s[] = {sizeof(Smem<3, 1, Real>), sizeof(Smem<3, 2, Real>),
-                      sizeof(Smem<6, 1, Real>), sizeof(Smem<6, 2, Real>), sizeof(Smem<6, 4, Real>),
-                      sizeof(Smem<7, 1, Real>), sizeof(Smem<7, 2, Real>), sizeof(Smem<7, 4, Real>)};
+  const size_t s[] = {smem_bytes<3, 1, Real, TS>(), smem_bytes<3, 2, Real, TS>(),
+                      smem_bytes<6, 1, Real, TS>(), smem_bytes<6, 2, Real, TS>(),
+                      TS ? 0 : smem_bytes<6, 4, Real, false>(),
+                      smem_bytes<7, 1, Real, TS>(), smem_bytes<7, 2, Real, TS>(),
+                      TS ? 0 : smem_bytes<7, 4, Real, false>()};
   for (size_t v : s) m = v > m ? v : m;
   return m;
 }
 
-template <class Real>
+template <class Real, bool TS = false>
 __global__ __launch_bounds__(kBlock) void sqp_mixed_kernel(KArgs a) {
-  __shared__ __align__(16) char smem[mixed_smem_bytes<Real>()];
+  static_assert(mixed_smem_bytes<Real, TS>() <= 160 * 1024, "LDS of one workgroup exceeds 160 KB");
+  __shared__ __align__(16) char smem[mixed_smem_bytes<Real, TS>()];
   const int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
   if (sid < 0 || sid >= a.M) return;   // a caller-provided slot out of range: nothing to do
   const SolveDesc &D = a.desc[sid];
   switch (D.n * 8 + D.kpt) {
-    case 3 * 8 + 1: sqp_solve<3, 1, Real>(a, sid, smem); break;
-    case 3 * 8 + 2: sqp_solve<3, 2, Real>(a, sid, smem); break;
-    case 6 * 8 + 1: sqp_solve<6, 1, Real>(a, sid, smem); break;
-    case 6 * 8 + 2: sqp_solve<6, 2, Real>(a, sid, smem); break;
-    case 6 * 8 + 4: sqp_solve<6, 4, Real>(a, sid, smem); break;
-    case 7 * 8 + 1: sqp_solve<7, 1, Real>(a, sid, smem); break;
-    case 7 * 8 + 2: sqp_solve<7, 2, Real>(a, sid, smem); break;
-    case 7 * 8 + 4: sqp_solve<7, 4, Real>(a, sid, smem); break;
+    case 3 * 8 + 1: sqp_solve<3, 1, Real, TS>(a, sid, smem); break;
+    case 3 * 8 + 2: sqp_solve<3, 2, Real, TS>(a, sid, smem); break;
+    case 6 * 8 + 1: sqp_solve<6, 1, Real, TS>(a, sid, smem); break;
+    case 6 * 8 + 2: sqp_solve<6, 2, Real, TS>(a, sid, smem); break;
+    case 7 * 8 + 1: sqp_solve<7, 1, Real, TS>(a, sid, smem); break;
+    case 7 * 8 + 2: sqp_solve<7, 2, Real, TS>(a, sid, smem); break;
+    case 6 * 8 + 4:
+      if constexpr (!TS) sqp_solve<6, 4, Real, false>(a, sid, smem);
+      break;
+    case 7 * 8 + 4:
+      if constexpr (!TS) sqp_solve<7, 4, Real, false>(a, sid, smem);
+      break;
     default: break;  // the host only builds the shapes above
   }
 }

@@ -182,8 +182,6 @@ def test_task_space_restrictions_are_reported():
     solves = [w.figure8_solve(8, i, n=7, N=32) for i in range(2)]
     b = g.Batch.from_solves(solves)
     with pytest.raises(g.GatoError):
-        b.set_dispatch(g.DISPATCH_MIXED)
-    with pytest.raises(g.GatoError):
         b.set_mapping(7, 32, 4)
     b.set_mapping(7, 32, 2)         # kpt 2 is compiled
     b.close()
@@ -210,3 +208,35 @@ def test_tip_positions_match_the_oracle_kinematics():
                 assert np.abs(P[i, k] - ref).max() <= 2e-6 * max(1.0, np.abs(ref).max()), (i, k)
             else:
                 assert not P[i, k].any()
+
+
+def test_uneven_task_batch_mixed_launch_equals_grouped_and_the_oracle():
+    # One mixed-shape launch over DoF {3, 6, 7} and N {16, 33, 64} runs every
+    # solve through the same specialisation as its grouped launch: bitwise
+    # equal results; a sampled solve against the oracle at tight tolerance.
+    _say("task uneven batch: mixed vs grouped")
+    shapes = [(7, 16), (3, 33), (6, 64), (7, 64), (3, 16), (6, 33), (7, 33)]
+    solves = [w.figure8_solve(10, i, n=n, N=N) for i, (n, N) in enumerate(shapes)]
+    p = g.Params(sqp_iters=3, pcg_tol=1e-8, pcg_max_iter=3000)
+    outs = []
+    for mode in (g.DISPATCH_GROUPED, g.DISPATCH_MIXED):
+        b = g.Batch.from_solves(solves, p)
+        b.set_dispatch(mode)
+        xs, goal, X, U = g.pack_inputs(solves)
+        st = b.solve(xs, goal, X, U)
+        outs.append((X.cpu().numpy(), U.cpu().numpy(), st))
+        b.close()
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    X, U, st = outs[1]
+    for i in (0, 2, 3):
+        s = solves[i]
+        ex, eu, _ = _replay(s, X[i].astype(np.float64), U[i].astype(np.float64), st[i], p,
+                            kkt_mode=0 if s.N <= 32 else 2)
+        assert ex <= 1e-4 and eu <= 1e-4, (i, ex, eu)
+    # The autotuner picks among the compiled task-space mappings.
+    b = g.Batch.from_solves(solves, p)
+    xs, goal, X, U = g.pack_inputs(solves)
+    buckets = b.autotune(xs, goal, X, U, n_iters=1, reps=1)
+    assert all(x["kpt"] in (1, 2) for x in buckets)
+    b.close()
