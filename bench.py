@@ -13,7 +13,7 @@ batched launch and for the plain form (M one-solve launches in order), per-call
 latency p50/p99 from HIP events, the roofline position of the fused kernel,
 every precision setting, the uneven batch (mixed DoF and horizon, per-shape
 against mixed-shape launch, autotuned, graph-captured), the task-space batch
-(figure-8 tip tracking), the closed-loop disturbance batch (RK4 plant, torque
+(figure-8 tip tracking, batched and in closed loop), the closed-loop disturbance batch (RK4 plant, torque
 impulses), the served MPC loop at several Poisson arrival rates (Python and
 native request loops), and the oracle's CPU throughput on a bounded sample
 (the only part that runs the oracle; the accuracy figures against it come
@@ -262,6 +262,45 @@ def task_space_report(g, torch, M=256, N=32, iters=10, steps=10, seed=0, pcg_tol
     return out
 
 
+def task_closed_loop_report(g, torch, M=256, N=32, ticks=300, iters=3, seed=0, pcg_tol=1e-5, pcg_max_iter=1000):
+    """Figure-8 MPC: M 7-DoF chains track a figure-8 with the tip in closed loop
+    (RK4 plant, 10 sub-steps of 1 ms per 10 ms tick), each tick re-solving with
+    the reference window of the tick (the horizon moves with the clock) from
+    the plan shifted one knot, `iters` SQP iterations per tick. Reports
+    solves/s and the tip's distance to the moving reference."""
+    import workload as w
+    from paper_2510_07625_amd import closed_loop
+    solves = w.figure8_batch(seed, M, N=N)
+    path = torch.from_numpy(np.stack([s.pref for s in w.figure8_batch(seed, M, N=N + ticks)])
+                            .astype(np.float32)).cuda()                  # [M, N + ticks, 3]
+    b = g.Batch.from_solves(solves, g.Params(sqp_iters=iters, pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter))
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    b.set_trajectories(X0, U0)
+    torch.cuda.synchronize()
+    run = closed_loop.run(b, xs, goal, ticks, n_iters=iters, reference=lambda t: path[:, t:t + N].contiguous())
+    # Tip of the plant at every tick against the reference at that time.
+    states = run.states                                                     # [ticks + 1, M, nx]
+    tips = []
+    for c in range(0, ticks + 1, N):
+        chunk = states[c:c + N]
+        if chunk.shape[0] < N:
+            chunk = torch.cat([chunk, chunk[-1:].expand(N - chunk.shape[0], -1, -1)])
+        tips.append(b.tip_positions(chunk.permute(1, 0, 2).contiguous())[:, :min(N, ticks + 1 - c)])
+    b.close()
+    tip = torch.cat(tips, dim=1).cpu().numpy()                             # [M, ticks + 1, 3]
+    err = np.linalg.norm(tip - path[:, :ticks + 1].cpu().numpy(), axis=2)  # [M, ticks + 1]
+    dev_ms = float(np.sum(run.tick_ms))
+    p50, p99 = _pcts(run.tick_ms)
+    half = ticks // 2
+    out = dict(M=M, N=N, ticks=ticks, sqp_iters_per_tick=iters, pcg_tol=pcg_tol,
+               solves_per_s=M * ticks / (dev_ms * 1e-3), tick_p50_ms=p50, tick_p99_ms=p99,
+               tip_error_m=dict(start=float(err[:, 0].mean()), mean_second_half=float(err[:, half:].mean()),
+                                final=float(err[:, -1].mean()),
+                                below_5cm_second_half=float((err[:, half:] < 0.05).mean())))
+    print(f"# task closed loop {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, seed=0, pcg_tol=1e-5):
     """Closed-loop disturbance batch: M 7-DoF N-knot MPC instances stepped `ticks`
     control ticks at dt = 0.01 s, plant RK4 with 10 sub-steps of 1 ms, a torque
@@ -469,6 +508,8 @@ def main():
     ap.add_argument("--no-precision", action="store_true", help="skip the per-precision-setting report")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch report")
     ap.add_argument("--no-task-space", action="store_true", help="skip the task-space (figure-8) report")
+    ap.add_argument("--task-closed-loop-ticks", type=int, default=300,
+                    help="control ticks of the figure-8 closed loop (0 skips it)")
     ap.add_argument("--heatmap", action="store_true",
                     help="also time one SQP iteration over M in 1..512 x N in 8..128 (6-DoF chains)")
     ap.add_argument("--hypotheses", action="store_true",
@@ -531,6 +572,8 @@ def main():
     prec = [] if args.profile_run or args.no_precision else precision_report(g, torch, M, 5, args.pcg_tol)
     uneven = {} if args.profile_run or args.no_uneven else uneven_report(g, torch)
     task = {} if args.profile_run or args.no_task_space else task_space_report(g, torch)
+    if task and args.task_closed_loop_ticks > 0:
+        task["closed_loop"] = task_closed_loop_report(g, torch, ticks=args.task_closed_loop_ticks)
     hmap = heatmap(g, torch) if args.heatmap else []
     rsweep = rho_sweep(g, torch) if args.rho_sweep else []
     hyps = hypothesis_report(g, torch) if args.hypotheses else []

@@ -21,15 +21,18 @@ class ClosedLoopRun:
 
 
 def run(batch, x0, goal, ticks: int, n_iters: int = 3, h: float | None = None, substeps: int = 10,
-        disturbance=None, record_ticks=(), timing: bool = True) -> ClosedLoopRun:
+        disturbance=None, record_ticks=(), timing: bool = True, reference=None) -> ClosedLoopRun:
     """Runs `ticks` control ticks over all M instances of `batch`.
 
     x0 [M, nx_max] and goal [M, nu_max] are device tensors. disturbance(tick)
-    returns a [M, nu_max] device torque added at the plant (or None). For the
-    ticks in record_ticks the run keeps, on the host, the instances' plans
-    before the tick (X_prev, U_prev), the plant state (xs), the new plans (X, U)
-    and the per-iteration statistics, so that the tick can be replayed.
-    The batch's resident trajectories are the warm start of the first tick.
+    returns a [M, nu_max] device torque added at the plant (or None).
+    reference(tick), for batches with a tip tracking term, returns the tick's
+    reference tip positions [M, N_max, 3] (device): the horizon moves with the
+    clock. For the ticks in record_ticks the run keeps, on the host, the
+    instances' plans before the tick (X_prev, U_prev), the plant state (xs),
+    the new plans (X, U), the per-iteration statistics and the reference
+    (pref), so that the tick can be replayed. The batch's resident
+    trajectories are the warm start of the first tick.
     """
     import torch
     from . import STATS_DTYPE, Batch
@@ -50,9 +53,12 @@ def run(batch, x0, goal, ticks: int, n_iters: int = 3, h: float | None = None, s
     for t in range(ticks):
         if t in rec_set:
             Xp, Up = batch.get_trajectories()
+        ref = reference(t) if reference is not None else None
         if timing:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
+        if ref is not None:
+            batch.set_tip_reference(ref)
         batch.serve_step(slots, states[t], goal, n_iters=n_iters, shift=1, Xout=Xo, Uout=Uo, d_stats=st)
         controls[t].copy_(Uo[:, 0])
         tau.copy_(controls[t])
@@ -66,7 +72,8 @@ def run(batch, x0, goal, ticks: int, n_iters: int = 3, h: float | None = None, s
             evs.append((e0, e1))
         if t in rec_set:
             records[t] = dict(X_prev=Xp.cpu().numpy(), U_prev=Up.cpu().numpy(), xs=states[t].cpu().numpy(),
-                              X=Xo.cpu().numpy(), U=Uo.cpu().numpy(), stats=Batch.decode_stats(st, M, n_iters))
+                              X=Xo.cpu().numpy(), U=Uo.cpu().numpy(), stats=Batch.decode_stats(st, M, n_iters),
+                              pref=None if ref is None else ref.cpu().numpy())
     torch.cuda.synchronize()
     tick_ms = [a.elapsed_time(b) for a, b in evs]
     return ClosedLoopRun(states, controls, tick_ms, records)

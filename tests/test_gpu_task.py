@@ -8,6 +8,7 @@ trajectories within 1e-4 of the exact oracle after the SQP iterations (with
 the GPU's accepted steps replayed), and the PCG iteration counts of the
 congruent systems equal to those of the oracle's PCG up to rounding.
 """
+import dataclasses
 import sys
 
 import numpy as np
@@ -240,3 +241,37 @@ def test_uneven_task_batch_mixed_launch_equals_grouped_and_the_oracle():
     buckets = b.autotune(xs, goal, X, U, n_iters=1, reps=1)
     assert all(x["kpt"] in (1, 2) for x in buckets)
     b.close()
+
+
+def test_figure8_closed_loop_ticks_replay_in_the_oracle():
+    # MPC on the figure-8: every tick re-solves from the plant state with the
+    # reference window of the tick (the horizon moves with the clock), the
+    # plan shifted one knot as warm start; sampled ticks replayed in the oracle.
+    _say("figure-8 closed loop ticks")
+    from paper_2510_07625_amd import closed_loop
+    M, N, iters, ticks = 3, 32, 2, 8
+    solves = [w.figure8_solve(11, i, n=7, N=N) for i in range(M)]
+    long = [w.figure8_solve(11, i, n=7, N=N + ticks) for i in range(M)]
+    path = torch.from_numpy(np.stack([s.pref for s in long]).astype(np.float32)).cuda()   # [M, N + ticks, 3]
+    p = g.Params(sqp_iters=iters, pcg_tol=1e-8, pcg_max_iter=3000)
+    b = g.Batch.from_solves(solves, p)
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    b.set_trajectories(X0, U0)
+    rec = (0, 3, 7)
+    run = closed_loop.run(b, xs, goal, ticks, n_iters=iters, record_ticks=rec,
+                          reference=lambda t: path[:, t:t + N].contiguous())
+    b.close()
+    assert np.isfinite(run.states.cpu().numpy()).all()
+    for t in rec:
+        R = run.records[t]
+        np.testing.assert_array_equal(R["pref"], path[:, t:t + N].cpu().numpy())
+        for i, s in enumerate(solves):
+            Xp, Up = R["X_prev"][i].astype(np.float64), R["U_prev"][i].astype(np.float64)
+            Xw = Xp[np.minimum(np.arange(N) + 1, N - 1)]
+            Uw = Up[np.minimum(np.arange(N - 1) + 1, N - 2)]
+            st = dataclasses.replace(s, xs=R["xs"][i].astype(np.float64), pref=R["pref"][i].astype(np.float64))
+            ref = oracle.sqp(st, oracle.Params(sqp_iters=iters, kkt_mode=0), X=Xw, U=Uw,
+                             alpha_replay=R["stats"][i]["alpha"].astype(np.float64))
+            ex = np.abs(R["X"][i] - ref.X).max() / np.abs(ref.X).max()
+            eu = np.abs(R["U"][i] - ref.U).max() / np.abs(ref.U).max()
+            assert ex <= 1e-4 and eu <= 1e-4, (t, i, ex, eu)
