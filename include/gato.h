@@ -296,9 +296,18 @@ int gato_reset_warm_start(gato_batch *b);
  */
 typedef struct gato_serve_ctx gato_serve_ctx;
 
+int gato_serve_ctx_create(gato_batch *b, int capacity, int n_iters, gato_serve_ctx **out);
+void gato_serve_ctx_destroy(gato_serve_ctx *c);
+int gato_serve_ctx_buffers(gato_serve_ctx *c, int **h_slots, float **h_xs, float **h_goal, const float **h_x1,
+                           const float **h_u0, const gato_solve_stats **h_stats);
+int gato_serve_ctx_submit(gato_serve_ctx *c, int n_req, int shift);
+int gato_serve_ctx_query(gato_serve_ctx *c);
+int gato_serve_ctx_trajectories(gato_serve_ctx *c, float *h_X, float *h_U);
+
 /*
  * Native request loop over R MPC re-solve requests (the serving pattern: new
- * requests join while others run on the device). Request r arrives at
+ * requests join while others run on the device; each re-solve warm-started
+ * as in the experiments of Sec. IV), on n_ctx (1..16) launch contexts as above. Request r arrives at
  * h_arrival_s[r] seconds after the call starts (ascending), for instance
  * h_instance[r] (0..M-1) with goal h_goal[r] ([R][nu_max], host). The loop
  * admits requests as they arrive into per-instance FIFOs (GATO_ST_ADMIT_REJECT
@@ -322,13 +331,6 @@ typedef struct gato_serve_ctx gato_serve_ctx;
 int gato_serve_run(gato_batch *b, int n_ctx, int n_iters, int R, const double *h_arrival_s, const int *h_instance,
                    const float *h_goal, float *h_state, int queue_limit, size_t memory_budget, double *h_latency_s,
                    double *h_launch_s, unsigned *h_status, float *h_u0, int *h_launches);
-int gato_serve_ctx_create(gato_batch *b, int capacity, int n_iters, gato_serve_ctx **out);
-void gato_serve_ctx_destroy(gato_serve_ctx *c);
-int gato_serve_ctx_buffers(gato_serve_ctx *c, int **h_slots, float **h_xs, float **h_goal, const float **h_x1,
-                           const float **h_u0, const gato_solve_stats **h_stats);
-int gato_serve_ctx_submit(gato_serve_ctx *c, int n_req, int shift);
-int gato_serve_ctx_query(gato_serve_ctx *c);
-int gato_serve_ctx_trajectories(gato_serve_ctx *c, float *h_X, float *h_U);
 
 /*
  * Plant of closed-loop studies (the simulations of Sec. IV-E integrate the
