@@ -265,8 +265,27 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
                     int n_iters, int shift, float *d_Xout, float *d_Uout, gato_solve_stats *d_stats,
                     void *hip_stream);
 
-/* Resets the PCG warm-start multipliers of every solve to zero (stream-ordered). */
+/* Resets the PCG warm-start multipliers of every solve to zero (stream-ordered;
+ * a kernel, so it may be captured in a graph). */
 int gato_reset_warm_start(gato_batch *b);
+
+/*
+ * The PCG warm-start multipliers of every slot (FP64, [M][N_max][nx_max],
+ * device; the lambda of Eq. (4) per knot): copied out or in, device to device,
+ * stream-ordered on the batch stream. Errors: GATO_EINVAL, GATO_EDEVICE.
+ */
+int gato_get_multipliers(gato_batch *b, double *d_lam);
+int gato_set_multipliers(gato_batch *b, const double *d_lam);
+
+/*
+ * Shifts the resident trajectory, controls and multipliers of slots
+ * d_slots[0..n-1] (device, distinct) one knot towards the start, the last knot
+ * repeated: the warm start of the next control step (Sec. IV). A following
+ * gato_serve_step with shift = 0 equals one with shift = 1 on the unshifted
+ * slot. Slots outside 0..M-1 are skipped. Launched on hip_stream (NULL: the
+ * batch stream). Errors: GATO_EINVAL, GATO_EDEVICE.
+ */
+int gato_shift_warm_start(gato_batch *b, const int *d_slots, int n, void *hip_stream);
 
 /*
  * Serving launch context: the host side of one serving launch in native code,

@@ -71,7 +71,8 @@ EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "
            "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_set_rho", "gato_get_rho",
            "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
            "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_serve_run", "gato_set_tip_reference",
-           "gato_tip_positions", "gato_last_error")
+           "gato_tip_positions", "gato_get_multipliers", "gato_set_multipliers", "gato_shift_warm_start",
+           "gato_last_error")
 
 _lib = None
 
@@ -119,6 +120,9 @@ def lib() -> C.CDLL:
         L.gato_get_rho.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_set_tip_reference.argtypes = [vp, vp]
         L.gato_tip_positions.argtypes = [vp, vp, vp, vp]
+        L.gato_get_multipliers.argtypes = [vp, vp]
+        L.gato_set_multipliers.argtypes = [vp, vp]
+        L.gato_shift_warm_start.argtypes = [vp, vp, ip, vp]
         L.gato_serve_run.argtypes = [vp, ip, ip, ip, vp, vp, vp, vp, ip, C.c_size_t, vp, vp, vp, vp, C.POINTER(ip)]
         L.gato_buckets.argtypes = [vp, C.POINTER(Bucket), ip, C.POINTER(ip)]
         L.gato_set_mapping.argtypes = [vp, ip, ip, ip]
@@ -502,6 +506,27 @@ class Batch:
 
     def reset_warm_start(self):
         _check(lib().gato_reset_warm_start(self._h))
+
+    def get_multipliers(self):
+        """gato_get_multipliers: the PCG warm-start multipliers, float64 cuda tensor [M, N_max, nx_max]."""
+        import torch
+        lam = torch.empty((self.M, self.N_max, self.nx_max), dtype=torch.float64, device="cuda")
+        _check(lib().gato_get_multipliers(self._h, _dptr(lam)))
+        return lam
+
+    def set_multipliers(self, lam):
+        """gato_set_multipliers: lam float64 cuda tensor [M, N_max, nx_max]."""
+        import torch
+        self._chk(lam, (self.M, self.N_max, self.nx_max), torch.float64)
+        _check(lib().gato_set_multipliers(self._h, _dptr(lam)))
+
+    def shift_warm_start(self, slots, stream=None):
+        """gato_shift_warm_start: shift the resident plans of slots (int32 cuda tensor) one knot."""
+        import torch
+        n = int(slots.shape[0])
+        self._chk(slots, (n,), torch.int32)
+        st = stream.cuda_stream if stream is not None else None
+        _check(lib().gato_shift_warm_start(self._h, _dptr(slots), n, C.c_void_p(st) if st else None))
 
 
 class ServeContext:

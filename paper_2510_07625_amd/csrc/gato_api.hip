@@ -901,8 +901,31 @@ int gato_serve_run(gato_batch *b, int n_ctx, int n_iters, int R, const double *h
 
 int gato_reset_warm_start(gato_batch *b) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
-  hipError_t e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, b->stream);
-  if (e != hipSuccess) return hip_fail(e, "hipMemsetAsync(lambda)");
+  hipError_t e = gato::launch_fill(b->d_lam, b->lam_bytes / sizeof(double), 0.0, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch (fill)");
+  return GATO_OK;
+}
+
+int gato_get_multipliers(gato_batch *b, double *d_lam) {
+  if (!b || !d_lam) return fail(GATO_EINVAL, "batch and buffer must not be NULL");
+  hipError_t e = hipMemcpyAsync(d_lam, b->d_lam, b->lam_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(multipliers out)");
+  return GATO_OK;
+}
+
+int gato_set_multipliers(gato_batch *b, const double *d_lam) {
+  if (!b || !d_lam) return fail(GATO_EINVAL, "batch and buffer must not be NULL");
+  hipError_t e = hipMemcpyAsync(b->d_lam, d_lam, b->lam_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(multipliers in)");
+  return GATO_OK;
+}
+
+int gato_shift_warm_start(gato_batch *b, const int *d_slots, int n, void *hip_stream) {
+  if (!b || !d_slots) return fail(GATO_EINVAL, "batch and slots must not be NULL");
+  if (n < 1 || n > b->M) return fail(GATO_EINVAL, "n must be in 1..M");
+  hipError_t e = gato::launch_shift(b->d_desc, b->M, n, d_slots, b->N_max, 2 * b->n_max, b->n_max, b->d_Xres,
+                                    b->d_Ures, b->d_lam, hip_stream ? (hipStream_t)hip_stream : b->stream);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch (shift)");
   return GATO_OK;
 }
 

@@ -22,6 +22,13 @@ constexpr int kTaskKptMax = 2;
 // Launches the closed-loop plant step (RK4, one thread per instance).
 hipError_t launch_plant(const PlantArgs &a, hipStream_t s);
 
+// Fills n doubles with v.
+hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s);
+
+// Shifts the resident trajectories and multipliers of n slots one knot.
+hipError_t launch_shift(const SolveDesc *desc, int M, int n, const int *slots, int N_max, int nx_max, int nu_max,
+                        float *X, float *U, double *lam, hipStream_t s);
+
 // Launches the tip kinematics of every knot: X [M][N_max][nx_max] -> P [M][N_max][3].
 hipError_t launch_tips(const SolveDesc *desc, int M, int N_max, int nx_max, const float *X, float *P,
                        hipStream_t s);

@@ -105,7 +105,59 @@ __global__ __launch_bounds__(256) void tip_kernel(const SolveDesc *desc, int M, 
   for (int c = 0; c < 3; ++c) P[(size_t)t * 3 + c] = p[c];
 }
 
+// Fills n doubles with v (a kernel, so that callers may capture it in a graph).
+__global__ __launch_bounds__(256) void fill_kernel(double *p, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Shifts the resident trajectory and multipliers of slot slots[b] one knot
+// towards the start, the last knot repeated; one workgroup per slot, staged
+// through LDS so that the in-place update reads only old values.
+__global__ __launch_bounds__(256) void shift_kernel(const SolveDesc *desc, int M, int n, const int *slots, int N_max,
+                                                    int nx_max, int nu_max, float *X, float *U, double *lam) {
+  __shared__ float xs[GATO_MAX_KNOTS * 2 * kMaxDof];
+  __shared__ float us[GATO_MAX_KNOTS * kMaxDof];
+  __shared__ double ls[GATO_MAX_KNOTS * 2 * kMaxDof];
+  if ((int)blockIdx.x >= n) return;
+  const int sid = slots[blockIdx.x];
+  if (sid < 0 || sid >= M) return;   // uniform across the workgroup
+  const int N = desc[sid].N;
+  float *Xs = X + (size_t)sid * N_max * nx_max;
+  float *Us = U + (size_t)sid * (N_max - 1) * nu_max;
+  double *Ls = lam + (size_t)sid * N_max * nx_max;
+  const int nxe = N * nx_max, nue = (N - 1) * nu_max;
+  for (int t = threadIdx.x; t < nxe; t += blockDim.x) {
+    xs[t] = Xs[t];
+    ls[t] = Ls[t];
+  }
+  for (int t = threadIdx.x; t < nue; t += blockDim.x) us[t] = Us[t];
+  __syncthreads();
+  for (int t = threadIdx.x; t < nxe; t += blockDim.x) {
+    const int k = t / nx_max, j = t - k * nx_max;
+    const int ks = min(k + 1, N - 1);
+    Xs[t] = xs[ks * nx_max + j];
+    Ls[t] = ls[ks * nx_max + j];
+  }
+  for (int t = threadIdx.x; t < nue; t += blockDim.x) {
+    const int k = t / nu_max, j = t - k * nu_max;
+    Us[t] = us[min(k + 1, N - 2) * nu_max + j];
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(const SolveDesc *desc, int M, int n, const int *slots, int N_max, int nx_max, int nu_max,
+                        float *X, float *U, double *lam, hipStream_t s) {
+  hipLaunchKernelGGL(shift_kernel, dim3(n), dim3(256), 0, s, desc, M, n, slots, N_max, nx_max, nu_max, X, U, lam);
+  return hipGetLastError();
+}
 
 hipError_t launch_tips(const SolveDesc *desc, int M, int N_max, int nx_max, const float *X, float *P,
                        hipStream_t s) {

@@ -107,6 +107,9 @@ def test_invalid_arguments_are_rejected_on_the_host():
     rc, msg = _create([good_r], [good_p], g.Params(rho_adapt=3))
     assert rc == g.GATO_EINVAL and "rho_adapt" in msg
     assert L.gato_set_tip_reference(None, None) == g.GATO_EINVAL
+    assert L.gato_get_multipliers(None, None) == g.GATO_EINVAL
+    assert L.gato_set_multipliers(None, None) == g.GATO_EINVAL
+    assert L.gato_shift_warm_start(None, None, 1, None) == g.GATO_EINVAL
     assert L.gato_tip_positions(None, None, None, None) == g.GATO_EINVAL
     n = C.c_int()
     assert L.gato_serve_run(None, 1, 1, 0, None, None, None, None, 0, 0, None, None, None, None, C.byref(n)) \

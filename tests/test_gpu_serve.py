@@ -197,3 +197,31 @@ def test_native_loop_rejects_beyond_the_queue_limit():
     assert len(rep.rejected) == 54 and len(rep.completions) == 10
     assert sorted(c.rid for c in rep.completions) == list(range(10))
     b.close()
+
+
+def test_shift_then_serve_equals_serve_with_shift_and_multipliers_round_trip():
+    _say("shift warm start")
+    solves, b1, xs, goal, X, U = _pool(5, seed=12, sqp_iters=2)
+    b2 = g.Batch.from_solves(solves, g.Params(sqp_iters=2))
+    for b in (b1, b2):
+        b.step(xs, goal, X.clone(), U.clone(), 1)       # non-trivial multipliers in both
+        b.set_trajectories(X, U)
+    lam = b1.get_multipliers()
+    b2.set_multipliers(lam)
+    torch.cuda.synchronize()
+    assert torch.equal(b2.get_multipliers(), lam) and lam.abs().max() > 0
+    sl = torch.tensor([3, 0, 4], dtype=torch.int32, device="cuda")
+    outs = []
+    for b, shift in ((b1, 1), (b2, 0)):
+        if shift == 0:
+            b.shift_warm_start(sl)
+        Xo = torch.zeros((3,) + tuple(X.shape[1:]), device="cuda")
+        Uo = torch.zeros((3,) + tuple(U.shape[1:]), device="cuda")
+        b.serve_step(sl, xs[[3, 0, 4]].contiguous(), goal[[3, 0, 4]].contiguous(), n_iters=2, shift=shift,
+                     Xout=Xo, Uout=Uo)
+        torch.cuda.synchronize()
+        outs.append((Xo, Uo, b.get_multipliers()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    assert torch.equal(outs[0][2], outs[1][2])
+    b1.close()
+    b2.close()
