@@ -1116,7 +1116,7 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
       for (int r = 0; r <= reps; ++r) {
         e = hipMemcpyAsync(X, d_X, b->xres_bytes, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipMemcpyAsync(U, d_U, b->ures_bytes, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess) e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, s);
+        if (e == hipSuccess) e = gato::launch_fill(b->d_lam, b->lam_bytes / sizeof(double), 0.0, s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         if (e == hipSuccess) e = launch_mixed(b, (int)v.size(), a, s);
         if (e == hipSuccess) e = hipEventRecord(e1, s);
@@ -1139,7 +1139,7 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
     }
   }
   cleanup();
-  e = hipMemsetAsync(b->d_lam, 0, b->lam_bytes, s);
+  e = gato::launch_fill(b->d_lam, b->lam_bytes / sizeof(double), 0.0, s);
   if (e == hipSuccess) e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "autotune clean-up");
   return rebuild_dispatch(b);
