@@ -256,6 +256,29 @@ def test_plain_launches_equal_batched_launch():
     b.close()
 
 
+def test_batch_of_more_solves_than_cus_is_batch_invariant():
+    # 600 solves: more workgroups than the chip holds at once (LDS allows one
+    # per CU), so later solves start as earlier ones finish. Every solve must
+    # come out bit for bit as in a batch of its own, and sampled solves match
+    # the oracle.
+    _say("M=600 batch invariance")
+    M = 600
+    solves = w.chain_batch(21, M, N=16)
+    p = g.Params(sqp_iters=3, pcg_tol=1e-7)
+    b = g.Batch.from_solves(solves, p)
+    xs, goal, X, U = g.pack_inputs(solves)
+    st = b.solve(xs, goal, X, U)
+    b.close()
+    Xb, Ub = X.cpu().numpy(), U.cpu().numpy()
+    for i in (0, 257, 599):
+        b1 = g.Batch.from_solves([solves[i]], p)
+        xs1, goal1, X1, U1 = g.pack_inputs([solves[i]])
+        b1.solve(xs1, goal1, X1, U1)
+        b1.close()
+        assert np.array_equal(X1.cpu().numpy()[0], Xb[i]) and np.array_equal(U1.cpu().numpy()[0], Ub[i]), i
+        _replay_check(solves[i], Xb[i].astype(np.float64), Ub[i].astype(np.float64), st[i], p)
+
+
 def test_double_integrator_one_step_is_the_lq_optimum():
     _say("double integrator")
     s = w.double_integrator_solve(3, 0, n=3, N=12, spring_k=1.0)
