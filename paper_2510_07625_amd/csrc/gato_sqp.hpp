@@ -138,8 +138,9 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // ---- Cross-lane sums. Every lane ends with the bit-identical total.
-// The patterns used (quad permutations, row mirrors) read a valid lane for
-// every lane, so the moves need no previous destination value.
+// The in-row patterns (quad permutations, row mirrors) read a valid lane for
+// every lane, so those moves need no previous destination value; the row
+// broadcasts that combine the four rows stay in registers (no LDS round trip).
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
@@ -150,12 +151,16 @@ __device__ __forceinline__ double dpp(double v) {
   const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
   return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ float swz16(float v) {  // lane ^ 16 inside each half-wave
-  return __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+// Row broadcasts (row_bcast:15 = 0x142, row_bcast:31 = 0x143) into the rows
+// of ROWS; the other rows read 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xF, false));
 }
-__device__ __forceinline__ double swz16(double v) {
-  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
-  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double bcast(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ float lane_val(float v, int l) {
@@ -172,9 +177,11 @@ __device__ __forceinline__ R wave_sum(R v) {
   v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
   v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
-  v += swz16(v);
-  return lane_val(v, 0) + lane_val(v, 32);
+  v += dpp<0x140>(v);  // row_mirror: every lane holds its row's sum
+  // Row 3 ends with (r3 + r2) + (r1 + r0), the rows' sums in a fixed order.
+  v += bcast<0x142, 0xA>(v);
+  v += bcast<0x143, 0xC>(v);
+  return lane_val(v, 63);
 }
 
 // Two wavefront sums interleaved step by step (each step of one hides the
@@ -189,10 +196,12 @@ __device__ __forceinline__ void wave_sum2(R &a, R &b) {
   b += dpp<0x141>(b);
   a += dpp<0x140>(a);
   b += dpp<0x140>(b);
-  a += swz16(a);
-  b += swz16(b);
-  a = lane_val(a, 0) + lane_val(a, 32);
-  b = lane_val(b, 0) + lane_val(b, 32);
+  a += bcast<0x142, 0xA>(a);
+  b += bcast<0x142, 0xA>(b);
+  a += bcast<0x143, 0xC>(a);
+  b += bcast<0x143, 0xC>(b);
+  a = lane_val(a, 63);
+  b = lane_val(b, 63);
 }
 
 // Sum over the workgroup of NV values: butterfly inside each wavefront, then a
