@@ -49,6 +49,7 @@ extern "C" {
 #define GATO_ST_NONFINITE 2u   /* non-finite step or merit; the iterate was kept */
 #define GATO_ST_NO_DESCENT 4u  /* no candidate step lowered the merit (stepped anyway) */
 #define GATO_ST_ADMIT_REJECT 8u /* serving: the request was refused at admission (queue full) */
+#define GATO_ST_EXCHANGE 16u    /* split solve: a wait for another part gave up (result invalid) */
 
 /* Robot models. */
 #define GATO_MODEL_SERIAL_CHAIN 0        /* revolute chain, joint axes z, y, z, y, ... */
@@ -426,6 +427,23 @@ int gato_get_rho(gato_batch *b, double *h_rho);
  */
 enum { GATO_DISPATCH_AUTO = 0, GATO_DISPATCH_GROUPED = 1, GATO_DISPATCH_MIXED = 2 };
 int gato_set_dispatch(gato_batch *b, int mode);
+
+/*
+ * Multi-CU split of long solves. A solve with four knots per lane group (6-7
+ * DoF, N > 64) in a batch with schur_fp64 = 1 and no tip tracking runs on
+ * parts = 4 workgroups (the default): each holds the PCG rows of 32 knots in
+ * registers (the PCG of Sec. III-B: the same Eq. (5) system, preconditioner
+ * and stopping rule), and the four exchange halo rows and inner products
+ * through device memory at every PCG iteration; the rest of the SQP iteration
+ * is computed by each part alike, and part 0 writes the results. The split
+ * applies to gato_step, gato_solve and gato_profile_phases when every
+ * workgroup of the launch fits the device at once (a cooperative launch);
+ * otherwise, under gato_step_graph and with parts = 1 every solve runs on one
+ * workgroup. The inner products are summed per part first, so results differ
+ * from the one-workgroup form at rounding level. A part that waits too long
+ * for another sets GATO_ST_EXCHANGE. Errors: GATO_EINVAL (parts not 1 or 4).
+ */
+int gato_set_split(gato_batch *b, int parts);
 
 /* One (n_dof, N) bucket of a batch and the mapping its solves use. */
 typedef struct {

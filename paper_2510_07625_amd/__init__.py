@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libgato.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "gato.h")
 
 GATO_OK, GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE, GATO_EUNSUPPORTED = 0, -1, -2, -3, -4
-ST_PCG_MAXITER, ST_NONFINITE, ST_NO_DESCENT, ST_ADMIT_REJECT = 1, 2, 4, 8
+ST_PCG_MAXITER, ST_NONFINITE, ST_NO_DESCENT, ST_ADMIT_REJECT, ST_EXCHANGE = 1, 2, 4, 8, 16
 MODEL_SERIAL_CHAIN, MODEL_DOUBLE_INTEGRATOR = 0, 1
 MAX_DOF, MAX_KNOTS, MAX_ALPHA = 7, 128, 16
 DISPATCH_AUTO, DISPATCH_GROUPED, DISPATCH_MIXED = 0, 1, 2
@@ -67,7 +67,7 @@ EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "
            "gato_batch_shape", "gato_solve", "gato_step", "gato_step_plain", "gato_debug_lq",
            "gato_debug_kkt", "gato_reset_warm_start", "gato_rbd_flops", "gato_profile_phases",
            "gato_set_trajectories", "gato_get_trajectories", "gato_serve_step", "gato_plant_step",
-           "gato_set_external_force", "gato_set_dispatch",
+           "gato_set_external_force", "gato_set_dispatch", "gato_set_split",
            "gato_buckets", "gato_set_mapping", "gato_autotune", "gato_step_graph", "gato_set_rho", "gato_get_rho",
            "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
            "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_serve_run", "gato_set_tip_reference",
@@ -109,6 +109,7 @@ def lib() -> C.CDLL:
         L.gato_plant_step.argtypes = [vp, ip, vp, vp, vp, vp, C.c_double, ip, vp, vp, vp]
         L.gato_set_external_force.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_set_dispatch.argtypes = [vp, ip]
+        L.gato_set_split.argtypes = [vp, ip]
         L.gato_set_rho.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_serve_ctx_create.argtypes = [vp, ip, ip, C.POINTER(vp)]
         L.gato_serve_ctx_destroy.argtypes = [vp]
@@ -373,6 +374,10 @@ class Batch:
         r = np.zeros(self.M, np.float64)
         _check(lib().gato_get_rho(self._h, r.ctypes.data_as(C.POINTER(C.c_double))))
         return r
+
+    def set_split(self, parts: int):
+        """gato_set_split: 4 (long solves on four workgroups where the launch fits) or 1."""
+        _check(lib().gato_set_split(self._h, int(parts)))
 
     def set_dispatch(self, mode: int):
         """gato_set_dispatch: DISPATCH_AUTO, DISPATCH_GROUPED or DISPATCH_MIXED."""

@@ -21,6 +21,9 @@ hipError_t launch_sqp_n6(int kpt, bool f64, int grid, const KArgs &a, hipStream_
 hipError_t launch_sqp_n7(int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
 hipError_t launch_sqp_mixed_f32(int grid, const KArgs &a, hipStream_t s);
 hipError_t launch_sqp_mixed_f64(int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_n6_split(int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_n7_split(int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_mixed_f64_split(int grid, const KArgs &a, hipStream_t s);
 
 hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s) {
   if (a.pref) return launch_sqp_task(nd, kpt, f64, grid, a, s);   // a batch with task-space solves
@@ -109,9 +112,19 @@ struct gato_batch {
   struct Group {
     int n, kpt, count;
     int *d_order;
+    int *d_order_split;   // the same with four blocks per split solve (or null)
+    int grid_split;
   };
   std::vector<Group> groups;
   int *d_order_all = nullptr;  // every solve, decreasing work (mixed-shape launch)
+  // Split long solves (6-7 DoF, N > 64, FP64 Schur): four workgroups per solve
+  // sharing the PCG through the exchange words, when the launch fits the chip.
+  unsigned long long *d_xch = nullptr;
+  int n_split = 0;               // solves that can split
+  int split_parts = gato::kSplitParts;   // gato_set_split: 4 (split where possible) or 1
+  unsigned epoch = 0;            // tag epoch of the last split launch (1..65535)
+  int *d_order_split_all = nullptr;
+  int grid_split_all = 0;
   int dispatch = GATO_DISPATCH_AUTO;
   std::vector<float> tuned_ms;  // per solve: the tuned time of its bucket (0 if never tuned)
   // Captured step (gato_step_graph).
@@ -128,9 +141,30 @@ static int rebuild_dispatch(gato_batch *b) {
   const auto &desc = b->desc;
   hipError_t e = hipMemcpy(b->d_desc, desc.data(), M * sizeof(SolveDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(desc)");
-  for (auto &g : b->groups)
+  for (auto &g : b->groups) {
     if (g.d_order) (void)hipFree(g.d_order);
+    if (g.d_order_split) (void)hipFree(g.d_order_split);
+  }
   b->groups.clear();
+  if (b->d_order_split_all) (void)hipFree(b->d_order_split_all);
+  b->d_order_split_all = nullptr;
+  b->grid_split_all = 0;
+  // A split solve takes four consecutive blocks: the part in bits 24..31.
+  auto expand = [&](const std::vector<int> &v) {
+    std::vector<int> o;
+    for (int i : v) {
+      if (desc[i].xch_off >= 0 && desc[i].kpt == 4)
+        for (int j = 0; j < gato::kSplitParts; ++j) o.push_back(i | (j << 24));
+      else
+        o.push_back(i);
+    }
+    return o;
+  };
+  auto upload = [&](const std::vector<int> &v, int **dst) -> hipError_t {
+    hipError_t e2 = hipMalloc((void **)dst, v.size() * sizeof(int));
+    if (e2 != hipSuccess) return e2;
+    return hipMemcpy(*dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
+  };
   auto longer = [&](int x, int y) {
     const long wx = (long)desc[x].N * desc[x].n, wy = (long)desc[y].N * desc[y].n;
     return wx != wy ? wx > wy : desc[x].N > desc[y].N;
@@ -140,14 +174,32 @@ static int rebuild_dispatch(gato_batch *b) {
   std::stable_sort(all.begin(), all.end(), longer);
   e = hipMemcpy(b->d_order_all, all.data(), M * sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(order)");
+  if (b->n_split > 0) {
+    const std::vector<int> xall = expand(all);
+    e = upload(xall, &b->d_order_split_all);
+    if (e != hipSuccess) return hip_fail(e, "split order");
+    b->grid_split_all = (int)xall.size();
+  }
   std::vector<std::vector<int>> members(64);
   for (int i : all) members[desc[i].n * 8 + desc[i].kpt].push_back(i);
   for (int key = 0; key < 64; ++key) {
     auto &v = members[key];
     if (v.empty()) continue;
-    gato_batch::Group g{key / 8, key % 8, (int)v.size(), nullptr};
+    gato_batch::Group g{key / 8, key % 8, (int)v.size(), nullptr, nullptr, 0};
     e = hipMalloc((void **)&g.d_order, v.size() * sizeof(int));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(order)");
+    if (b->n_split > 0) {
+      const std::vector<int> xv = expand(v);
+      if (xv.size() > v.size()) {
+        e = upload(xv, &g.d_order_split);
+        if (e != hipSuccess) {
+          (void)hipFree(g.d_order);
+          if (g.d_order_split) (void)hipFree(g.d_order_split);
+          return hip_fail(e, "split order");
+        }
+        g.grid_split = (int)xv.size();
+      }
+    }
     b->groups.push_back(g);
     e = hipMemcpy(g.d_order, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpy(order)");
@@ -304,6 +356,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
   b->p = prm;
   b->stream = (hipStream_t)hip_stream;
   size_t off = 0;
+  int64_t xwords = 0;
   for (int i = 0; i < M; ++i) {
     const Layout l = layout_for(desc[i].n, desc[i].N);
     desc[i].ws_off = (int64_t)off;
@@ -312,7 +365,16 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     desc[i].offD = (int64_t)l.offD;
     desc[i].offT = (int64_t)l.offT;
     desc[i].offAT = (int64_t)l.offAT;
-    off += l.total;
+    // Long solves (four knots per lane group) of an FP64-Schur batch can split:
+    // a workspace per part and an exchange area.
+    const bool can_split = desc[i].kpt == 4 && prm.schur_fp64 && !task;
+    desc[i].ws_part = can_split ? (int64_t)l.total : 0;
+    desc[i].xch_off = can_split ? xwords : -1;
+    if (can_split) {
+      xwords += gato::kXWordsPerSolve;
+      ++b->n_split;
+    }
+    off += l.total * (can_split ? gato::kSplitParts : 1);
   }
   b->ws_bytes = off;
   b->desc = desc;
@@ -323,6 +385,12 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(desc)"); }
   e = hipMalloc((void **)&b->d_order_all, M * sizeof(int));
   if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(order)"); }
+  if (xwords > 0) {
+    e = hipMalloc((void **)&b->d_xch, (size_t)xwords * sizeof(unsigned long long));
+    if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMalloc(exchange)"); }
+    e = hipMemset(b->d_xch, 0, (size_t)xwords * sizeof(unsigned long long));
+    if (e != hipSuccess) { gato_batch_destroy(b); return hip_fail(e, "hipMemset(exchange)"); }
+  }
   rc = rebuild_dispatch(b);
   if (rc != GATO_OK) { gato_batch_destroy(b); return rc; }
   e = hipMalloc((void **)&b->d_ws, b->ws_bytes);
@@ -368,9 +436,13 @@ void gato_batch_destroy(gato_batch *b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   else (void)hipDeviceSynchronize();
-  for (auto &g : b->groups)
+  for (auto &g : b->groups) {
     if (g.d_order) (void)hipFree(g.d_order);
+    if (g.d_order_split) (void)hipFree(g.d_order_split);
+  }
   if (b->d_order_all) (void)hipFree(b->d_order_all);
+  if (b->d_order_split_all) (void)hipFree(b->d_order_split_all);
+  if (b->d_xch) (void)hipFree(b->d_xch);
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_desc) (void)hipFree(b->d_desc);
@@ -431,9 +503,28 @@ hipError_t launch_mixed(const gato_batch *b, int grid, const gato::KArgs &a, hip
 }
 
 // All solves of the batch: one mixed-shape launch over the decreasing-work
-// order, or one launch per shape group.
-int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s) {
+// order, or one launch per shape group. Long solves split across four
+// workgroups (a cooperative launch) unless `allow_split` is false (graph
+// capture), the batch has it switched off, or the launch would not fit the chip
+// at once; then they run one workgroup each.
+int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split = true) {
+  const bool split = allow_split && a.mode == gato::kModeSqp && b->split_parts == gato::kSplitParts &&
+                     b->n_split > 0;
+  gato::KArgs as = a;
+  if (split) {
+    b->epoch = b->epoch % 65535u + 1u;
+    as.split = 1;
+    as.epoch = b->epoch;
+    as.xch = b->d_xch;
+  }
   if (use_mixed(b)) {
+    if (split && b->grid_split_all > b->M) {
+      as.order = b->d_order_split_all;
+      const hipError_t e = gato::launch_sqp_mixed_f64_split(b->grid_split_all, as, s);
+      if (e == hipSuccess) return GATO_OK;
+      if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(e, "kernel launch (split)");
+      (void)hipGetLastError();
+    }
     a.order = b->d_order_all;
     hipError_t e = launch_mixed(b, b->M, a, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -441,6 +532,14 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s) {
   }
   const bool f64 = b->p.schur_fp64 != 0;
   for (const auto &g : b->groups) {
+    if (split && g.d_order_split && f64 && (g.n == 6 || g.n == 7)) {
+      as.order = g.d_order_split;
+      const hipError_t e = g.n == 7 ? gato::launch_sqp_n7_split(g.grid_split, as, s)
+                                    : gato::launch_sqp_n6_split(g.grid_split, as, s);
+      if (e == hipSuccess) continue;
+      if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(e, "kernel launch (split)");
+      (void)hipGetLastError();
+    }
     a.order = g.d_order;
     hipError_t e = gato::launch_sqp(g.n, g.kpt, f64, g.count, a, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
@@ -1011,6 +1110,13 @@ int gato_get_rho(gato_batch *b, double *h_rho) {
   return GATO_OK;
 }
 
+int gato_set_split(gato_batch *b, int parts) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (parts != 1 && parts != gato::kSplitParts) return fail(GATO_EINVAL, "parts must be 1 or 4");
+  b->split_parts = parts;
+  return GATO_OK;
+}
+
 int gato_set_dispatch(gato_batch *b, int mode) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (mode != GATO_DISPATCH_AUTO && mode != GATO_DISPATCH_GROUPED && mode != GATO_DISPATCH_MIXED)
@@ -1176,7 +1282,7 @@ int gato_step_graph(gato_batch *b, const float *d_xs, const float *d_goal, float
     a.mode = gato::kModeSqp;
     e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    rc = launch_groups(b, a, b->cap_stream);
+    rc = launch_groups(b, a, b->cap_stream, false);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(b->cap_stream, &g);
     if (rc != GATO_OK) {

@@ -32,9 +32,18 @@ struct SolveDesc {
   int64_t offA, offB, offD, offT;  // byte offsets inside it: A_k, B_k and the inverse
                                    // diagonal blocks (float); Schur diagonal rows (double)
   int64_t offAT;                   // A_k^T (float), for column reads of A_k
+  // Multi-CU split of a long solve (four knots per lane group, FP64 Schur):
+  // bytes of one part's workspace (part j at ws_off + j ws_part) and the word
+  // offset of the solve's exchange area, or -1 when the solve cannot split.
+  int64_t ws_part;
+  int64_t xch_off;
 };
 
 enum KernelMode { kModeSqp = 0, kModeLq = 1, kModeKkt = 2 };
+
+// Split solves: parts per solve and 64-bit exchange words per solve.
+constexpr int kSplitParts = 4;
+constexpr int kXWordsPerSolve = kSplitParts * (4 * 72 + 1024);
 
 struct KArgs {
   const SolveDesc *desc;
@@ -76,6 +85,13 @@ struct KArgs {
   int by_block;
   int shift;
   float *Xout, *Uout;
+  // Split launch: `order` entries carry the part in bits 24..31 and the solve in
+  // bits 0..23; the parts of a solve exchange through `xch` under tags of this
+  // launch's `epoch` (1..65535). All workgroups of such a launch are co-resident
+  // (cooperative launch).
+  int split;
+  unsigned epoch;
+  unsigned long long *xch;
 };
 
 // Closed-loop plant step (gato_plant_step).

@@ -19,6 +19,20 @@ hipError_t launch_sqp_task(int nd, int kpt, bool f64, int grid, const KArgs &a, 
 hipError_t launch_sqp_mixed_task(int grid, bool f64, const KArgs &a, hipStream_t s);
 constexpr int kTaskKptMax = 2;
 
+// hipSuccess when `grid` workgroups of kernel f fit the device at once (the
+// condition of a cooperative launch), hipErrorCooperativeLaunchTooLarge when
+// they do not (nothing is launched then).
+inline hipError_t cooperative_fits(const void *f, int grid) {
+  int per_cu = 0, dev = 0, cus = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0);
+  if (e != hipSuccess) return e;
+  e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  return (long)per_cu * cus >= grid ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
+}
+
 // Launches the closed-loop plant step (RK4, one thread per instance).
 hipError_t launch_plant(const PlantArgs &a, hipStream_t s);
 

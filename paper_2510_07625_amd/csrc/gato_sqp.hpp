@@ -99,6 +99,7 @@ struct Smem {
   float alpha[kMaxAlpha];
   float xs[G], xg[G], c0[G];
   int bad[2];              // per-iteration flag, indexed by iteration parity
+  int xfail, xpad;         // split solve: a wait for another part gave up
   float A[LB][NX * NX];    // A_k
   float B[LB][NX * NU];    // B_k
   float Dinv[LB][NX * NX]; // inverse diagonal blocks of S~
@@ -234,8 +235,52 @@ __device__ __forceinline__ void block_sum(double (*red)[3][kBlock / 64], int &bu
   buf ^= 1;
 }
 
+// ---- Exchange between the workgroups (parts) of a split solve. An FP64 value
+// travels as two 64-bit words, each holding one 32-bit half of the value under
+// a 32-bit tag (launch epoch, exchange number). The words are written and
+// polled with relaxed agent-scope atomics: each access is single-copy atomic
+// and coherent across the XCDs' L2 caches, so a reader that sees the tag sees
+// the half stored with it, and no fence (no whole-L2 write-back or
+// invalidation) is needed. Exchange e uses slot e mod 4 of the writer; a part
+// reuses a slot only after completing later exchanges that every reader of the
+// slot had to take part in. Every wait is bounded.
+constexpr int kXSlot = 72;                    // words: left row [0, 32), right row [32, 64), sums [64, 70)
+constexpr int kXSlots = 4;
+constexpr int kXLam = 1024;                   // words: multipliers of 32 knots x 16 rows
+constexpr int kXPart = kXSlots * kXSlot + kXLam;
+constexpr int kXParts = 4;
+constexpr int kXSpin = 1 << 17;               // polls before a wait gives up
+static_assert(kXParts == kSplitParts && kXParts * kXPart == kXWordsPerSolve, "exchange layout");
+
+__device__ __forceinline__ void xput(unsigned long long *w, unsigned tag, double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned long long t = (unsigned long long)tag << 32;
+  __hip_atomic_store(w, t | (u & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(w + 1, t | (u >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// The value stored under `tag` at w; false (and 0) when the wait gave up or
+// `dead` (an earlier wait of the workgroup gave up) is set.
+__device__ __forceinline__ bool xget(unsigned long long *w, unsigned tag, bool dead, double &v) {
+  v = 0.0;
+  if (dead) return false;
+  unsigned long long lo = 0, hi = 0;
+  int n = 0;
+  for (;;) {
+    lo = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((unsigned)(lo >> 32) == tag) break;
+    if (++n >= kXSpin) return false;
+  }
+  for (;;) {
+    hi = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((unsigned)(hi >> 32) == tag) break;
+    if (++n >= kXSpin) return false;
+  }
+  v = __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+  return true;
+}
+
 template <int ND, int KPT, class Real, bool TS = false>
-__device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, int sid, char *smem_raw) {
+__device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, int sid, int part, char *smem_raw) {
   using Sh = Shape<ND>;
   constexpr int NX = Sh::NX, NU = Sh::NU, G = Sh::G, SLOTS = Sh::SLOTS;
   constexpr bool kLds = BlockStore<ND, KPT>::kLds;
@@ -251,7 +296,13 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   const int N = D.N;
   const float h = D.dt;
   const int n_alpha = a.n_alpha;
-  char *ws = a.ws + D.ws_off;
+  // Split solve (four knots per lane group, FP64 Schur): four workgroups run
+  // the same SQP iteration, each with its own workspace, and share the PCG:
+  // part j owns the knots 32 j .. 32 j + 31 (p == j). Only part 0 writes results.
+  constexpr bool kSplitOk = (KPT == 4) && (sizeof(Real) == 8) && !TS;
+  const bool split = kSplitOk && a.split && a.mode == kModeSqp && D.xch_off >= 0 && part >= 0 && part < kXParts;
+  const bool writer = !split || part == 0;
+  char *ws = a.ws + D.ws_off + (split ? (int64_t)part * D.ws_part : 0);
   const size_t xoff = (size_t)sid * a.N_max * a.nx_max;
   const size_t uoff = (size_t)sid * (a.N_max - 1) * a.nu_max;
   double *gL = a.lam + xoff;  // [N][nx_max]
@@ -313,6 +364,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   if (tid == 0) {
     sm.bad[0] = 0;
     sm.bad[1] = 0;
+    sm.xfail = 0;
     float al = 1.f;
     for (int i = 0; i < n_alpha; ++i) {
       sm.alpha[i] = al;
@@ -329,6 +381,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
                  ? (Real)gL[min(k + sh, N - 1) * a.nx_max + lane0] : (Real)0;
   }
   int redbuf = 0;
+  unsigned xe = 0;   // split solve: exchange number (the same sequence in every part)
   // Damping on every Q_k (Sec. IV-C); uniform across the workgroup.
   double rho = a.rho[sid];
   __syncthreads();
@@ -352,7 +405,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       sm.Qni[tid] = tid < NX ? (unit ? 1.0 : 1.0 / (D.QNd[tid] + rho)) : 0.0;
     }
     int &bad_flag = sm.bad[it & 1];
-    unsigned long long *clk = (a.clk && tid == 0) ? a.clk + ((size_t)sid * a.iters + it) * 8 : nullptr;
+    unsigned long long *clk = (a.clk && tid == 0 && writer) ? a.clk + ((size_t)sid * a.iters + it) * 8 : nullptr;
     unsigned long long cyc0 = 0;
     if (clk) {
       clk[0] = wall_clock64();
@@ -887,11 +940,82 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // an iteration shares a workgroup barrier with the vector exchange, so an
     // iteration needs two barriers and the scalar divisions overlap the
     // matrix-vector products.
+    // Split solve: this part's rows only, until the multipliers are gathered.
+    bool xon = split;
+    auto own = [&](int p) { return !xon || p == part; };
+    unsigned long long *xb = split ? a.xch + D.xch_off : nullptr;
+    auto xtag = [&](unsigned e) { return ((a.epoch & 0xffffu) << 16) | (e & 0xffffu); };
+    auto xslot = [&](int q, unsigned e) { return xb + (size_t)q * kXPart + (size_t)(e % kXSlots) * kXSlot; };
+    const int kf = part * SLOTS, kl = min(kf + SLOTS, N) - 1;   // own knots kf..kl (none when kf >= N)
+    const bool has_l = split && part > 0 && kf < N;              // a part on the left / the right
+    const bool has_r = split && kl + 1 < N;
+    // Halo rows: the first own knot's row of vl goes to the left part, the last
+    // one's of vr to the right part; the neighbours' rows land in vr[kf - 1]
+    // and vl[kl + 1], read only by the lane groups that receive them.
+    auto xhalo_put = [&](unsigned e, Real (*vl)[G], Real (*vr)[G]) {
+      if (lane < NX) {
+        if (has_l && slot == 0) xput(xslot(part, e) + 2 * lane, xtag(e), (double)vl[kf][lane]);
+        if (has_r && slot == kl - kf) xput(xslot(part, e) + 32 + 2 * lane, xtag(e), (double)vr[kl][lane]);
+      }
+    };
+    auto xhalo_get = [&](unsigned e, Real (*vl)[G], Real (*vr)[G]) {
+      const bool dead = sm.xfail != 0;
+      if (lane < NX) {
+        double v;
+        if (has_l && slot == 0) {
+          if (!xget(xslot(part - 1, e) + 32 + 2 * lane, xtag(e), dead, v)) sm.xfail = 1;
+          vr[kf - 1][lane] = (Real)v;
+        }
+        if (has_r && slot == kl - kf) {
+          if (!xget(xslot(part + 1, e) + 2 * lane, xtag(e), dead, v)) sm.xfail = 1;
+          vl[kl + 1][lane] = (Real)v;
+        }
+      }
+      wave_sync();
+    };
+    // Sums over the parts (fixed order) of three partials that every lane holds.
+    auto xsum_put = [&](unsigned e, double s0, double s1, double s2) {
+      if (tid < 3) xput(xslot(part, e) + 64 + 2 * tid, xtag(e), tid == 0 ? s0 : (tid == 1 ? s1 : s2));
+    };
+    auto xsum_get = [&](unsigned e, double &s0, double &s1, double &s2) {
+      const bool dead = sm.xfail != 0;
+      const int l = tid & 63;
+      double v = 0.0;
+      if (l < 3 * kXParts) {
+        if (!xget(xslot(l / 3, e) + 64 + 2 * (l % 3), xtag(e), dead, v)) sm.xfail = 1;
+      }
+      s0 = (lane_val(v, 0) + lane_val(v, 3)) + (lane_val(v, 6) + lane_val(v, 9));
+      s1 = (lane_val(v, 1) + lane_val(v, 4)) + (lane_val(v, 7) + lane_val(v, 10));
+      s2 = (lane_val(v, 2) + lane_val(v, 5)) + (lane_val(v, 8) + lane_val(v, 11));
+    };
+    auto xhalo = [&](Real (*vl)[G], Real (*vr)[G]) {
+      xhalo_put(xe, vl, vr);
+      xhalo_get(xe, vl, vr);
+      ++xe;
+    };
+    // Every part's multipliers to every part (after the PCG).
+    auto xlam = [&]() {
+      const unsigned e = xe++;
+#pragma unroll
+      for (int p = 0; p < KPT; ++p)
+        if (p == part && slot + p * SLOTS < N && lane < NX)
+          xput(xb + (size_t)p * kXPart + kXSlots * kXSlot + 2 * (slot * G + lane), xtag(e), (double)lam[p]);
+      const bool dead = sm.xfail != 0;
+#pragma unroll
+      for (int p = 0; p < KPT; ++p) {
+        if (p != part && slot + p * SLOTS < N && lane < NX) {
+          double v;
+          if (!xget(xb + (size_t)p * kXPart + kXSlots * kXSlot + 2 * (slot * G + lane), xtag(e), dead, v))
+            sm.xfail = 1;
+          lam[p] = (Real)v;
+        }
+      }
+    };
     auto share_S = [&](const Real *vals) {   // operand of S~: vals and Q^-1 vals
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
         const int k = slot + p * SLOTS;
-        if (k < N) {
+        if (k < N && own(p)) {
           const bool valid = lane < NX;
           sm.pv[k][lane] = valid ? vals[p] : (Real)0;
           sm.sv[k][lane] = valid ? qown[p] * vals[p] : (Real)0;
@@ -902,7 +1026,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
         const int k = slot + p * SLOTS;
-        if (k < N) buf[k][lane] = (lane < NX) ? vals[p] : (Real)0;
+        if (k < N && own(p)) buf[k][lane] = (lane < NX) ? vals[p] : (Real)0;
       }
     };
     // With one knot per lane group, block-row products accumulate in two
@@ -1001,7 +1125,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
         const int k = slot + p * SLOTS;
-        if (k < N) {
+        if (k < N && own(p)) {
           const Real z = group_dinv(p, vals[p]);
           sm.rv[k][lane] = (lane < NX) ? z : (Real)0;
           sm.gv[k][lane] = (lane < NX) ? qown[p] * z : (Real)0;
@@ -1023,23 +1147,26 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       }
       return group_dinv(p, v - oz);
     };
-    auto row_valid = [&](int p) { return (slot + p * SLOTS) < N && lane < NX; };
+    auto row_valid = [&](int p) { return (slot + p * SLOTS) < N && lane < NX && own(p); };
 
     // r = gamma~ - S~ lambda, u = P r, w = S~ u; eta_ref = gamma~^T P gamma~.
     Real r[KPT], u[KPT], w[KPT], vm[KPT], vn[KPT], vz[KPT], vq[KPT], vs[KPT], vp[KPT];
     share_S(lam);
     __syncthreads();
+    if (xon) xhalo(sm.pv, sm.sv);
 #pragma unroll
     for (int p = 0; p < KPT; ++p) r[p] = row_valid(p) ? gam[p] - apply_S(p) : (Real)0;
     Real Pgam[KPT];   // P gamma~, for the reference norm
     if constexpr (kFactP) {
       prepare_P(r);
       __syncthreads();
+      if (xon) xhalo(sm.rv, sm.gv);
 #pragma unroll
       for (int p = 0; p < KPT; ++p) u[p] = row_valid(p) ? finish_P(p, r[p]) : (Real)0;
       __syncthreads();
       prepare_P(gam);
       __syncthreads();
+      if (xon) xhalo(sm.rv, sm.gv);
 #pragma unroll
       for (int p = 0; p < KPT; ++p) Pgam[p] = row_valid(p) ? finish_P(p, gam[p]) : (Real)0;
     } else {
@@ -1121,6 +1248,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     } else {
       share_S(u);
       __syncthreads();
+      if (xon) xhalo(sm.pv, sm.sv);
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
         w[p] = row_valid(p) ? apply_S(p) : (Real)0;
@@ -1172,8 +1300,23 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         __syncthreads();
         // Pairwise tree over the per-wavefront partials (fixed order).
         gma = pair_tree<kBlock / 64>(sm.red[redbuf][0]);
-        const Real dlt = pair_tree<kBlock / 64>(sm.red[redbuf][1]);
-        if (its == 0) stop = (Real)a.pcg_tol * (Real)a.pcg_tol * pair_tree<kBlock / 64>(sm.red[redbuf][2]);
+        Real dlt = pair_tree<kBlock / 64>(sm.red[redbuf][1]);
+        if (xon) {
+          // Halo rows for finish_P and this part's inner products out; the
+          // neighbours' rows and the sums over the parts in.
+          const double e0 = (its == 0) ? pair_tree<kBlock / 64>(sm.red[redbuf][2]) : 0.0;
+          xhalo_put(xe, sm.rv, sm.gv);
+          xsum_put(xe, gma, dlt, e0);
+          xhalo_get(xe, sm.rv, sm.gv);
+          double g_, d_, e_;
+          xsum_get(xe, g_, d_, e_);
+          ++xe;
+          gma = (Real)g_;
+          dlt = (Real)d_;
+          if (its == 0) stop = (Real)a.pcg_tol * (Real)a.pcg_tol * (Real)e_;
+        } else if (its == 0) {
+          stop = (Real)a.pcg_tol * (Real)a.pcg_tol * pair_tree<kBlock / 64>(sm.red[redbuf][2]);
+        }
         redbuf ^= 1;
         if (!(gma > stop) || its >= max_it) break;
 #pragma unroll
@@ -1188,6 +1331,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         const Real alpha = kSplit ? gma / (dlt - gma * gma * cga)
                                   : ((its == 0) ? gma / dlt : gma / (dlt - beta * gma / cga));
         __syncthreads();
+        if (xon) xhalo(sm.pv, sm.sv);
 #pragma unroll
         for (int p = 0; p < KPT; ++p) {
           vn[p] = row_valid(p) ? apply_S(p) : (Real)0;
@@ -1209,6 +1353,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         }
         ++its;
       }
+    }
+    if (xon) {
+      xlam();
+      xon = false;
     }
     unsigned status = (gma > stop) ? GATO_ST_PCG_MAXITER : 0u;
     if (clk) clk[4] = wall_clock64();
@@ -1371,7 +1519,8 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         if (k < N - 1 && j < 8) sm.U[k][j] += al * sm.dU[k][j];
       }
     }
-    if (tid == 0 && a.stats) {
+    if (split && sm.xfail) status |= GATO_ST_EXCHANGE;
+    if (tid == 0 && a.stats && writer) {
       gato_solve_stats st;
       st.merit0 = (float)sm.merit[n_alpha];
       st.merit = bad ? (float)sm.merit[n_alpha] : (float)sm.merit[best];
@@ -1390,7 +1539,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 
   // ---- Write back the iterate, the warm-start multipliers and the adapted damping.
   const int lane = lane0, slot = slot0;
-  if (a.mode == kModeSqp) {
+  if (a.mode == kModeSqp && writer) {
     if (a.rho_adapt && tid == 0) a.rho[sid] = rho;
     const size_t rxo = (size_t)blockIdx.x * a.N_max * a.nx_max;
     const size_t ruo = (size_t)blockIdx.x * (a.N_max - 1) * a.nu_max;
@@ -1417,9 +1566,14 @@ template <int ND, int KPT, class Real, bool TS = false>
 __global__ __launch_bounds__(kBlock) void sqp_kernel(KArgs a) {
   static_assert(smem_bytes<ND, KPT, Real, TS>() <= 160 * 1024, "LDS of one workgroup exceeds 160 KB");
   __shared__ __align__(16) char smem[smem_bytes<ND, KPT, Real, TS>()];
-  const int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
+  int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
+  int part = 0;
+  if (a.split) {
+    part = (int)((unsigned)sid >> 24);
+    sid &= 0xffffff;
+  }
   if (sid < 0 || sid >= a.M) return;   // a caller-provided slot out of range: nothing to do
-  sqp_solve<ND, KPT, Real, TS>(a, sid, smem);
+  sqp_solve<ND, KPT, Real, TS>(a, sid, part, smem);
 }
 
 // Mixed-shape kernel: every workgroup reads its solve's (n, kpt) and runs the
@@ -1444,21 +1598,26 @@ template <class Real, bool TS = false>
 __global__ __launch_bounds__(kBlock) void sqp_mixed_kernel(KArgs a) {
   static_assert(mixed_smem_bytes<Real, TS>() <= 160 * 1024, "LDS of one workgroup exceeds 160 KB");
   __shared__ __align__(16) char smem[mixed_smem_bytes<Real, TS>()];
-  const int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
+  int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
+  int part = 0;
+  if (a.split) {
+    part = (int)((unsigned)sid >> 24);
+    sid &= 0xffffff;
+  }
   if (sid < 0 || sid >= a.M) return;   // a caller-provided slot out of range: nothing to do
   const SolveDesc &D = a.desc[sid];
   switch (D.n * 8 + D.kpt) {
-    case 3 * 8 + 1: sqp_solve<3, 1, Real, TS>(a, sid, smem); break;
-    case 3 * 8 + 2: sqp_solve<3, 2, Real, TS>(a, sid, smem); break;
-    case 6 * 8 + 1: sqp_solve<6, 1, Real, TS>(a, sid, smem); break;
-    case 6 * 8 + 2: sqp_solve<6, 2, Real, TS>(a, sid, smem); break;
-    case 7 * 8 + 1: sqp_solve<7, 1, Real, TS>(a, sid, smem); break;
-    case 7 * 8 + 2: sqp_solve<7, 2, Real, TS>(a, sid, smem); break;
+    case 3 * 8 + 1: sqp_solve<3, 1, Real, TS>(a, sid, part, smem); break;
+    case 3 * 8 + 2: sqp_solve<3, 2, Real, TS>(a, sid, part, smem); break;
+    case 6 * 8 + 1: sqp_solve<6, 1, Real, TS>(a, sid, part, smem); break;
+    case 6 * 8 + 2: sqp_solve<6, 2, Real, TS>(a, sid, part, smem); break;
+    case 7 * 8 + 1: sqp_solve<7, 1, Real, TS>(a, sid, part, smem); break;
+    case 7 * 8 + 2: sqp_solve<7, 2, Real, TS>(a, sid, part, smem); break;
     case 6 * 8 + 4:
-      if constexpr (!TS) sqp_solve<6, 4, Real, false>(a, sid, smem);
+      if constexpr (!TS) sqp_solve<6, 4, Real, false>(a, sid, part, smem);
       break;
     case 7 * 8 + 4:
-      if constexpr (!TS) sqp_solve<7, 4, Real, false>(a, sid, smem);
+      if constexpr (!TS) sqp_solve<7, 4, Real, false>(a, sid, part, smem);
       break;
     default: break;  // the host only builds the shapes above
   }

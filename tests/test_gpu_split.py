@@ -1,0 +1,116 @@
+"""Long solves split across four workgroups (gato_set_split) against the oracle
+and against the one-workgroup form.
+
+Each part of a split solve holds the PCG rows of 32 knots and exchanges halo
+rows and inner products with the other parts at every PCG iteration; the PCG
+is the same method (Sec. III-B), with its inner products summed per part
+first. Bars: the oracle replay of the accepted steps within 1e-4 (PCG
+tolerance 1e-7, as the other trajectory tests), no exchange time-out, and the
+multipliers within 1e-6 of the one-workgroup form while not bit-identical to
+it (the split path ran).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workload as w
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2510_07625_amd as g  # noqa: E402
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _run(solves, p, parts, dispatch=None):
+    b = g.Batch.from_solves(solves, p)
+    b.set_split(parts)
+    if dispatch is not None:
+        b.set_dispatch(dispatch)
+    xs, goal, X, U = g.pack_inputs(solves)
+    st = b.stats_buffer(p.sqp_iters)
+    b.reset_warm_start()
+    b.step(xs, goal, X, U, p.sqp_iters, st)
+    torch.cuda.synchronize()
+    lam_d = b.get_multipliers()
+    torch.cuda.synchronize()
+    lam = lam_d.cpu().numpy()
+    out = (X.cpu().numpy().astype(np.float64), U.cpu().numpy().astype(np.float64),
+           g.Batch.decode_stats(st, b.M, p.sqp_iters), lam)
+    b.close()
+    return out
+
+
+def _replay(s, Xg, Ug, st, iters):
+    ref = oracle.sqp(s, oracle.Params(sqp_iters=iters, kkt_mode=2), alpha_replay=st["alpha"].astype(np.float64))
+    n, N = s.n, s.N
+    ex = np.abs(Xg[:N, :2 * n] - ref.X).max() / np.abs(ref.X).max()
+    eu = np.abs(Ug[:N - 1, :n] - ref.U).max() / np.abs(ref.U).max()
+    return ex, eu
+
+
+# N = 128: four full parts; 100: the last part holds 4 knots; 80: the last part
+# holds none (it still takes part in every exchange).
+@pytest.mark.parametrize("n,N", [(7, 128), (6, 100), (7, 80)])
+def test_split_solve_matches_the_oracle_and_the_one_workgroup_form(n, N):
+    _say(f"split n={n} N={N}")
+    solves = [w.chain_solve(31, i, n=n, N=N) for i in range(2)]
+    p = g.Params(sqp_iters=5, pcg_tol=1e-7)
+    Xs, Us, ss, ls = _run(solves, p, 4)
+    X1, U1, s1, l1 = _run(solves, p, 1)
+    assert not (ss["status"] & (g.ST_EXCHANGE | g.ST_NONFINITE | g.ST_PCG_MAXITER)).any(), ss["status"]
+    for i, s in enumerate(solves):
+        ex, eu = _replay(s, Xs[i], Us[i], ss[i], p.sqp_iters)
+        print(f"solve {i}: split vs oracle X {ex:.2e} U {eu:.2e}; PCG its split {ss[i]['pcg_iters'].tolist()} "
+              f"one-workgroup {s1[i]['pcg_iters'].tolist()}")
+        assert ex <= 1e-4 and eu <= 1e-4, (i, ex, eu)
+    # The same method: equal step sizes, multipliers close but summed in another
+    # order. Near the stopping value the PCG residual decreases slowly, so the
+    # summation order moves single counts by a few percent; the totals over the
+    # iterations stay within 5%.
+    np.testing.assert_array_equal(ss["alpha"], s1["alpha"])
+    ts, t1 = ss["pcg_iters"].sum(axis=1), s1["pcg_iters"].sum(axis=1)
+    assert np.all(np.abs(ts - t1) <= 0.05 * t1), (ts, t1)
+    scale = np.abs(l1).max()
+    assert np.abs(ls - l1).max() <= 1e-6 * scale
+    assert not np.array_equal(ls, l1), "the split path did not run"
+
+
+def test_split_uneven_batch_mixed_equals_grouped():
+    # Split and one-workgroup solves in one mixed-shape launch, and per shape group.
+    _say("split uneven")
+    solves = w.uneven_batch(33, M=10, horizons=(16, 64, 128))
+    assert any(s.N > 64 and s.n >= 6 for s in solves)
+    p = g.Params(sqp_iters=3, pcg_tol=1e-7)
+    Xm, Um, sm, lm = _run(solves, p, 4, g.DISPATCH_MIXED)
+    Xg, Ug, sg, lg = _run(solves, p, 4, g.DISPATCH_GROUPED)
+    np.testing.assert_array_equal(Xm, Xg)
+    np.testing.assert_array_equal(Um, Ug)
+    np.testing.assert_array_equal(lm, lg)
+    assert not (sm["status"] & (g.ST_EXCHANGE | g.ST_NONFINITE)).any()
+    for i, s in enumerate(solves):
+        if s.N > 64 and s.n >= 6:
+            ex, eu = _replay(s, Xm[i], Um[i], sm[i], p.sqp_iters)
+            assert ex <= 1e-4 and eu <= 1e-4, (i, ex, eu)
+
+
+def test_split_falls_back_when_the_launch_does_not_fit():
+    # 300 long solves need 1200 workgroups at once: the launch runs them one
+    # workgroup each, with the one-workgroup form's results.
+    _say("split fallback")
+    solves = [w.chain_solve(35, i % 4, n=7, N=128) for i in range(300)]
+    p = g.Params(sqp_iters=1, pcg_tol=1e-5)
+    Xs, Us, ss, ls = _run(solves, p, 4)
+    X1, U1, s1, l1 = _run(solves, p, 1)
+    np.testing.assert_array_equal(Xs, X1)
+    np.testing.assert_array_equal(ls, l1)
+    np.testing.assert_array_equal(ss["status"], s1["status"])
