@@ -258,25 +258,36 @@ __device__ __forceinline__ void xput(unsigned long long *w, unsigned tag, double
   __hip_atomic_store(w, t | (u & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   __hip_atomic_store(w + 1, t | (u >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// The value stored under `tag` at w; false (and 0) when the wait gave up or
-// `dead` (an earlier wait of the workgroup gave up) is set.
-__device__ __forceinline__ bool xget(unsigned long long *w, unsigned tag, bool dead, double &v) {
-  v = 0.0;
+// The values stored under `tag` at wa and wb (wb may be null: one value);
+// the four words are polled together, so a wait costs one round trip. False
+// (values 0) when the wait gave up or `dead` (an earlier wait of the
+// workgroup gave up) is set.
+__device__ __forceinline__ bool xget2(unsigned long long *wa, unsigned long long *wb, unsigned tag, bool dead,
+                                      double &va, double &vb) {
+  va = 0.0;
+  vb = 0.0;
   if (dead) return false;
-  unsigned long long lo = 0, hi = 0;
-  int n = 0;
-  for (;;) {
-    lo = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((unsigned)(lo >> 32) == tag) break;
-    if (++n >= kXSpin) return false;
+  unsigned long long a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+  const unsigned long long t = (unsigned long long)tag;
+  for (int n = 0;; ++n) {
+    a0 = __hip_atomic_load(wa, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a1 = __hip_atomic_load(wa + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (wb) {
+      b0 = __hip_atomic_load(wb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      b1 = __hip_atomic_load(wb + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      b0 = b1 = t << 32;
+    }
+    if ((a0 >> 32) == t && (a1 >> 32) == t && (b0 >> 32) == t && (b1 >> 32) == t) break;
+    if (n + 1 >= kXSpin) return false;
   }
-  for (;;) {
-    hi = __hip_atomic_load(w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if ((unsigned)(hi >> 32) == tag) break;
-    if (++n >= kXSpin) return false;
-  }
-  v = __longlong_as_double((long long)((hi << 32) | (lo & 0xffffffffull)));
+  va = __longlong_as_double((long long)((a1 << 32) | (a0 & 0xffffffffull)));
+  vb = __longlong_as_double((long long)((b1 << 32) | (b0 & 0xffffffffull)));
   return true;
+}
+__device__ __forceinline__ bool xget(unsigned long long *w, unsigned tag, bool dead, double &v) {
+  double unused;
+  return xget2(w, nullptr, tag, dead, v, unused);
 }
 
 template <int ND, int KPT, class Real, bool TS = false>
@@ -952,10 +963,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // Halo rows: the first own knot's row of vl goes to the left part, the last
     // one's of vr to the right part; the neighbours' rows land in vr[kf - 1]
     // and vl[kl + 1], read only by the lane groups that receive them.
-    auto xhalo_put = [&](unsigned e, Real (*vl)[G], Real (*vr)[G]) {
+    // (Published where the rows are formed, in share_S and prepare_P, for
+    // the exchange that follows them: number xe.)
+    auto xhalo_put_row = [&](int k, double left, double right) {
       if (lane < NX) {
-        if (has_l && slot == 0) xput(xslot(part, e) + 2 * lane, xtag(e), (double)vl[kf][lane]);
-        if (has_r && slot == kl - kf) xput(xslot(part, e) + 32 + 2 * lane, xtag(e), (double)vr[kl][lane]);
+        if (has_l && k == kf) xput(xslot(part, xe) + 2 * lane, xtag(xe), left);
+        if (has_r && k == kl) xput(xslot(part, xe) + 32 + 2 * lane, xtag(xe), right);
       }
     };
     auto xhalo_get = [&](unsigned e, Real (*vl)[G], Real (*vr)[G]) {
@@ -977,19 +990,30 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     auto xsum_put = [&](unsigned e, double s0, double s1, double s2) {
       if (tid < 3) xput(xslot(part, e) + 64 + 2 * tid, xtag(e), tid == 0 ? s0 : (tid == 1 ? s1 : s2));
     };
-    auto xsum_get = [&](unsigned e, double &s0, double &s1, double &s2) {
+    // Halo rows and sums of one exchange, all words polled together.
+    auto xhalo_sum_get = [&](unsigned e, Real (*vl)[G], Real (*vr)[G], double &s0, double &s1, double &s2) {
       const bool dead = sm.xfail != 0;
       const int l = tid & 63;
-      double v = 0.0;
-      if (l < 3 * kXParts) {
-        if (!xget(xslot(l / 3, e) + 64 + 2 * (l % 3), xtag(e), dead, v)) sm.xfail = 1;
+      const bool hl = has_l && slot == 0 && lane < NX;
+      const bool hr = has_r && slot == kl - kf && lane < NX;
+      unsigned long long *wh = hl ? xslot(part - 1, e) + 32 + 2 * lane : (hr ? xslot(part + 1, e) + 2 * lane : nullptr);
+      unsigned long long *ws = l < 3 * kXParts ? xslot(l / 3, e) + 64 + 2 * (l % 3) : nullptr;
+      double vh = 0.0, v = 0.0;
+      if (wh || ws) {
+        bool ok;
+        if (wh && ws) ok = xget2(wh, ws, xtag(e), dead, vh, v);
+        else if (wh) ok = xget(wh, xtag(e), dead, vh);
+        else ok = xget(ws, xtag(e), dead, v);
+        if (!ok) sm.xfail = 1;
       }
+      if (hl) vr[kf - 1][lane] = (Real)vh;
+      if (hr) vl[kl + 1][lane] = (Real)vh;
+      wave_sync();
       s0 = (lane_val(v, 0) + lane_val(v, 3)) + (lane_val(v, 6) + lane_val(v, 9));
       s1 = (lane_val(v, 1) + lane_val(v, 4)) + (lane_val(v, 7) + lane_val(v, 10));
       s2 = (lane_val(v, 2) + lane_val(v, 5)) + (lane_val(v, 8) + lane_val(v, 11));
     };
     auto xhalo = [&](Real (*vl)[G], Real (*vr)[G]) {
-      xhalo_put(xe, vl, vr);
       xhalo_get(xe, vl, vr);
       ++xe;
     };
@@ -1019,6 +1043,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           const bool valid = lane < NX;
           sm.pv[k][lane] = valid ? vals[p] : (Real)0;
           sm.sv[k][lane] = valid ? qown[p] * vals[p] : (Real)0;
+          if (xon) xhalo_put_row(k, (double)vals[p], (double)(qown[p] * vals[p]));
         }
       }
     };
@@ -1129,6 +1154,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           const Real z = group_dinv(p, vals[p]);
           sm.rv[k][lane] = (lane < NX) ? z : (Real)0;
           sm.gv[k][lane] = (lane < NX) ? qown[p] * z : (Real)0;
+          if (xon) xhalo_put_row(k, (double)z, (double)(qown[p] * z));
         }
       }
     };
@@ -1305,11 +1331,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           // Halo rows for finish_P and this part's inner products out; the
           // neighbours' rows and the sums over the parts in.
           const double e0 = (its == 0) ? pair_tree<kBlock / 64>(sm.red[redbuf][2]) : 0.0;
-          xhalo_put(xe, sm.rv, sm.gv);
           xsum_put(xe, gma, dlt, e0);
-          xhalo_get(xe, sm.rv, sm.gv);
           double g_, d_, e_;
-          xsum_get(xe, g_, d_, e_);
+          xhalo_sum_get(xe, sm.rv, sm.gv, g_, d_, e_);
           ++xe;
           gma = (Real)g_;
           dlt = (Real)d_;
