@@ -441,9 +441,12 @@ int gato_set_dispatch(gato_batch *b, int mode);
  * otherwise, under gato_step_graph and with parts = 1 every solve runs on one
  * workgroup. The inner products are summed per part first, so results differ
  * from the one-workgroup form at rounding level. A part that waits too long
- * for another sets GATO_ST_EXCHANGE. Errors: GATO_EINVAL (parts not 1 or 4).
+ * for another sets GATO_ST_EXCHANGE: every wait polls at most max_polls times
+ * (0: the default, 131072 polls, about 0.1 s), after which the part stops
+ * waiting for the rest of the call and its results are invalid. Errors:
+ * GATO_EINVAL (parts not 1 or 4, max_polls < 0).
  */
-int gato_set_split(gato_batch *b, int parts);
+int gato_set_split(gato_batch *b, int parts, int max_polls);
 
 /* One (n_dof, N) bucket of a batch and the mapping its solves use. */
 typedef struct {

@@ -109,7 +109,7 @@ def lib() -> C.CDLL:
         L.gato_plant_step.argtypes = [vp, ip, vp, vp, vp, vp, C.c_double, ip, vp, vp, vp]
         L.gato_set_external_force.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_set_dispatch.argtypes = [vp, ip]
-        L.gato_set_split.argtypes = [vp, ip]
+        L.gato_set_split.argtypes = [vp, ip, ip]
         L.gato_set_rho.argtypes = [vp, C.POINTER(C.c_double)]
         L.gato_serve_ctx_create.argtypes = [vp, ip, ip, C.POINTER(vp)]
         L.gato_serve_ctx_destroy.argtypes = [vp]
@@ -375,9 +375,10 @@ class Batch:
         _check(lib().gato_get_rho(self._h, r.ctypes.data_as(C.POINTER(C.c_double))))
         return r
 
-    def set_split(self, parts: int):
-        """gato_set_split: 4 (long solves on four workgroups where the launch fits) or 1."""
-        _check(lib().gato_set_split(self._h, int(parts)))
+    def set_split(self, parts: int, max_polls: int = 0):
+        """gato_set_split: 4 (long solves on four workgroups where the launch fits) or 1;
+        max_polls bounds every wait of a part for another (0: the default)."""
+        _check(lib().gato_set_split(self._h, int(parts), int(max_polls)))
 
     def set_dispatch(self, mode: int):
         """gato_set_dispatch: DISPATCH_AUTO, DISPATCH_GROUPED or DISPATCH_MIXED."""

@@ -122,6 +122,7 @@ struct gato_batch {
   unsigned long long *d_xch = nullptr;
   int n_split = 0;               // solves that can split
   int split_parts = gato::kSplitParts;   // gato_set_split: 4 (split where possible) or 1
+  int split_polls = 0;                   // polls before a wait gives up (0: the kernel's default)
   unsigned epoch = 0;            // tag epoch of the last split launch (1..65535)
   int *d_order_split_all = nullptr;
   int grid_split_all = 0;
@@ -516,6 +517,7 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split 
     as.split = 1;
     as.epoch = b->epoch;
     as.xch = b->d_xch;
+    as.xspin = b->split_polls;
   }
   if (use_mixed(b)) {
     if (split && b->grid_split_all > b->M) {
@@ -1110,10 +1112,12 @@ int gato_get_rho(gato_batch *b, double *h_rho) {
   return GATO_OK;
 }
 
-int gato_set_split(gato_batch *b, int parts) {
+int gato_set_split(gato_batch *b, int parts, int max_polls) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (parts != 1 && parts != gato::kSplitParts) return fail(GATO_EINVAL, "parts must be 1 or 4");
+  if (max_polls < 0) return fail(GATO_EINVAL, "max_polls must be >= 0");
   b->split_parts = parts;
+  b->split_polls = max_polls;
   return GATO_OK;
 }
 

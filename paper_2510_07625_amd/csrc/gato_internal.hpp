@@ -92,6 +92,7 @@ struct KArgs {
   int split;
   unsigned epoch;
   unsigned long long *xch;
+  int xspin;                 // polls before a wait gives up (0: the default)
 };
 
 // Closed-loop plant step (gato_plant_step).

@@ -99,7 +99,8 @@ struct Smem {
   float alpha[kMaxAlpha];
   float xs[G], xg[G], c0[G];
   int bad[2];              // per-iteration flag, indexed by iteration parity
-  int xfail, xpad;         // split solve: a wait for another part gave up
+  int xfail, xpad[3];      // split solve: a wait for another part gave up (16 bytes: keeps
+                           // the blocks below 16-byte aligned for 128-bit LDS reads)
   float A[LB][NX * NX];    // A_k
   float B[LB][NX * NU];    // B_k
   float Dinv[LB][NX * NX]; // inverse diagonal blocks of S~
@@ -249,7 +250,7 @@ constexpr int kXSlots = 4;
 constexpr int kXLam = 1024;                   // words: multipliers of 32 knots x 16 rows
 constexpr int kXPart = kXSlots * kXSlot + kXLam;
 constexpr int kXParts = 4;
-constexpr int kXSpin = 1 << 17;               // polls before a wait gives up
+constexpr int kXSpin = 1 << 17;               // polls before a wait gives up (default)
 static_assert(kXParts == kSplitParts && kXParts * kXPart == kXWordsPerSolve, "exchange layout");
 
 __device__ __forceinline__ void xput(unsigned long long *w, unsigned tag, double v) {
@@ -263,7 +264,7 @@ __device__ __forceinline__ void xput(unsigned long long *w, unsigned tag, double
 // (values 0) when the wait gave up or `dead` (an earlier wait of the
 // workgroup gave up) is set.
 __device__ __forceinline__ bool xget2(unsigned long long *wa, unsigned long long *wb, unsigned tag, bool dead,
-                                      double &va, double &vb) {
+                                      int spin, double &va, double &vb) {
   va = 0.0;
   vb = 0.0;
   if (dead) return false;
@@ -279,15 +280,15 @@ __device__ __forceinline__ bool xget2(unsigned long long *wa, unsigned long long
       b0 = b1 = t << 32;
     }
     if ((a0 >> 32) == t && (a1 >> 32) == t && (b0 >> 32) == t && (b1 >> 32) == t) break;
-    if (n + 1 >= kXSpin) return false;
+    if (n + 1 >= spin) return false;
   }
   va = __longlong_as_double((long long)((a1 << 32) | (a0 & 0xffffffffull)));
   vb = __longlong_as_double((long long)((b1 << 32) | (b0 & 0xffffffffull)));
   return true;
 }
-__device__ __forceinline__ bool xget(unsigned long long *w, unsigned tag, bool dead, double &v) {
+__device__ __forceinline__ bool xget(unsigned long long *w, unsigned tag, bool dead, int spin, double &v) {
   double unused;
-  return xget2(w, nullptr, tag, dead, v, unused);
+  return xget2(w, nullptr, tag, dead, spin, v, unused);
 }
 
 template <int ND, int KPT, class Real, bool TS = false>
@@ -955,6 +956,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     bool xon = split;
     auto own = [&](int p) { return !xon || p == part; };
     unsigned long long *xb = split ? a.xch + D.xch_off : nullptr;
+    const int xspin = a.xspin > 0 ? a.xspin : kXSpin;
     auto xtag = [&](unsigned e) { return ((a.epoch & 0xffffu) << 16) | (e & 0xffffu); };
     auto xslot = [&](int q, unsigned e) { return xb + (size_t)q * kXPart + (size_t)(e % kXSlots) * kXSlot; };
     const int kf = part * SLOTS, kl = min(kf + SLOTS, N) - 1;   // own knots kf..kl (none when kf >= N)
@@ -976,11 +978,11 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       if (lane < NX) {
         double v;
         if (has_l && slot == 0) {
-          if (!xget(xslot(part - 1, e) + 32 + 2 * lane, xtag(e), dead, v)) sm.xfail = 1;
+          if (!xget(xslot(part - 1, e) + 32 + 2 * lane, xtag(e), dead, xspin, v)) sm.xfail = 1;
           vr[kf - 1][lane] = (Real)v;
         }
         if (has_r && slot == kl - kf) {
-          if (!xget(xslot(part + 1, e) + 2 * lane, xtag(e), dead, v)) sm.xfail = 1;
+          if (!xget(xslot(part + 1, e) + 2 * lane, xtag(e), dead, xspin, v)) sm.xfail = 1;
           vl[kl + 1][lane] = (Real)v;
         }
       }
@@ -1001,9 +1003,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       double vh = 0.0, v = 0.0;
       if (wh || ws) {
         bool ok;
-        if (wh && ws) ok = xget2(wh, ws, xtag(e), dead, vh, v);
-        else if (wh) ok = xget(wh, xtag(e), dead, vh);
-        else ok = xget(ws, xtag(e), dead, v);
+        if (wh && ws) ok = xget2(wh, ws, xtag(e), dead, xspin, vh, v);
+        else if (wh) ok = xget(wh, xtag(e), dead, xspin, vh);
+        else ok = xget(ws, xtag(e), dead, xspin, v);
         if (!ok) sm.xfail = 1;
       }
       if (hl) vr[kf - 1][lane] = (Real)vh;
@@ -1029,7 +1031,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       for (int p = 0; p < KPT; ++p) {
         if (p != part && slot + p * SLOTS < N && lane < NX) {
           double v;
-          if (!xget(xb + (size_t)p * kXPart + kXSlots * kXSlot + 2 * (slot * G + lane), xtag(e), dead, v))
+          if (!xget(xb + (size_t)p * kXPart + kXSlots * kXSlot + 2 * (slot * G + lane), xtag(e), dead, xspin, v))
             sm.xfail = 1;
           lam[p] = (Real)v;
         }

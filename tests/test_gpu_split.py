@@ -114,3 +114,38 @@ def test_split_falls_back_when_the_launch_does_not_fit():
     np.testing.assert_array_equal(Xs, X1)
     np.testing.assert_array_equal(ls, l1)
     np.testing.assert_array_equal(ss["status"], s1["status"])
+
+
+def test_split_wait_bound_reports_the_exchange_and_returns():
+    # Failure handling, forced from the host: one poll per wait, so that parts
+    # give up waiting for each other. Every kernel still finishes; the split
+    # solves report GATO_ST_EXCHANGE, the one-workgroup solve of the same
+    # launch is untouched, and the next call with the default bound is clean
+    # (stale exchange words carry another launch's tag).
+    _say("split wait bound")
+    solves = [w.chain_solve(37, 0, n=7, N=128), w.chain_solve(37, 1, n=7, N=32)]
+    p = g.Params(sqp_iters=3, pcg_tol=1e-7)
+    b = g.Batch.from_solves(solves, p)
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    st = b.stats_buffer(3)
+    b.set_split(4, 1)
+    X, U = X0.clone(), U0.clone()
+    b.reset_warm_start()
+    b.step(xs, goal, X, U, 3, st)
+    torch.cuda.synchronize()
+    s_bad = g.Batch.decode_stats(st, b.M, 3)
+    Xb = X.cpu().numpy()
+    b.set_split(4)
+    X, U = X0.clone(), U0.clone()
+    b.reset_warm_start()
+    b.step(xs, goal, X, U, 3, st)
+    torch.cuda.synchronize()
+    s_ok = g.Batch.decode_stats(st, b.M, 3)
+    Xok = X.cpu().numpy()
+    b.close()
+    assert (s_bad["status"][0] & g.ST_EXCHANGE).any(), s_bad["status"]
+    assert not (s_bad["status"][1] & g.ST_EXCHANGE).any()
+    np.testing.assert_array_equal(Xb[1], Xok[1])
+    assert not (s_ok["status"] & g.ST_EXCHANGE).any(), s_ok["status"]
+    ex, eu = _replay(solves[0], Xok[0].astype(np.float64), U.cpu().numpy()[0].astype(np.float64), s_ok[0], 3)
+    assert ex <= 1e-4 and eu <= 1e-4, (ex, eu)
