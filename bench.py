@@ -563,7 +563,7 @@ def main():
     achieved = flops_launch / (kern.mean() * 1e-3)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_ALU / 1e12, unit="TFLOP/s",
                 frac=achieved / PEAK_ALU, traffic=measured_traffic(),
-                kernel="gato::sqp_kernel<7, 1, double, false>",
+                kernel="gato::sqp_kernel<7, 1, double, false, false>",
                 flops_per_launch=flops_launch, avg_kernel_ms=float(kern.mean()),
                 pcg_iters_per_solve=float(pcg.sum(axis=1).mean()))
     sweep, plain = [], []

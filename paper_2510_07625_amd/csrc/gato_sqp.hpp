@@ -291,7 +291,7 @@ __device__ __forceinline__ bool xget(unsigned long long *w, unsigned tag, bool d
   return xget2(w, nullptr, tag, dead, spin, v, unused);
 }
 
-template <int ND, int KPT, class Real, bool TS = false>
+template <int ND, int KPT, class Real, bool TS = false, bool SPLIT = false>
 __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, int sid, int part, char *smem_raw) {
   using Sh = Shape<ND>;
   constexpr int NX = Sh::NX, NU = Sh::NU, G = Sh::G, SLOTS = Sh::SLOTS;
@@ -311,7 +311,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   // Split solve (four knots per lane group, FP64 Schur): four workgroups run
   // the same SQP iteration, each with its own workspace, and share the PCG:
   // part j owns the knots 32 j .. 32 j + 31 (p == j). Only part 0 writes results.
-  constexpr bool kSplitOk = (KPT == 4) && (sizeof(Real) == 8) && !TS;
+  // (SPLIT: compiled into kernels of their own, so that the one-workgroup
+  // kernels carry none of the exchange code.)
+  constexpr bool kSplitOk = SPLIT && (KPT == 4) && (sizeof(Real) == 8) && !TS;
   const bool split = kSplitOk && a.split && a.mode == kModeSqp && D.xch_off >= 0 && part >= 0 && part < kXParts;
   const bool writer = !split || part == 0;
   char *ws = a.ws + D.ws_off + (split ? (int64_t)part * D.ws_part : 0);
@@ -1588,18 +1590,20 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   }
 }
 
-template <int ND, int KPT, class Real, bool TS = false>
+template <int ND, int KPT, class Real, bool TS = false, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void sqp_kernel(KArgs a) {
   static_assert(smem_bytes<ND, KPT, Real, TS>() <= 160 * 1024, "LDS of one workgroup exceeds 160 KB");
   __shared__ __align__(16) char smem[smem_bytes<ND, KPT, Real, TS>()];
   int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
   int part = 0;
-  if (a.split) {
-    part = (int)((unsigned)sid >> 24);
-    sid &= 0xffffff;
+  if constexpr (SPLIT) {
+    if (a.split) {
+      part = (int)((unsigned)sid >> 24);
+      sid &= 0xffffff;
+    }
   }
   if (sid < 0 || sid >= a.M) return;   // a caller-provided slot out of range: nothing to do
-  sqp_solve<ND, KPT, Real, TS>(a, sid, part, smem);
+  sqp_solve<ND, KPT, Real, TS, SPLIT>(a, sid, part, smem);
 }
 
 // Mixed-shape kernel: every workgroup reads its solve's (n, kpt) and runs the
@@ -1620,15 +1624,17 @@ constexpr size_t mixed_smem_bytes() {
   return m;
 }
 
-template <class Real, bool TS = false>
+template <class Real, bool TS = false, bool SPLIT = false>
 __global__ __launch_bounds__(kBlock) void sqp_mixed_kernel(KArgs a) {
   static_assert(mixed_smem_bytes<Real, TS>() <= 160 * 1024, "LDS of one workgroup exceeds 160 KB");
   __shared__ __align__(16) char smem[mixed_smem_bytes<Real, TS>()];
   int sid = a.order ? a.order[blockIdx.x] : a.sid_base + (int)blockIdx.x;
   int part = 0;
-  if (a.split) {
-    part = (int)((unsigned)sid >> 24);
-    sid &= 0xffffff;
+  if constexpr (SPLIT) {
+    if (a.split) {
+      part = (int)((unsigned)sid >> 24);
+      sid &= 0xffffff;
+    }
   }
   if (sid < 0 || sid >= a.M) return;   // a caller-provided slot out of range: nothing to do
   const SolveDesc &D = a.desc[sid];
@@ -1640,10 +1646,10 @@ __global__ __launch_bounds__(kBlock) void sqp_mixed_kernel(KArgs a) {
     case 7 * 8 + 1: sqp_solve<7, 1, Real, TS>(a, sid, part, smem); break;
     case 7 * 8 + 2: sqp_solve<7, 2, Real, TS>(a, sid, part, smem); break;
     case 6 * 8 + 4:
-      if constexpr (!TS) sqp_solve<6, 4, Real, false>(a, sid, part, smem);
+      if constexpr (!TS) sqp_solve<6, 4, Real, false, SPLIT>(a, sid, part, smem);
       break;
     case 7 * 8 + 4:
-      if constexpr (!TS) sqp_solve<7, 4, Real, false>(a, sid, part, smem);
+      if constexpr (!TS) sqp_solve<7, 4, Real, false, SPLIT>(a, sid, part, smem);
       break;
     default: break;  // the host only builds the shapes above
   }

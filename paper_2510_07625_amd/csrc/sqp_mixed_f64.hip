@@ -13,7 +13,7 @@ hipError_t launch_sqp_mixed_f64(int grid, const KArgs &a, hipStream_t s) {
 // With split long solves: a cooperative launch (the parts of a solve are
 // resident together).
 hipError_t launch_sqp_mixed_f64_split(int grid, const KArgs &a, hipStream_t s) {
-  const void *f = reinterpret_cast<const void *>(&sqp_mixed_kernel<double>);
+  const void *f = reinterpret_cast<const void *>(&sqp_mixed_kernel<double, false, true>);
   const hipError_t e = cooperative_fits(f, grid);
   if (e != hipSuccess) return e;
   KArgs arg = a;
