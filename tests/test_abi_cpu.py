@@ -97,6 +97,7 @@ def test_invalid_arguments_are_rejected_on_the_host():
     L = g.lib()
     n = C.c_int()
     assert L.gato_set_dispatch(None, 0) == g.GATO_EINVAL
+    assert L.gato_set_split(None, 4, 0) == g.GATO_EINVAL
     assert L.gato_buckets(None, None, 0, C.byref(n)) == g.GATO_EINVAL
     assert L.gato_set_mapping(None, 7, 32, 1) == g.GATO_EINVAL
     assert L.gato_autotune(None, None, None, None, None, 1, 1) == g.GATO_EINVAL
