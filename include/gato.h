@@ -438,8 +438,8 @@ int gato_set_dispatch(gato_batch *b, int mode);
  * is computed by each part alike, and part 0 writes the results. The split
  * applies to gato_step, gato_solve and gato_profile_phases when every
  * workgroup of the launch fits the device at once (a cooperative launch);
- * otherwise, under gato_step_graph and with parts = 1 every solve runs on one
- * workgroup. The inner products are summed per part first, so results differ
+ * otherwise, under gato_step_graph or any stream capture, and with parts = 1
+ * every solve runs on one workgroup. The inner products are summed per part first, so results differ
  * from the one-workgroup form at rounding level. A part that waits too long
  * for another sets GATO_ST_EXCHANGE: every wait polls at most max_polls times
  * (0: the default, 131072 polls, about 0.1 s), after which the part stops

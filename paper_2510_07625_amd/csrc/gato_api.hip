@@ -509,8 +509,12 @@ hipError_t launch_mixed(const gato_batch *b, int grid, const gato::KArgs &a, hip
 // capture), the batch has it switched off, or the launch would not fit the chip
 // at once; then they run one workgroup each.
 int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split = true) {
-  const bool split = allow_split && a.mode == gato::kModeSqp && b->split_parts == gato::kSplitParts &&
-                     b->n_split > 0;
+  bool split = allow_split && a.mode == gato::kModeSqp && b->split_parts == gato::kSplitParts && b->n_split > 0;
+  if (split) {
+    // A stream under capture (the caller's own graph) takes the one-workgroup form.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) split = false;
+  }
   gato::KArgs as = a;
   if (split) {
     b->epoch = b->epoch % 65535u + 1u;
