@@ -179,10 +179,10 @@ def precision_report(g, torch, M, steps, pcg_tol):
 def uneven_report(g, torch, M=128, steps=3, seed=0):
     """Uneven batch: M solves with DoF from {3, 6, 7} and N from {16, 32, 64, 128},
     10 SQP iterations; per-shape launches against one mixed-shape launch, the
-    autotuned mapping, and the graph-captured step; both precisions. With FP64
-    Schur rows the long solves (6-7 DoF, N > 64) split across four workgroups
-    in the eager launches (not under graph capture); `one_workgroup_ms` is the
-    mixed-shape launch with the split switched off."""
+    autotuned mapping, and the graph-captured step; both precisions. The long
+    solves (6-7 DoF, N > 64) split across four workgroups in the eager launches
+    (not under graph capture); `one_workgroup_ms` is the mixed-shape launch with
+    the split switched off."""
     import workload as w
     solves = w.uneven_batch(seed, M=M)
     xs, goal, X0, U0 = g.pack_inputs(solves)
@@ -213,11 +213,9 @@ def uneven_report(g, torch, M=128, steps=3, seed=0):
         buckets = b.autotune(xs, goal, X0, U0, n_iters=2, reps=3)
         t_tuned = timed(b)
         t_graph = timed(b, graph=True)
-        t_one = None
-        if fp64:
-            b.set_split(1)
-            t_one = timed(b)
-            b.set_split(4)
+        b.set_split(1)
+        t_one = timed(b)
+        b.set_split(4)
         b.close()
         out["fp64-schur" if fp64 else "fp32"] = dict(
             grouped_ms=t_grouped, mixed_ms=t_mixed, tuned_mixed_ms=t_tuned, tuned_mixed_graph_ms=t_graph,

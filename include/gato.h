@@ -430,7 +430,7 @@ int gato_set_dispatch(gato_batch *b, int mode);
 
 /*
  * Multi-CU split of long solves. A solve with four knots per lane group (6-7
- * DoF, N > 64) in a batch with schur_fp64 = 1 and no tip tracking runs on
+ * DoF, N > 64) in a batch without tip tracking runs on
  * parts = 4 workgroups (the default): each holds the PCG rows of 32 knots in
  * registers (the PCG of Sec. III-B: the same Eq. (5) system, preconditioner
  * and stopping rule), and the four exchange halo rows and inner products

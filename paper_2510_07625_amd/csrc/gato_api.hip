@@ -21,9 +21,10 @@ hipError_t launch_sqp_n6(int kpt, bool f64, int grid, const KArgs &a, hipStream_
 hipError_t launch_sqp_n7(int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
 hipError_t launch_sqp_mixed_f32(int grid, const KArgs &a, hipStream_t s);
 hipError_t launch_sqp_mixed_f64(int grid, const KArgs &a, hipStream_t s);
-hipError_t launch_sqp_n6_split(int grid, const KArgs &a, hipStream_t s);
-hipError_t launch_sqp_n7_split(int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_n6_split(int grid, bool f64, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_n7_split(int grid, bool f64, const KArgs &a, hipStream_t s);
 hipError_t launch_sqp_mixed_f64_split(int grid, const KArgs &a, hipStream_t s);
+hipError_t launch_sqp_mixed_f32_split(int grid, const KArgs &a, hipStream_t s);
 
 hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s) {
   if (a.pref) return launch_sqp_task(nd, kpt, f64, grid, a, s);   // a batch with task-space solves
@@ -117,7 +118,7 @@ struct gato_batch {
   };
   std::vector<Group> groups;
   int *d_order_all = nullptr;  // every solve, decreasing work (mixed-shape launch)
-  // Split long solves (6-7 DoF, N > 64, FP64 Schur): four workgroups per solve
+  // Split long solves (6-7 DoF, N > 64): four workgroups per solve
   // sharing the PCG through the exchange words, when the launch fits the chip.
   unsigned long long *d_xch = nullptr;
   int n_split = 0;               // solves that can split
@@ -366,9 +367,9 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     desc[i].offD = (int64_t)l.offD;
     desc[i].offT = (int64_t)l.offT;
     desc[i].offAT = (int64_t)l.offAT;
-    // Long solves (four knots per lane group) of an FP64-Schur batch can split:
-    // a workspace per part and an exchange area.
-    const bool can_split = desc[i].kpt == 4 && prm.schur_fp64 && !task;
+    // Long solves (four knots per lane group) can split: a workspace per part
+    // and an exchange area.
+    const bool can_split = desc[i].kpt == 4 && !task;
     desc[i].ws_part = can_split ? (int64_t)l.total : 0;
     desc[i].xch_off = can_split ? xwords : -1;
     if (can_split) {
@@ -526,7 +527,8 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split 
   if (use_mixed(b)) {
     if (split && b->grid_split_all > b->M) {
       as.order = b->d_order_split_all;
-      const hipError_t e = gato::launch_sqp_mixed_f64_split(b->grid_split_all, as, s);
+      const hipError_t e = b->p.schur_fp64 ? gato::launch_sqp_mixed_f64_split(b->grid_split_all, as, s)
+                                           : gato::launch_sqp_mixed_f32_split(b->grid_split_all, as, s);
       if (e == hipSuccess) return GATO_OK;
       if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(e, "kernel launch (split)");
       (void)hipGetLastError();
@@ -538,10 +540,10 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split 
   }
   const bool f64 = b->p.schur_fp64 != 0;
   for (const auto &g : b->groups) {
-    if (split && g.d_order_split && f64 && (g.n == 6 || g.n == 7)) {
+    if (split && g.d_order_split && (g.n == 6 || g.n == 7)) {
       as.order = g.d_order_split;
-      const hipError_t e = g.n == 7 ? gato::launch_sqp_n7_split(g.grid_split, as, s)
-                                    : gato::launch_sqp_n6_split(g.grid_split, as, s);
+      const hipError_t e = g.n == 7 ? gato::launch_sqp_n7_split(g.grid_split, f64, as, s)
+                                    : gato::launch_sqp_n6_split(g.grid_split, f64, as, s);
       if (e == hipSuccess) continue;
       if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(e, "kernel launch (split)");
       (void)hipGetLastError();

@@ -308,12 +308,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   const int N = D.N;
   const float h = D.dt;
   const int n_alpha = a.n_alpha;
-  // Split solve (four knots per lane group, FP64 Schur): four workgroups run
+  // Split solve (four knots per lane group): four workgroups run
   // the same SQP iteration, each with its own workspace, and share the PCG:
   // part j owns the knots 32 j .. 32 j + 31 (p == j). Only part 0 writes results.
   // (SPLIT: compiled into kernels of their own, so that the one-workgroup
   // kernels carry none of the exchange code.)
-  constexpr bool kSplitOk = SPLIT && (KPT == 4) && (sizeof(Real) == 8) && !TS;
+  constexpr bool kSplitOk = SPLIT && (KPT == 4) && !TS;
   const bool split = kSplitOk && a.split && a.mode == kModeSqp && D.xch_off >= 0 && part >= 0 && part < kXParts;
   const bool writer = !split || part == 0;
   char *ws = a.ws + D.ws_off + (split ? (int64_t)part * D.ws_part : 0);
@@ -995,11 +995,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       if (tid < 3) xput(xslot(part, e) + 64 + 2 * tid, xtag(e), tid == 0 ? s0 : (tid == 1 ? s1 : s2));
     };
     // Halo rows and sums of one exchange, all words polled together.
-    auto xhalo_sum_get = [&](unsigned e, Real (*vl)[G], Real (*vr)[G], double &s0, double &s1, double &s2) {
+    auto xhalo_sum_get = [&](unsigned e, bool halo, Real (*vl)[G], Real (*vr)[G], double &s0, double &s1,
+                             double &s2) {
       const bool dead = sm.xfail != 0;
       const int l = tid & 63;
-      const bool hl = has_l && slot == 0 && lane < NX;
-      const bool hr = has_r && slot == kl - kf && lane < NX;
+      const bool hl = halo && has_l && slot == 0 && lane < NX;
+      const bool hr = halo && has_r && slot == kl - kf && lane < NX;
       unsigned long long *wh = hl ? xslot(part - 1, e) + 32 + 2 * lane : (hr ? xslot(part + 1, e) + 2 * lane : nullptr);
       unsigned long long *ws = l < 3 * kXParts ? xslot(l / 3, e) + 64 + 2 * (l % 3) : nullptr;
       double vh = 0.0, v = 0.0;
@@ -1019,6 +1020,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     };
     auto xhalo = [&](Real (*vl)[G], Real (*vr)[G]) {
       xhalo_get(xe, vl, vr);
+      ++xe;
+    };
+    // Sums over the parts of three workgroup totals (no halo rows).
+    auto xsums = [&](double &s0, double &s1, double &s2) {
+      xsum_put(xe, s0, s1, s2);
+      xhalo_sum_get(xe, false, sm.pv, sm.sv, s0, s1, s2);
       ++xe;
     };
     // Every part's multipliers to every part (after the PCG).
@@ -1233,11 +1240,18 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           vp[p] = u[p];
         }
         block_sum<3>(sm.red, redbuf, sums);
+        if (xon) {
+          double t0 = (double)sums[0], t1 = (double)sums[1], t2 = (double)sums[2];
+          xsums(t0, t1, t2);
+          sums[0] = (Acc)t0;
+          sums[2] = (Acc)t2;
+        }
         Acc g = sums[0];
         const Acc stop_a = (Acc)a.pcg_tol * (Acc)a.pcg_tol * sums[2];
         while (g > stop_a && its < max_it) {
           share_S(vp);
           __syncthreads();
+          if (xon) xhalo(sm.pv, sm.sv);
           Acc pw[1] = {0};
 #pragma unroll
           for (int p = 0; p < KPT; ++p) {
@@ -1245,6 +1259,11 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             pw[0] += (Acc)vp[p] * (Acc)w[p];
           }
           block_sum<1>(sm.red, redbuf, pw);
+          if (xon) {
+            double t0 = (double)pw[0], t1 = 0.0, t2 = 0.0;
+            xsums(t0, t1, t2);
+            pw[0] = (Acc)t0;
+          }
           const Real alpha = (Real)(g / pw[0]);
 #pragma unroll
           for (int p = 0; p < KPT; ++p) {
@@ -1254,6 +1273,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           if constexpr (kFactP) prepare_P(r);
           else share_P(r, sm.rv);
           __syncthreads();
+          if (xon) xhalo(sm.rv, sm.gv);
           Acc rz[1] = {0};
 #pragma unroll
           for (int p = 0; p < KPT; ++p) {
@@ -1262,6 +1282,11 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             rz[0] += (Acc)r[p] * (Acc)u[p];
           }
           block_sum<1>(sm.red, redbuf, rz);
+          if (xon) {
+            double t0 = (double)rz[0], t1 = 0.0, t2 = 0.0;
+            xsums(t0, t1, t2);
+            rz[0] = (Acc)t0;
+          }
           const Real beta = (Real)(rz[0] / g);
           g = rz[0];
 #pragma unroll
@@ -1337,7 +1362,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           const double e0 = (its == 0) ? pair_tree<kBlock / 64>(sm.red[redbuf][2]) : 0.0;
           xsum_put(xe, gma, dlt, e0);
           double g_, d_, e_;
-          xhalo_sum_get(xe, sm.rv, sm.gv, g_, d_, e_);
+          xhalo_sum_get(xe, true, sm.rv, sm.gv, g_, d_, e_);
           ++xe;
           gma = (Real)g_;
           dlt = (Real)d_;

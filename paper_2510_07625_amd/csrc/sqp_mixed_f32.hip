@@ -10,4 +10,16 @@ hipError_t launch_sqp_mixed_f32(int grid, const KArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
+// With split long solves: a cooperative launch (the parts of a solve are
+// resident together).
+hipError_t launch_sqp_mixed_f32_split(int grid, const KArgs &a, hipStream_t s) {
+  const void *f = reinterpret_cast<const void *>(&sqp_mixed_kernel<float, false, true>);
+  const hipError_t e = cooperative_fits(f, grid);
+  if (e != hipSuccess) return e;
+  KArgs arg = a;
+  void *args[] = {&arg};
+  return hipLaunchCooperativeKernel(f, dim3(grid),
+                                    dim3(kBlock), args, 0, s);
+}
+
 }  // namespace gato

@@ -20,8 +20,9 @@ hipError_t launch_sqp_n6(int kpt, bool f64, int grid, const KArgs &a, hipStream_
 
 // Split long solves (four knots per lane group, FP64 Schur): a cooperative
 // launch, so that the parts of a solve are resident together.
-hipError_t launch_sqp_n6_split(int grid, const KArgs &a, hipStream_t s) {
-  const void *f = reinterpret_cast<const void *>(&sqp_kernel<6, 4, double, false, true>);
+hipError_t launch_sqp_n6_split(int grid, bool f64, const KArgs &a, hipStream_t s) {
+  const void *f = f64 ? reinterpret_cast<const void *>(&sqp_kernel<6, 4, double, false, true>)
+                      : reinterpret_cast<const void *>(&sqp_kernel<6, 4, float, false, true>);
   const hipError_t e = cooperative_fits(f, grid);
   if (e != hipSuccess) return e;
   KArgs arg = a;
