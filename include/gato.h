@@ -430,21 +430,24 @@ int gato_set_dispatch(gato_batch *b, int mode);
 
 /*
  * Multi-CU split of long solves. A solve with four knots per lane group (6-7
- * DoF, N > 64) in a batch without tip tracking runs on
- * parts = 4 workgroups (the default): each holds the PCG rows of 32 knots in
- * registers (the PCG of Sec. III-B: the same Eq. (5) system, preconditioner
- * and stopping rule), and the four exchange halo rows and inner products
- * through device memory at every PCG iteration; the rest of the SQP iteration
- * is computed by each part alike, and part 0 writes the results. The split
- * applies to gato_step, gato_solve and gato_profile_phases when every
- * workgroup of the launch fits the device at once (a cooperative launch);
- * otherwise, under gato_step_graph or any stream capture, and with parts = 1
- * every solve runs on one workgroup. The inner products are summed per part first, so results differ
- * from the one-workgroup form at rounding level. A part that waits too long
- * for another sets GATO_ST_EXCHANGE: every wait polls at most max_polls times
- * (0: the default, 131072 polls, about 0.1 s), after which the part stops
- * waiting for the rest of the call and its results are invalid. Errors:
- * GATO_EINVAL (parts not 1 or 4, max_polls < 0).
+ * DoF, N > 64) in a batch without tip tracking runs on four workgroups (parts
+ * = 4, the default), each holding the PCG rows of 32 knots, or on two, each
+ * holding those of 64 knots, when four workgroups per solve do not fit the
+ * device at once. The parts run the PCG of Sec. III-B (the same Eq. (5)
+ * system, preconditioner and stopping rule) together, exchanging halo rows and
+ * inner products through device memory at every PCG iteration; the rest of the
+ * SQP iteration is computed by each part alike, and part 0 writes the results.
+ * The split applies to gato_step, gato_solve and gato_profile_phases as a
+ * cooperative launch (every workgroup resident at once). Under gato_step_graph
+ * or any stream capture, with parts = 1, and when even two workgroups per
+ * solve do not fit, every solve runs on one workgroup. The inner products are
+ * summed per part first, so results differ from the one-workgroup form at
+ * rounding level. A part that waits too long for another sets
+ * GATO_ST_EXCHANGE: every wait polls at most max_polls times (0: the default,
+ * 131072 polls, about 0.1 s), after which the part stops waiting for the rest
+ * of the call and its results are invalid. A batch allocates four workspaces
+ * and an exchange area (42 KB) per such solve. Errors: GATO_EINVAL (parts not
+ * 1 or 4, max_polls < 0).
  */
 int gato_set_split(gato_batch *b, int parts, int max_polls);
 

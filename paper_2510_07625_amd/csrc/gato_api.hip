@@ -113,8 +113,8 @@ struct gato_batch {
   struct Group {
     int n, kpt, count;
     int *d_order;
-    int *d_order_split;   // the same with four blocks per split solve (or null)
-    int grid_split;
+    int *d_order_split[2];   // the same with four / two blocks per split solve (or null)
+    int grid_split[2];
   };
   std::vector<Group> groups;
   int *d_order_all = nullptr;  // every solve, decreasing work (mixed-shape launch)
@@ -125,8 +125,8 @@ struct gato_batch {
   int split_parts = gato::kSplitParts;   // gato_set_split: 4 (split where possible) or 1
   int split_polls = 0;                   // polls before a wait gives up (0: the kernel's default)
   unsigned epoch = 0;            // tag epoch of the last split launch (1..65535)
-  int *d_order_split_all = nullptr;
-  int grid_split_all = 0;
+  int *d_order_split_all[2] = {nullptr, nullptr};   // four / two blocks per split solve
+  int grid_split_all[2] = {0, 0};
   int dispatch = GATO_DISPATCH_AUTO;
   std::vector<float> tuned_ms;  // per solve: the tuned time of its bucket (0 if never tuned)
   // Captured step (gato_step_graph).
@@ -145,18 +145,21 @@ static int rebuild_dispatch(gato_batch *b) {
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(desc)");
   for (auto &g : b->groups) {
     if (g.d_order) (void)hipFree(g.d_order);
-    if (g.d_order_split) (void)hipFree(g.d_order_split);
+    for (int *o : g.d_order_split)
+      if (o) (void)hipFree(o);
   }
   b->groups.clear();
-  if (b->d_order_split_all) (void)hipFree(b->d_order_split_all);
-  b->d_order_split_all = nullptr;
-  b->grid_split_all = 0;
-  // A split solve takes four consecutive blocks: the part in bits 24..31.
-  auto expand = [&](const std::vector<int> &v) {
+  for (int q = 0; q < 2; ++q) {
+    if (b->d_order_split_all[q]) (void)hipFree(b->d_order_split_all[q]);
+    b->d_order_split_all[q] = nullptr;
+    b->grid_split_all[q] = 0;
+  }
+  // A split solve takes `parts` consecutive blocks: the part in bits 24..31.
+  auto expand = [&](const std::vector<int> &v, int parts) {
     std::vector<int> o;
     for (int i : v) {
       if (desc[i].xch_off >= 0 && desc[i].kpt == 4)
-        for (int j = 0; j < gato::kSplitParts; ++j) o.push_back(i | (j << 24));
+        for (int j = 0; j < parts; ++j) o.push_back(i | (j << 24));
       else
         o.push_back(i);
     }
@@ -177,29 +180,32 @@ static int rebuild_dispatch(gato_batch *b) {
   e = hipMemcpy(b->d_order_all, all.data(), M * sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(order)");
   if (b->n_split > 0) {
-    const std::vector<int> xall = expand(all);
-    e = upload(xall, &b->d_order_split_all);
-    if (e != hipSuccess) return hip_fail(e, "split order");
-    b->grid_split_all = (int)xall.size();
+    for (int q = 0; q < 2; ++q) {
+      const std::vector<int> xall = expand(all, q == 0 ? 4 : 2);
+      e = upload(xall, &b->d_order_split_all[q]);
+      if (e != hipSuccess) return hip_fail(e, "split order");
+      b->grid_split_all[q] = (int)xall.size();
+    }
   }
   std::vector<std::vector<int>> members(64);
   for (int i : all) members[desc[i].n * 8 + desc[i].kpt].push_back(i);
   for (int key = 0; key < 64; ++key) {
     auto &v = members[key];
     if (v.empty()) continue;
-    gato_batch::Group g{key / 8, key % 8, (int)v.size(), nullptr, nullptr, 0};
+    gato_batch::Group g{key / 8, key % 8, (int)v.size(), nullptr, {nullptr, nullptr}, {0, 0}};
     e = hipMalloc((void **)&g.d_order, v.size() * sizeof(int));
     if (e != hipSuccess) return hip_fail(e, "hipMalloc(order)");
-    if (b->n_split > 0) {
-      const std::vector<int> xv = expand(v);
+    for (int q = 0; q < 2 && b->n_split > 0; ++q) {
+      const std::vector<int> xv = expand(v, q == 0 ? 4 : 2);
       if (xv.size() > v.size()) {
-        e = upload(xv, &g.d_order_split);
+        e = upload(xv, &g.d_order_split[q]);
         if (e != hipSuccess) {
           (void)hipFree(g.d_order);
-          if (g.d_order_split) (void)hipFree(g.d_order_split);
+          for (int *o : g.d_order_split)
+            if (o) (void)hipFree(o);
           return hip_fail(e, "split order");
         }
-        g.grid_split = (int)xv.size();
+        g.grid_split[q] = (int)xv.size();
       }
     }
     b->groups.push_back(g);
@@ -440,10 +446,12 @@ void gato_batch_destroy(gato_batch *b) {
   else (void)hipDeviceSynchronize();
   for (auto &g : b->groups) {
     if (g.d_order) (void)hipFree(g.d_order);
-    if (g.d_order_split) (void)hipFree(g.d_order_split);
+    for (int *o : g.d_order_split)
+      if (o) (void)hipFree(o);
   }
   if (b->d_order_all) (void)hipFree(b->d_order_all);
-  if (b->d_order_split_all) (void)hipFree(b->d_order_split_all);
+  for (int *o : b->d_order_split_all)
+    if (o) (void)hipFree(o);
   if (b->d_xch) (void)hipFree(b->d_xch);
   if (b->graph) (void)hipGraphExecDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
@@ -506,9 +514,10 @@ hipError_t launch_mixed(const gato_batch *b, int grid, const gato::KArgs &a, hip
 
 // All solves of the batch: one mixed-shape launch over the decreasing-work
 // order, or one launch per shape group. Long solves split across four
-// workgroups (a cooperative launch) unless `allow_split` is false (graph
-// capture), the batch has it switched off, or the launch would not fit the chip
-// at once; then they run one workgroup each.
+// workgroups (a cooperative launch), or two when four per solve would not fit
+// the chip at once, unless `allow_split` is false (graph capture), the stream is
+// under capture or the batch has it switched off; otherwise, and when even two
+// do not fit, they run one workgroup each.
 int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split = true) {
   bool split = allow_split && a.mode == gato::kModeSqp && b->split_parts == gato::kSplitParts && b->n_split > 0;
   if (split) {
@@ -519,16 +528,17 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split 
   gato::KArgs as = a;
   if (split) {
     b->epoch = b->epoch % 65535u + 1u;
-    as.split = 1;
     as.epoch = b->epoch;
     as.xch = b->d_xch;
     as.xspin = b->split_polls;
   }
   if (use_mixed(b)) {
-    if (split && b->grid_split_all > b->M) {
-      as.order = b->d_order_split_all;
-      const hipError_t e = b->p.schur_fp64 ? gato::launch_sqp_mixed_f64_split(b->grid_split_all, as, s)
-                                           : gato::launch_sqp_mixed_f32_split(b->grid_split_all, as, s);
+    for (int q = 0; split && q < 2; ++q) {
+      if (b->grid_split_all[q] <= b->M) continue;
+      as.split = q == 0 ? 4 : 2;
+      as.order = b->d_order_split_all[q];
+      const hipError_t e = b->p.schur_fp64 ? gato::launch_sqp_mixed_f64_split(b->grid_split_all[q], as, s)
+                                           : gato::launch_sqp_mixed_f32_split(b->grid_split_all[q], as, s);
       if (e == hipSuccess) return GATO_OK;
       if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(e, "kernel launch (split)");
       (void)hipGetLastError();
@@ -540,14 +550,18 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split 
   }
   const bool f64 = b->p.schur_fp64 != 0;
   for (const auto &g : b->groups) {
-    if (split && g.d_order_split && (g.n == 6 || g.n == 7)) {
-      as.order = g.d_order_split;
-      const hipError_t e = g.n == 7 ? gato::launch_sqp_n7_split(g.grid_split, f64, as, s)
-                                    : gato::launch_sqp_n6_split(g.grid_split, f64, as, s);
-      if (e == hipSuccess) continue;
-      if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(e, "kernel launch (split)");
-      (void)hipGetLastError();
+    bool done = false;
+    for (int q = 0; split && !done && q < 2 && (g.n == 6 || g.n == 7); ++q) {
+      if (!g.d_order_split[q]) continue;
+      as.split = q == 0 ? 4 : 2;
+      as.order = g.d_order_split[q];
+      const hipError_t e = g.n == 7 ? gato::launch_sqp_n7_split(g.grid_split[q], f64, as, s)
+                                    : gato::launch_sqp_n6_split(g.grid_split[q], f64, as, s);
+      if (e == hipSuccess) done = true;
+      else if (e != hipErrorCooperativeLaunchTooLarge) return hip_fail(e, "kernel launch (split)");
+      else (void)hipGetLastError();
     }
+    if (done) continue;
     a.order = g.d_order;
     hipError_t e = gato::launch_sqp(g.n, g.kpt, f64, g.count, a, s);
     if (e != hipSuccess) return hip_fail(e, "kernel launch");

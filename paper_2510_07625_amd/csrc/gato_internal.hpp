@@ -85,10 +85,11 @@ struct KArgs {
   int by_block;
   int shift;
   float *Xout, *Uout;
-  // Split launch: `order` entries carry the part in bits 24..31 and the solve in
-  // bits 0..23; the parts of a solve exchange through `xch` under tags of this
-  // launch's `epoch` (1..65535). All workgroups of such a launch are co-resident
-  // (cooperative launch).
+  // Split launch (split = 4 or 2 parts per long solve, 0: none): `order` entries
+  // carry the part in bits 24..31 and the solve in bits 0..23; the parts of a
+  // solve exchange through `xch` under tags of this launch's `epoch`
+  // (1..65535). All workgroups of such a launch are co-resident (cooperative
+  // launch).
   int split;
   unsigned epoch;
   unsigned long long *xch;

@@ -308,13 +308,18 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   const int N = D.N;
   const float h = D.dt;
   const int n_alpha = a.n_alpha;
-  // Split solve (four knots per lane group): four workgroups run
+  // Split solve (four knots per lane group): four (or two) workgroups run
   // the same SQP iteration, each with its own workspace, and share the PCG:
-  // part j owns the knots 32 j .. 32 j + 31 (p == j). Only part 0 writes results.
+  // part j owns the knots of p == j (or p == 2 j, 2 j + 1). Only part 0 writes
+  // results.
   // (SPLIT: compiled into kernels of their own, so that the one-workgroup
   // kernels carry none of the exchange code.)
   constexpr bool kSplitOk = SPLIT && (KPT == 4) && !TS;
-  const bool split = kSplitOk && a.split && a.mode == kModeSqp && D.xch_off >= 0 && part >= 0 && part < kXParts;
+  // a.split = 4: part j owns p = j; a.split = 2 (when four workgroups per solve
+  // do not fit the chip): part j owns p = 2 j and 2 j + 1.
+  const int nparts = a.split == 2 ? 2 : kXParts;
+  const int psh = nparts == 2 ? 1 : 0;
+  const bool split = kSplitOk && a.split && a.mode == kModeSqp && D.xch_off >= 0 && part >= 0 && part < nparts;
   const bool writer = !split || part == 0;
   char *ws = a.ws + D.ws_off + (split ? (int64_t)part * D.ws_part : 0);
   const size_t xoff = (size_t)sid * a.N_max * a.nx_max;
@@ -956,12 +961,13 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // matrix-vector products.
     // Split solve: this part's rows only, until the multipliers are gathered.
     bool xon = split;
-    auto own = [&](int p) { return !xon || p == part; };
+    auto own = [&](int p) { return !xon || (p >> psh) == part; };
     unsigned long long *xb = split ? a.xch + D.xch_off : nullptr;
     const int xspin = a.xspin > 0 ? a.xspin : kXSpin;
     auto xtag = [&](unsigned e) { return ((a.epoch & 0xffffu) << 16) | (e & 0xffffu); };
     auto xslot = [&](int q, unsigned e) { return xb + (size_t)q * kXPart + (size_t)(e % kXSlots) * kXSlot; };
-    const int kf = part * SLOTS, kl = min(kf + SLOTS, N) - 1;   // own knots kf..kl (none when kf >= N)
+    const int kf = (part << psh) * SLOTS;                        // own knots kf..kl (none when kf >= N)
+    const int kl = min(kf + (SLOTS << psh), N) - 1;
     const bool has_l = split && part > 0 && kf < N;              // a part on the left / the right
     const bool has_r = split && kl + 1 < N;
     // Halo rows: the first own knot's row of vl goes to the left part, the last
@@ -983,7 +989,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           if (!xget(xslot(part - 1, e) + 32 + 2 * lane, xtag(e), dead, xspin, v)) sm.xfail = 1;
           vr[kf - 1][lane] = (Real)v;
         }
-        if (has_r && slot == kl - kf) {
+        if (has_r && slot == kl % SLOTS) {
           if (!xget(xslot(part + 1, e) + 2 * lane, xtag(e), dead, xspin, v)) sm.xfail = 1;
           vl[kl + 1][lane] = (Real)v;
         }
@@ -1000,9 +1006,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       const bool dead = sm.xfail != 0;
       const int l = tid & 63;
       const bool hl = halo && has_l && slot == 0 && lane < NX;
-      const bool hr = halo && has_r && slot == kl - kf && lane < NX;
+      const bool hr = halo && has_r && slot == kl % SLOTS && lane < NX;
       unsigned long long *wh = hl ? xslot(part - 1, e) + 32 + 2 * lane : (hr ? xslot(part + 1, e) + 2 * lane : nullptr);
-      unsigned long long *ws = l < 3 * kXParts ? xslot(l / 3, e) + 64 + 2 * (l % 3) : nullptr;
+      unsigned long long *ws = l < 3 * nparts ? xslot(l / 3, e) + 64 + 2 * (l % 3) : nullptr;
       double vh = 0.0, v = 0.0;
       if (wh || ws) {
         bool ok;
@@ -1014,9 +1020,15 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       if (hl) vr[kf - 1][lane] = (Real)vh;
       if (hr) vl[kl + 1][lane] = (Real)vh;
       wave_sync();
-      s0 = (lane_val(v, 0) + lane_val(v, 3)) + (lane_val(v, 6) + lane_val(v, 9));
-      s1 = (lane_val(v, 1) + lane_val(v, 4)) + (lane_val(v, 7) + lane_val(v, 10));
-      s2 = (lane_val(v, 2) + lane_val(v, 5)) + (lane_val(v, 8) + lane_val(v, 11));
+      if (nparts == 2) {
+        s0 = lane_val(v, 0) + lane_val(v, 3);
+        s1 = lane_val(v, 1) + lane_val(v, 4);
+        s2 = lane_val(v, 2) + lane_val(v, 5);
+      } else {
+        s0 = (lane_val(v, 0) + lane_val(v, 3)) + (lane_val(v, 6) + lane_val(v, 9));
+        s1 = (lane_val(v, 1) + lane_val(v, 4)) + (lane_val(v, 7) + lane_val(v, 10));
+        s2 = (lane_val(v, 2) + lane_val(v, 5)) + (lane_val(v, 8) + lane_val(v, 11));
+      }
     };
     auto xhalo = [&](Real (*vl)[G], Real (*vr)[G]) {
       xhalo_get(xe, vl, vr);
@@ -1033,12 +1045,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       const unsigned e = xe++;
 #pragma unroll
       for (int p = 0; p < KPT; ++p)
-        if (p == part && slot + p * SLOTS < N && lane < NX)
+        if ((p >> psh) == part && slot + p * SLOTS < N && lane < NX)
           xput(xb + (size_t)p * kXPart + kXSlots * kXSlot + 2 * (slot * G + lane), xtag(e), (double)lam[p]);
       const bool dead = sm.xfail != 0;
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
-        if (p != part && slot + p * SLOTS < N && lane < NX) {
+        if ((p >> psh) != part && slot + p * SLOTS < N && lane < NX) {
           double v;
           if (!xget(xb + (size_t)p * kXPart + kXSlots * kXSlot + 2 * (slot * G + lane), xtag(e), dead, xspin, v))
             sm.xfail = 1;

@@ -127,8 +127,8 @@ def test_split_fp32_variant_matches_the_one_workgroup_form():
 
 
 def test_split_falls_back_when_the_launch_does_not_fit():
-    # 300 long solves need 1200 workgroups at once: the launch runs them one
-    # workgroup each, with the one-workgroup form's results.
+    # 300 long solves need 1200 workgroups at once (600 with two parts): the
+    # launch runs them one workgroup each, with the one-workgroup form's results.
     _say("split fallback")
     solves = [w.chain_solve(35, i % 4, n=7, N=128) for i in range(300)]
     p = g.Params(sqp_iters=1, pcg_tol=1e-5)
@@ -172,3 +172,20 @@ def test_split_wait_bound_reports_the_exchange_and_returns():
     assert not (s_ok["status"] & g.ST_EXCHANGE).any(), s_ok["status"]
     ex, eu = _replay(solves[0], Xok[0].astype(np.float64), U.cpu().numpy()[0].astype(np.float64), s_ok[0], 3)
     assert ex <= 1e-4 and eu <= 1e-4, (ex, eu)
+
+
+def test_two_parts_per_solve_when_four_do_not_fit():
+    # 80 long solves: four workgroups each (320) do not fit 256 CUs, two (160)
+    # do. Sampled solves against the oracle; the multipliers differ from the
+    # one-workgroup form at rounding level (the two-part path ran).
+    _say("split two parts")
+    solves = [w.chain_solve(41, i, n=7, N=128) for i in range(80)]
+    p = g.Params(sqp_iters=2, pcg_tol=1e-7)
+    Xs, Us, ss, ls = _run(solves, p, 4)
+    X1, U1, s1, l1 = _run(solves, p, 1)
+    assert not (ss["status"] & (g.ST_EXCHANGE | g.ST_NONFINITE)).any()
+    assert not np.array_equal(ls, l1), "the split path did not run"
+    assert np.abs(ls - l1).max() <= 1e-6 * np.abs(l1).max()
+    for i in (0, 41, 79):
+        ex, eu = _replay(solves[i], Xs[i], Us[i], ss[i], p.sqp_iters)
+        assert ex <= 1e-4 and eu <= 1e-4, (i, ex, eu)
