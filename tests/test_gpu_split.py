@@ -59,8 +59,10 @@ def _replay(s, Xg, Ug, st, iters):
 
 
 # N = 128: four full parts; 100: the last part holds 4 knots; 80: the last part
-# holds none (it still takes part in every exchange).
-@pytest.mark.parametrize("n,N", [(7, 128), (6, 100), (7, 80)])
+# holds none (it still takes part in every exchange); 65: the third part holds a
+# single knot (a left neighbour only) and the last none; 97: the last part holds
+# a single knot.
+@pytest.mark.parametrize("n,N", [(7, 128), (6, 100), (7, 80), (7, 65), (6, 97)])
 def test_split_solve_matches_the_oracle_and_the_one_workgroup_form(n, N):
     _say(f"split n={n} N={N}")
     solves = [w.chain_solve(31, i, n=n, N=N) for i in range(2)]
