@@ -6,8 +6,8 @@ rows and inner products with the other parts at every PCG iteration; the PCG
 is the same method (Sec. III-B), with its inner products summed per part
 first. Bars: the oracle replay of the accepted steps within 1e-4 (PCG
 tolerance 1e-7, as the other trajectory tests), no exchange time-out, and the
-multipliers within 1e-6 of the one-workgroup form while not bit-identical to
-it (the split path ran).
+multipliers within 1e-5 of the one-workgroup form (both stop at the PCG
+tolerance) while not bit-identical to it (the split path ran).
 """
 import sys
 
@@ -82,8 +82,10 @@ def test_split_solve_matches_the_oracle_and_the_one_workgroup_form(n, N):
     np.testing.assert_array_equal(ss["alpha"], s1["alpha"])
     ts, t1 = ss["pcg_iters"].sum(axis=1), s1["pcg_iters"].sum(axis=1)
     assert np.all(np.abs(ts - t1) <= 0.05 * t1), (ts, t1)
+    # Both stop at the PCG tolerance 1e-7 (R6), so their multipliers may differ
+    # at that tolerance's order.
     scale = np.abs(l1).max()
-    assert np.abs(ls - l1).max() <= 1e-6 * scale
+    assert np.abs(ls - l1).max() <= 1e-5 * scale
     assert not np.array_equal(ls, l1), "the split path did not run"
 
 
@@ -176,18 +178,20 @@ def test_split_wait_bound_reports_the_exchange_and_returns():
     assert ex <= 1e-4 and eu <= 1e-4, (ex, eu)
 
 
-def test_two_parts_per_solve_when_four_do_not_fit():
+# N = 70: the second part holds 6 knots in one lane-group block (p = 2).
+@pytest.mark.parametrize("N", [128, 70])
+def test_two_parts_per_solve_when_four_do_not_fit(N):
     # 80 long solves: four workgroups each (320) do not fit 256 CUs, two (160)
     # do. Sampled solves against the oracle; the multipliers differ from the
     # one-workgroup form at rounding level (the two-part path ran).
-    _say("split two parts")
-    solves = [w.chain_solve(41, i, n=7, N=128) for i in range(80)]
+    _say(f"split two parts N={N}")
+    solves = [w.chain_solve(41, i, n=7, N=N) for i in range(80)]
     p = g.Params(sqp_iters=2, pcg_tol=1e-7)
     Xs, Us, ss, ls = _run(solves, p, 4)
     X1, U1, s1, l1 = _run(solves, p, 1)
     assert not (ss["status"] & (g.ST_EXCHANGE | g.ST_NONFINITE)).any()
     assert not np.array_equal(ls, l1), "the split path did not run"
-    assert np.abs(ls - l1).max() <= 1e-6 * np.abs(l1).max()
+    assert np.abs(ls - l1).max() <= 1e-5 * np.abs(l1).max()   # PCG tolerance 1e-7 on both
     for i in (0, 41, 79):
         ex, eu = _replay(solves[i], Xs[i], Us[i], ss[i], p.sqp_iters)
         assert ex <= 1e-4 and eu <= 1e-4, (i, ex, eu)
