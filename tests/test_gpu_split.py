@@ -195,3 +195,30 @@ def test_two_parts_per_solve_when_four_do_not_fit(N):
     for i in (0, 41, 79):
         ex, eu = _replay(solves[i], Xs[i], Us[i], ss[i], p.sqp_iters)
         assert ex <= 1e-4 and eu <= 1e-4, (i, ex, eu)
+
+
+def test_full_size_uneven_batch_sampled_solves():
+    # The uneven-batch benchmark's launch: 128 seeded solves (seed 0; DoF from
+    # {3, 6, 7}, N from {16, 32, 64, 128}), one mixed-shape launch with the long
+    # solves split, 10 SQP iterations, PCG tolerance 1e-5. Sampled solves (two
+    # split 7-DoF and one split 6-DoF N = 128 solve, one short one) are replayed
+    # in the oracle; as for the headline batch, the bar is max(1e-4, 3 e_ref),
+    # e_ref being how far the same method in FP64 departs from the exact solve.
+    _say("full size uneven M=128")
+    solves = w.uneven_batch(0, M=128)
+    p = g.Params(sqp_iters=10, pcg_tol=1e-5)
+    Xg, Ug, st, _ = _run(solves, p, 4, g.DISPATCH_MIXED)
+    assert not (st["status"] & (g.ST_EXCHANGE | g.ST_NONFINITE | g.ST_PCG_MAXITER)).any()
+    for i in (1, 6, 4, 0):
+        s = solves[i]
+        alphas = st[i]["alpha"].astype(np.float64)
+        mode = 2 if s.N > 64 else 0
+        exact = oracle.sqp(s, oracle.Params(kkt_mode=mode), alpha_replay=alphas)
+        same = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=1e-5), alpha_replay=alphas)
+        e_ref = max(np.abs(same.X - exact.X).max() / np.abs(exact.X).max(),
+                    np.abs(same.U - exact.U).max() / np.abs(exact.U).max())
+        n, N = s.n, s.N
+        ex = np.abs(Xg[i, :N, :2 * n] - exact.X).max() / np.abs(exact.X).max()
+        eu = np.abs(Ug[i, :N - 1, :n] - exact.U).max() / np.abs(exact.U).max()
+        print(f"solve {i} (n={n}, N={N}): X {ex:.2e} U {eu:.2e}, e_ref {e_ref:.2e}")
+        assert max(ex, eu) <= max(1e-4, 3 * e_ref), (i, ex, eu, e_ref)
