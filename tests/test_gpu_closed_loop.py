@@ -84,3 +84,45 @@ def test_closed_loop_ticks_replay_in_the_oracle():
             ref = oracle.plant_rk4(s, states[t, i].astype(np.float64), tau, 0.01, 10)
             np.testing.assert_allclose(states[t + 1, i], ref, rtol=2e-6, atol=2e-6)
     b.close()
+
+
+def test_full_size_closed_loop_sampled_ticks():
+    # The closed-loop benchmark's batch: 256 7-DoF N = 64 instances (seed 0),
+    # 3 SQP iterations per tick at PCG tolerance 1e-5, torque impulses
+    # N(0, 5^2) N m at tick 100 (the benchmark's draw), 102 ticks. Ticks 0, 100
+    # and 101 of sampled instances are replayed in the oracle from the same
+    # plant state, shifted warm start and accepted steps; the bar is
+    # max(1e-4, 3 e_ref), e_ref being how far the same method in FP64 departs
+    # from the exact (Riccati) solve.
+    _say("closed loop full size M=256 N=64")
+    M, N, iters = 256, 64, 3
+    solves = w.chain_batch(0, M, N=N)
+    p = g.Params(sqp_iters=iters, pcg_tol=1e-5)
+    b = g.Batch.from_solves(solves, p)
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    b.set_trajectories(X0, U0)
+    rng = np.random.default_rng([0, 5])
+    kick = torch.from_numpy(rng.normal(0.0, 5.0, (M, 7)).astype(np.float32)).cuda()
+    rec = (0, 100, 101)
+    run = closed_loop.run(b, xs, goal, 102, n_iters=iters, disturbance=lambda t: kick if t == 100 else None,
+                          record_ticks=rec)
+    b.close()
+    assert np.isfinite(run.states.cpu().numpy()).all()
+    for t in rec:
+        R = run.records[t]
+        for i in (0, 97, 255):
+            s = solves[i]
+            Xp, Up = R["X_prev"][i].astype(np.float64), R["U_prev"][i].astype(np.float64)
+            Xw = Xp[np.minimum(np.arange(N) + 1, N - 1)]
+            Uw = Up[np.minimum(np.arange(N - 1) + 1, N - 2)]
+            st = dataclasses.replace(s, xs=R["xs"][i].astype(np.float64))
+            alphas = R["stats"][i]["alpha"].astype(np.float64)
+            exact = oracle.sqp(st, oracle.Params(sqp_iters=iters, kkt_mode=2), X=Xw, U=Uw, alpha_replay=alphas)
+            same = oracle.sqp(st, oracle.Params(sqp_iters=iters, kkt_mode=1, pcg_tol=1e-5), X=Xw, U=Uw,
+                              alpha_replay=alphas)
+            e_ref = max(np.abs(same.X - exact.X).max() / np.abs(exact.X).max(),
+                        np.abs(same.U - exact.U).max() / np.abs(exact.U).max())
+            ex = np.abs(R["X"][i] - exact.X).max() / np.abs(exact.X).max()
+            eu = np.abs(R["U"][i] - exact.U).max() / np.abs(exact.U).max()
+            print(f"tick {t} instance {i}: X {ex:.2e} U {eu:.2e}, e_ref {e_ref:.2e}")
+            assert max(ex, eu) <= max(1e-4, 3 * e_ref), (t, i, ex, eu, e_ref)
