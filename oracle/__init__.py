@@ -97,6 +97,8 @@ def lib():
                                   C.POINTER(C.c_int), dp]
         L.orc_kkt_from_lq.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, dp, dp, dp, dp, dp, C.c_int, dp, dp,
                                       dp]
+        L.orc_kkt_residual.argtypes = [rp, pp, C.c_double, dp, dp, dp, dp, dp, dp]
+        L.orc_kkt_residual.restype = C.c_double
         L.orc_merit.argtypes = [rp, pp, dp, dp, dp, dp, C.c_double, dp, dp]
         L.orc_merit.restype = C.c_double
         L.orc_tip.argtypes = [rp, dp, dp, dp]
@@ -299,6 +301,22 @@ def qp_step(s, X, U, mode: int = 0, rho: float = 0.0, pcg_tol: float = 1e-6, pcg
         raise FloatingPointError("QP step failed")
     dX, dU = split_dz(s, dZ)
     return dX, dU, lam.reshape(N, nx), its.value, res.value
+
+
+def kkt_residual(s, X, U, dZ, lam, rho: float = 0.0) -> float:
+    """inf-norm residual of the KKT system of Eq. (2) at (X, U) for the given
+    dZ [x_0 u_0 ... x_{N-1}] and multipliers lambda [N, nx] (the value the SQP
+    loop logs as kkt_res)."""
+    c = _Ctx(s)
+    X, U, xs, qg = _f64(X), _f64(U), _f64(s.xs), _f64(s.qgoal)
+    dZ, lam = _f64(dZ).reshape(-1), _f64(lam).reshape(-1)
+    nx, nu, N = 2 * s.n, s.n, s.N
+    assert dZ.size == N * nx + (N - 1) * nu and lam.size == N * nx
+    r = lib().orc_kkt_residual(C.byref(c.robot), C.byref(c.prob), float(rho), _ptr(xs), _ptr(qg), _ptr(X), _ptr(U),
+                               _ptr(dZ), _ptr(lam))
+    if r < 0:
+        raise FloatingPointError("QP data could not be formed")
+    return r
 
 
 def kkt_from_lq(A, B, e, q, r, c0, Qh, Rh, mode: int = 0):

@@ -799,10 +799,18 @@ Schur build_schur(const Lq &lq) {
   return s;
 }
 
-void dense_matvec(const std::vector<double> &A, const double *x, double *y, size_t dim) {
+// y = A x for a dim x dim matrix (dim = N nx) that is block tridiagonal with
+// nx x nx blocks, as S~ and P of Eq. (6) are by construction: row i sums over
+// the block columns bi-1..bi+1 of its block row bi in ascending column order,
+// so the terms left out are exactly the structural zeros and the sums equal
+// those of the full dense product. (N = 1: a plain dense product.)
+void tridiag_matvec(const std::vector<double> &A, const double *x, double *y, int nx, int N) {
+  const size_t dim = (size_t)N * nx;
   for (size_t i = 0; i < dim; ++i) {
+    const int bi = (int)(i / nx);
+    const size_t j0 = (size_t)std::max(bi - 1, 0) * nx, j1 = (size_t)std::min(bi + 2, N) * nx;
     double s = 0.0;
-    for (size_t j = 0; j < dim; ++j) s += A[i * dim + j] * x[j];
+    for (size_t j = j0; j < j1; ++j) s += A[i * dim + j] * x[j];
     y[i] = s;
   }
 }
@@ -812,12 +820,14 @@ void dense_matvec(const std::vector<double> &A, const double *x, double *y, size
 int pcg(const Schur &s, double *lam, double tol, int max_iter, bool *hit_max) {
   const size_t dim = (size_t)s.N * s.nx;
   std::vector<double> r(dim), z(dim), p(dim), w(dim), pg(dim);
-  dense_matvec(s.P, s.gamma.data(), pg.data(), dim);
+  auto S_times = [&](const double *x, double *y) { tridiag_matvec(s.S, x, y, s.nx, s.N); };
+  auto P_times = [&](const double *x, double *y) { tridiag_matvec(s.P, x, y, s.nx, s.N); };
+  P_times(s.gamma.data(), pg.data());
   double eta_ref = 0.0;
   for (size_t i = 0; i < dim; ++i) eta_ref += s.gamma[i] * pg[i];
-  dense_matvec(s.S, lam, w.data(), dim);
+  S_times(lam, w.data());
   for (size_t i = 0; i < dim; ++i) r[i] = s.gamma[i] - w[i];
-  dense_matvec(s.P, r.data(), z.data(), dim);
+  P_times(r.data(), z.data());
   double eta = 0.0;
   for (size_t i = 0; i < dim; ++i) { p[i] = z[i]; eta += r[i] * z[i]; }
   const double stop = tol * tol * eta_ref;
@@ -825,12 +835,12 @@ int pcg(const Schur &s, double *lam, double tol, int max_iter, bool *hit_max) {
   *hit_max = false;
   while (eta > stop) {
     if (it >= max_iter) { *hit_max = true; break; }
-    dense_matvec(s.S, p.data(), w.data(), dim);
+    S_times(p.data(), w.data());
     double pw = 0.0;
     for (size_t i = 0; i < dim; ++i) pw += p[i] * w[i];
     const double a = eta / pw;
     for (size_t i = 0; i < dim; ++i) { lam[i] += a * p[i]; r[i] -= a * w[i]; }
-    dense_matvec(s.P, r.data(), z.data(), dim);
+    P_times(r.data(), z.data());
     double eta_new = 0.0;
     for (size_t i = 0; i < dim; ++i) eta_new += r[i] * z[i];
     const double b = eta_new / eta;
@@ -1149,6 +1159,17 @@ int orc_qp_step(const orc_robot *rb, const orc_problem *pr, double rho, const do
   if (pcg_iters) *pcg_iters = its;
   if (kkt_res) *kkt_res = kkt_residual(lq, dZ, lam);
   return ok ? 0 : -1;
+}
+
+// inf-norm residual of Eq. (2) at (X, U) for a caller-given dZ [nz] and
+// lambda [N nx] (the residual every SQP iteration records); -1 if the QP data
+// could not be formed.
+double orc_kkt_residual(const orc_robot *rb, const orc_problem *pr, double rho, const double *xs,
+                        const double *qgoal, const double *X, const double *U, const double *dZ,
+                        const double *lam) {
+  Lq lq = build_lq(*rb, *pr, rho, xs, qgoal, X, U);
+  if (!lq.ok) return -1.0;
+  return kkt_residual(lq, dZ, lam);
 }
 
 // The KKT solve of one SQP step on caller-given QP data (Eq. (2)):
