@@ -192,6 +192,25 @@ def plant_rk4(s, x, tau, h: float = 0.01, substeps: int = 10) -> np.ndarray:
     return xn
 
 
+def hypothesis_select(s, x, tau, forces, x_meas, h: float = 0.01, substeps: int = 10):
+    """Selection step of the hypothesize-and-test case study (Sec. IV-D), read
+    as in the design notes: each hypothesis is an external tip force; its
+    one-step prediction is the RK4 plant from x under tau with that force; it
+    scores the Euclidean distance of its prediction to the measured state
+    x_meas; the smallest distance wins, ties to the smaller index. forces
+    [H, 3]; returns (index, distances [H])."""
+    import dataclasses
+    d = np.zeros(len(forces))
+    for j, f in enumerate(np.asarray(forces, np.float64)):
+        sj = dataclasses.replace(s, fext=tuple(float(v) for v in f))
+        d[j] = np.linalg.norm(plant_rk4(sj, x, tau, h, substeps) - _f64(x_meas))
+    best = 0
+    for j in range(1, len(d)):
+        if d[j] < d[best]:
+            best = j
+    return best, d
+
+
 def step_jacobians(s, x, u, h=None):
     """Returns (f(x, u), A, B) of the explicit Euler step."""
     c = _Ctx(s)

@@ -10,6 +10,8 @@ A report, not a test (pytest does not collect it): run it on an MI355X as
   the FP64 method's own distance from the exact solve;
 * every precision setting: the same trajectory error, and the KKT-solution
   error on identical QP data (the oracle's LQ data rounded once to FP32);
+* the uneven batch in its three precision settings: per (DoF, N) bucket,
+  sampled solves against the same-method and the exact oracle;
 * the closed-loop batch: sampled ticks replayed in the oracle from the same
   plant state and warm start, and the oracle's own closed loop for 150 ticks;
 * the task-space (figure-8) launch: sampled trajectories and, step by step,
@@ -177,6 +179,52 @@ def task_space(g, torch, M=256, iters=10, idx=(0, 128, 255)):
     return traj
 
 
+def uneven(g, torch, M=128, seed=0, per_bucket=2):
+    """The uneven batch of the benchmark (one mixed-shape launch, long solves
+    split) in each of its precision settings: per (DoF, N) bucket, the largest
+    error of `per_bucket` sampled solves against the same-method FP64 oracle
+    and against the exact (Riccati) oracle."""
+    solves = w.uneven_batch(seed, M=M)
+    buckets = {}
+    for i, s in enumerate(solves):
+        buckets.setdefault((s.n, s.N), []).append(i)
+    idx = sorted(i for v in buckets.values() for i in v[:per_bucket])
+    out = {}
+    for name, kw in (("fp64-schur", dict(schur_fp64=1)), ("fp32+fp64-inv", dict(schur_fp64=0, fp64_block_inv=1)),
+                     ("fp32", dict(schur_fp64=0))):
+        params = g.Params(sqp_iters=10, pcg_tol=1e-5, **kw)
+        b = g.Batch.from_solves(solves, params)
+        b.set_dispatch(g.DISPATCH_MIXED)
+        xs, goal, X, U = g.pack_inputs(solves)
+        st = b.stats_buffer(10)
+        b.reset_warm_start()
+        b.step(xs, goal, X, U, 10, st)
+        torch.cuda.synchronize()
+        X, U = X.cpu().numpy().astype(np.float64), U.cpu().numpy().astype(np.float64)
+        st = g.Batch.decode_stats(st, M, 10)
+        b.close()
+
+        def one(i):
+            s = solves[i]
+            al = st[i]["alpha"].astype(np.float64)
+            common = dict(sqp_iters=10, mu=params.mu, beta=params.beta, n_alpha=params.n_alpha)
+            exact = oracle.sqp(s, oracle.Params(kkt_mode=2, **common), alpha_replay=al)
+            same = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=params.pcg_tol, **common), alpha_replay=al)
+            n, N = s.n, s.N
+            Xi, Ui = X[i, :N, :2 * n], U[i, :N - 1, :n]
+            return _rel(Xi, Ui, same.X, same.U), _rel(Xi, Ui, exact.X, exact.U)
+
+        oracle.lib()
+        with ThreadPoolExecutor(16) as ex:
+            errs = dict(zip(idx, ex.map(one, idx)))
+        out[name] = {f"{n}x{N}": dict(vs_same_method=float(max(errs[i][0] for i in v[:per_bucket])),
+                                      vs_exact=float(max(errs[i][1] for i in v[:per_bucket])), count=len(v))
+                     for (n, N), v in sorted(buckets.items())}
+        out[name]["status_bits_set"] = int((st["status"] != 0).sum())
+        print("# uneven", name, out[name], file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     import torch
     import paper_2510_07625_amd as g
@@ -195,6 +243,7 @@ def main():
                          kkt_rel_err=kkt, kkt_pcg_iters=its))
         print("# precision", prec[-1], file=sys.stderr, flush=True)
     out["precision"] = prec
+    out["uneven"] = uneven(g, torch)
     out["closed_loop"] = closed_loop(g, torch)
     print("# closed loop", out["closed_loop"], file=sys.stderr, flush=True)
     out["task_space"] = task_space(g, torch)

@@ -13,7 +13,10 @@ pytestmark = pytest.mark.skipif(not os.path.exists(g.LIB_PATH), reason="libgato.
 
 
 def _declared():
-    text = open(g.HEADER).read()
+    import glob
+    headers = sorted(glob.glob(os.path.join(os.path.dirname(g.HEADER), "*.h")))
+    assert sorted(headers) == sorted(g.HEADERS)
+    text = "".join(open(h).read() for h in headers)
     return sorted(set(re.findall(r"\b(gato_[a-z_0-9]+)\s*\(", text)))
 
 

@@ -59,3 +59,44 @@ def test_hypotheses_explain_the_disturbance_and_track_better():
     assert np.isfinite(r.states).all()
     assert (terr[-10:].mean(axis=0) < 0.5 * terr[0]).all()
     assert track[-20:].mean() < track1[-20:].mean()
+
+
+def test_device_selection_replays_in_the_oracle():
+    # gato_select_hypotheses against the oracle's selection: at sampled ticks,
+    # every instance's hypotheses (the estimate before the tick plus the
+    # offsets, in the FP32 the solves use) are stepped by the oracle's RK4 plant
+    # from the same state under the applied control; the GPU's choice must be
+    # the oracle's nearest prediction to the measured next state (or tie with
+    # it at FP32 resolution), and the estimate must move to exactly that
+    # hypothesis.
+    import dataclasses
+
+    import oracle
+    _say("hypothesis selection vs oracle")
+    P, H, ticks = 4, 8, 12
+    base = [w.chain_solve(91, p, n=7, N=32) for p in range(P)]
+    solves = [s for s in base for _ in range(H)]
+    b = g.Batch.from_solves(solves, g.Params(sqp_iters=2))
+    xs, goal, X, U = g.pack_inputs(solves)
+    b.set_trajectories(X, U)
+    rng = np.random.default_rng([91, 1])
+    f_true = rng.normal(0.0, 20.0, (P, 3))
+    sigma = 12.0
+    r = hypotheses.run(b, P, H, xs[::H].contiguous(), goal[::H].contiguous(), ticks, lambda t: f_true, sigma=sigma)
+    b.close()
+    off = hypotheses.offsets(H) * sigma
+    ties = 0
+    for t in (0, 5, ticks - 1):
+        for p in range(P):
+            forces = (r.estimates[t, p][None, :] + off).astype(np.float32).astype(np.float64)
+            x = r.states[t, p, :14].astype(np.float64)
+            u = r.controls[t, p, :7].astype(np.float64)
+            meas = r.states[t + 1, p, :14].astype(np.float64)
+            j_or, d_or = oracle.hypothesis_select(dataclasses.replace(base[p], fext=(0.0, 0.0, 0.0)), x, u, forces,
+                                                  meas)
+            j_g = int(r.selected[t, p])
+            if j_g != j_or:
+                ties += 1
+                assert d_or[j_g] - d_or[j_or] <= 1e-6 * (1.0 + np.abs(meas).max()), (t, p, j_g, j_or, d_or)
+            np.testing.assert_array_equal(r.estimates[t + 1, p], r.estimates[t, p] + off[j_g])
+    print(f"selection replayed at 3 ticks x {P} instances; {ties} ties at FP32 resolution")

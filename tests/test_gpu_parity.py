@@ -15,6 +15,8 @@ import pytest
 import oracle
 import workload as w
 
+from . import _parity
+
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
@@ -182,28 +184,27 @@ def test_sqp_trajectory_parity_tight_tolerance(n, N, M):
 
 @pytest.mark.parametrize("n,N,M", [(7, 32, 4), (6, 48, 2)])
 def test_sqp_trajectory_at_config_tolerance(n, N, M):
-    # PCG tolerance 1e-5 (the benchmark setting). The method itself, run in
-    # FP64 by the oracle with the same stopping rule, departs from the exact
-    # solve by e_ref; the GPU must stay within max(1e-4, 3 e_ref) of it.
+    # PCG tolerance 1e-5 (the benchmark setting). The reference is the oracle
+    # running the same method in FP64 (Schur complement + stair preconditioner
+    # + PCG at 1e-5, same warm start) over the GPU's accepted steps: trajectory
+    # within 1e-4 and every accepted step a valid argmin of its merits. The
+    # distance of both to the exact solve is printed.
     _say(f"sqp config-tol n={n} N={N} M={M}")
     solves = [w.chain_solve(0, i, n=n, N=N) for i in range(M)]
     p = g.Params(sqp_iters=10, pcg_tol=1e-5)
     Xg, Ug, st = _run_gpu(solves, p)
-    for i, s in enumerate(solves):
-        alphas = st[i]["alpha"].astype(np.float64)
-        exact = oracle.sqp(s, oracle.Params(kkt_mode=0), alpha_replay=alphas)
-        same = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=1e-5), alpha_replay=alphas)
-        e_ref = max(np.abs(same.X - exact.X).max() / np.abs(exact.X).max(),
-                    np.abs(same.U - exact.U).max() / np.abs(exact.U).max())
-        _replay_check(s, Xg[i], Ug[i], st[i], p, tol=max(1e-4, 3 * e_ref), check_merit=False)
+    res = _parity.check_many([dict(s=s, Xg=Xg[i], Ug=Ug[i], st=st[i], p_gpu=p, label=f"solve {i}")
+                              for i, s in enumerate(solves)])
+    _parity.report(res, f"n={n} N={N} at PCG tol 1e-5")
 
 
 def test_full_size_batch_sampled_solves():
     # The benchmark's launch: M = 256 seeded 7-DoF chains, N = 32, 10 SQP
     # iterations, PCG tol 1e-5, one workgroup per solve (bench.py's step with
-    # the iterate restored and the warm start cleared). Sampled solves are
-    # replayed in the oracle; bound as at the configured tolerance above. The
-    # per-iteration statistics of every solve must be clean.
+    # the iterate restored and the warm start cleared). Eighteen solves (evenly
+    # spread, plus the slowest and the fastest PCG solve) are replayed in the
+    # same-method FP64 oracle. The per-iteration statistics of every solve must
+    # be clean.
     _say("full size M=256")
     M = 256
     solves = w.chain_batch(0, M)
@@ -218,14 +219,12 @@ def test_full_size_batch_sampled_solves():
     Xg, Ug = X.cpu().numpy().astype(np.float64), U.cpu().numpy().astype(np.float64)
     b.close()
     assert not (st["status"] & (g.ST_NONFINITE | g.ST_PCG_MAXITER)).any()
-    for i in (0, 97, 255):
-        s = solves[i]
-        alphas = st[i]["alpha"].astype(np.float64)
-        exact = oracle.sqp(s, oracle.Params(kkt_mode=0), alpha_replay=alphas)
-        same = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=1e-5), alpha_replay=alphas)
-        e_ref = max(np.abs(same.X - exact.X).max() / np.abs(exact.X).max(),
-                    np.abs(same.U - exact.U).max() / np.abs(exact.U).max())
-        _replay_check(s, Xg[i], Ug[i], st[i], p, tol=max(1e-4, 3 * e_ref), check_merit=False)
+    tot = st["pcg_iters"].sum(axis=1)
+    idx = _parity.sample_indices(M, tot, count=18)
+    assert int(np.argmax(tot)) in idx and len(idx) >= 16
+    res = _parity.check_many([dict(s=solves[i], Xg=Xg[i], Ug=Ug[i], st=st[i], p_gpu=p, label=f"solve {i}")
+                              for i in idx])
+    _parity.report(res, f"M=256 batch (slowest PCG solve {int(np.argmax(tot))}: {int(tot.max())} iterations)")
 
 
 def test_uneven_batch_matches_single_solves():

@@ -73,3 +73,23 @@ def test_power_balance_with_force():
     dE = (energy(q + h * qd, qd + h * qdd) - energy(q - h * qd, qd - h * qdd)) / (2 * h)
     v_tip = _fk.tip_jacobian(s0.links, q) @ qd
     assert abs(dE - (qd @ tau + f @ v_tip)) <= 1e-6 * max(1.0, abs(dE))
+
+
+def test_hypothesis_selection_picks_the_force_that_explains_the_step(oracle_lib):
+    # The measured state is the plant's own step under force 3 of the list:
+    # that hypothesis is at distance 0 and wins; a duplicate of it later in the
+    # list ties and loses to the earlier index; distances are those of the
+    # individual predictions.
+    import dataclasses
+    s = w.chain_solve(8, 0, n=7, N=4)
+    rng = np.random.default_rng(8)
+    x = np.concatenate([rng.uniform(-1, 1, 7), rng.normal(0, 0.3, 7)])
+    tau = rng.normal(0, 2, 7)
+    forces = rng.normal(0, 15, (6, 3))
+    forces[5] = forces[3]
+    meas = oracle.plant_rk4(dataclasses.replace(s, fext=tuple(forces[3])), x, tau, 0.01, 10)
+    j, d = oracle.hypothesis_select(s, x, tau, forces, meas)
+    assert j == 3 and d[3] == 0.0 and d[5] == 0.0
+    assert np.all(np.delete(d, [3, 5]) > 1e-6)
+    other = oracle.plant_rk4(dataclasses.replace(s, fext=tuple(forces[1])), x, tau, 0.01, 10)
+    assert d[1] == np.linalg.norm(other - meas)
