@@ -63,9 +63,78 @@ def measured_traffic():
     return float(vals["traffic-bytes-per-launch"])
 
 
+KERNEL_TRACE_SUMMARY = os.path.join(ROOT, "profiles", "sqp_kernel_7dof_N32_M256_kernel_trace.md")
+
+
+def profiled_kernel(path):
+    """Average duration (ms) of the headline kernel over the timed launches in the
+    committed kernel-trace summary, or None if the kernel sources changed since."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_07625_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    try:
+        with open(path) as fh:
+            for line in fh:
+                k, _, v = line.strip().partition(": ")
+                vals[k] = v
+    except OSError:
+        return None
+    if vals.get("kernel-source-sha256-16") != h.hexdigest()[:16] or "timed-avg-ms" not in vals:
+        return None
+    return float(vals["timed-avg-ms"])
+
+
+# LDS bytes the FP64 one-knot-per-group PCG iteration moves per lane (16 lanes
+# per knot, idle lanes included): the two neighbour vectors of the S~ product
+# and the two of the preconditioner's off-diagonal product (14 FP64 each,
+# 8 x 16-byte reads), the two per-wavefront partial vectors of the reduction
+# (8 FP64 each), and the four FP64 values each lane publishes.
+LDS_BYTES_PER_LANE_PCG_ITER = 4 * 14 * 8 + 2 * 8 * 8 + 4 * 8
+
+
+def lds_report(g, kernel_ms, pcg_iters_launch, M=256, N=32):
+    """LDS traffic of the headline kernel's PCG against the probed LDS peak."""
+    per_clk0, per_s0 = g.probe_lds(0)
+    per_clk1, per_s1 = g.probe_lds(1)
+    lanes = N * 16
+    bytes_launch = float(pcg_iters_launch) * lanes * LDS_BYTES_PER_LANE_PCG_ITER
+    achieved = bytes_launch / (kernel_ms * 1e-3)
+    peak = max(per_s0, per_s1)
+    return dict(bytes_per_launch_pcg=bytes_launch, achieved_GBps=achieved / 1e9, peak_GBps=peak / 1e9,
+                frac=achieved / peak, peak_bytes_per_clk_cu=dict(distinct=per_clk0, broadcast16=per_clk1),
+                peak_GBps_by_pattern=dict(distinct=per_s0 / 1e9, broadcast16=per_s1 / 1e9),
+                model="PCG iterations x N knots x 16 lanes x (4 neighbour vectors x 14 FP64 + 2 x 8 partials "
+                      "+ 4 published FP64) bytes")
+
+
 def _pcts(ms):
     a = np.asarray(ms, dtype=np.float64)
     return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def status_breakdown(g, stats):
+    """Per status bit: (solve, SQP iteration) pairs that carry it, per SQP
+    iteration index; for NO_DESCENT pairs, how far the best candidate's merit
+    sits from the current one relative to it (at convergence the step is below
+    the FP32 resolution of the per-knot merit terms, so the candidates tie)."""
+    st = stats["status"]
+    out = {"pairs": int(st.size)}
+    for name, bit in (("pcg_maxiter", g.ST_PCG_MAXITER), ("nonfinite", g.ST_NONFINITE),
+                      ("no_descent", g.ST_NO_DESCENT), ("exchange", g.ST_EXCHANGE)):
+        m = (st & bit) != 0
+        out[name] = dict(count=int(m.sum()), per_sqp_iteration=[int(v) for v in m.sum(axis=0)])
+    nd = (st & g.ST_NO_DESCENT) != 0
+    if nd.any():
+        m0 = stats["merit0"].astype(np.float64)
+        d = np.abs(stats["merit"].astype(np.float64) - m0) / np.maximum(np.abs(m0), 1e-30)
+        out["no_descent"]["rel_merit_change"] = dict(median=float(np.median(d[nd])), max=float(d[nd].max()))
+        ok = ~nd & ((st & g.ST_NONFINITE) == 0)
+        if ok.any():
+            out["descent_rel_merit_change_median"] = float(np.median(d[ok]))
+    return out
 
 
 def run_batched(g, torch, M, steps, warmup, params, seed=0):
@@ -176,20 +245,28 @@ def precision_report(g, torch, M, steps, pcg_tol):
     return out
 
 
+UNEVEN_SETTINGS = (("fp64-schur", dict(schur_fp64=1)), ("fp32+fp64-inv", dict(schur_fp64=0, fp64_block_inv=1)),
+                   ("fp32", dict(schur_fp64=0)))
+
+
 def uneven_report(g, torch, M=128, steps=3, seed=0):
     """Uneven batch: M solves with DoF from {3, 6, 7} and N from {16, 32, 64, 128},
     10 SQP iterations; per-shape launches against one mixed-shape launch, the
-    autotuned mapping, and the graph-captured step; both precisions. The long
-    solves (6-7 DoF, N > 64) split across four workgroups in the eager launches
-    (not under graph capture); `one_workgroup_ms` is the mixed-shape launch with
-    the split switched off."""
+    autotuned mapping, and the graph-captured step (config 3's figure:
+    `solves_per_s` is M over the graph replay's time); the FP64-Schur default,
+    FP32 with the FP64 diagonal-block inverse, and all FP32. The long solves
+    (6-7 DoF, N > 64) split across workgroups; `one_workgroup_ms` is the
+    mixed-shape launch with the split switched off. (Per-bucket errors against
+    the oracle come from tests/accuracy_report.py.)"""
     import workload as w
     solves = w.uneven_batch(seed, M=M)
     xs, goal, X0, U0 = g.pack_inputs(solves)
     out = {}
 
+    X, U = X0.clone(), U0.clone()
+    st = None
+
     def timed(b, graph=False):
-        X, U = X0.clone(), U0.clone()
         ms = []
         for r in range(steps + 1):
             X.copy_(X0)
@@ -197,15 +274,16 @@ def uneven_report(g, torch, M=128, steps=3, seed=0):
             b.reset_warm_start()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            b.step(xs, goal, X, U, 10, graph=graph)
+            b.step(xs, goal, X, U, 10, st, graph=graph)
             e1.record()
             torch.cuda.synchronize()
             if r:
                 ms.append(e0.elapsed_time(e1))
         return float(np.median(ms))
 
-    for fp64 in (1, 0):
-        b = g.Batch.from_solves(solves, g.Params(sqp_iters=10, schur_fp64=fp64))
+    for name, kw in UNEVEN_SETTINGS:
+        b = g.Batch.from_solves(solves, g.Params(sqp_iters=10, **kw))
+        st = b.stats_buffer(10)
         b.set_dispatch(g.DISPATCH_GROUPED)
         t_grouped = timed(b)
         b.set_dispatch(g.DISPATCH_MIXED)
@@ -213,14 +291,27 @@ def uneven_report(g, torch, M=128, steps=3, seed=0):
         buckets = b.autotune(xs, goal, X0, U0, n_iters=2, reps=3)
         t_tuned = timed(b)
         t_graph = timed(b, graph=True)
+        stats = g.Batch.decode_stats(st, M, 10)
+        flops = sum(g.sqp_iteration_flops(sv.n, sv.N, 8, stats["pcg_iters"][i]) for i, sv in enumerate(solves))
+        status = {k: int(((stats["status"] & bit) != 0).sum()) for k, bit in
+                  (("pcg_maxiter", g.ST_PCG_MAXITER), ("nonfinite", g.ST_NONFINITE), ("exchange", g.ST_EXCHANGE),
+                   ("no_descent", g.ST_NO_DESCENT))}
         b.set_split(1)
         t_one = timed(b)
         b.set_split(4)
         b.close()
-        out["fp64-schur" if fp64 else "fp32"] = dict(
+        out[name] = dict(
             grouped_ms=t_grouped, mixed_ms=t_mixed, tuned_mixed_ms=t_tuned, tuned_mixed_graph_ms=t_graph,
             one_workgroup_ms=t_one,
-            solves_per_s=M / (min(t_tuned, t_graph) * 1e-3),
+            solves_per_s=M / (t_graph * 1e-3), eager_solves_per_s=M / (t_tuned * 1e-3),
+            roofline=dict(bound="alu", flops_per_launch=flops, achieved=flops / (t_graph * 1e-3) / 1e12,
+                          peak=PEAK_ALU / 1e12, unit="TFLOP/s", frac=flops / (t_graph * 1e-3) / PEAK_ALU,
+                          kernel="gato::sqp_mixed_kernel (split: true)", time="graph replay"),
+            status_bits=status,
+            pcg_iters_per_solve_by_bucket={f"{n}x{N}": float(np.mean([stats["pcg_iters"][i].sum()
+                                                                      for i, sv in enumerate(solves)
+                                                                      if (sv.n, sv.N) == (n, N)]))
+                                           for n, N in sorted({(sv.n, sv.N) for sv in solves})},
             buckets=[(x["n_dof"], x["N"], x["count"], x["kpt"]) for x in buckets])
         print(f"# uneven {out}", file=sys.stderr, flush=True)
     return out
@@ -326,7 +417,7 @@ def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, seed=0, pcg_t
              for t in range(100, ticks, 100)}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    run = closed_loop.run(b, xs, goal, ticks, n_iters=iters, disturbance=kicks.get)
+    run = closed_loop.run(b, xs, goal, ticks, n_iters=iters, disturbance=kicks.get, count_pcg=True)
     wall = time.perf_counter() - t0
     b.close()
     q = run.states.cpu().numpy()[:, :, :7].astype(np.float64)
@@ -335,8 +426,15 @@ def closed_loop_report(g, torch, M=256, N=64, ticks=1000, iters=3, seed=0, pcg_t
     mean_track = track.mean(axis=1)
     dev_ms = float(np.sum(run.tick_ms))
     p50, p99 = _pcts(run.tick_ms)
+    solve_ms = float(np.sum(run.solve_ms))
+    flops = (M * ticks * g.sqp_iteration_flops(7, N, 8, np.zeros(iters))
+             + run.pcg_iters * (g.sqp_iteration_flops(7, N, 8, [1]) - g.sqp_iteration_flops(7, N, 8, [0])))
     out = dict(M=M, N=N, ticks=ticks, sqp_iters_per_tick=iters, pcg_tol=pcg_tol,
                solves_per_s=M * ticks / (dev_ms * 1e-3), wall_solves_per_s=M * ticks / wall,
+               roofline=dict(bound="alu", flops=flops, solver_ms=solve_ms, achieved=flops / (solve_ms * 1e-3) / 1e12,
+                             peak=PEAK_ALU / 1e12, unit="TFLOP/s", frac=flops / (solve_ms * 1e-3) / PEAK_ALU,
+                             kernel="gato::sqp_kernel<7, 2, double, false, false> (serving step, shift 1)",
+                             pcg_iters=int(run.pcg_iters)),
                tick_p50_ms=p50, tick_p99_ms=p99,
                tracking_error_rad=dict(mean=float(mean_track.mean()), final=float(mean_track[-1]),
                                        before_kicks=[float(mean_track[t]) for t in range(100, ticks, 100)],
@@ -385,7 +483,9 @@ def hypothesis_report(g, torch, P=32, Hs=(1, 8, 32), ticks=200, seed=4, sigma=12
     synthetic 7-DoF chains, N = 32, 2 SQP iterations per tick): P instances whose
     plants feel a constant unknown tip force N(0, 20^2) N per axis, each solved
     with H force hypotheses re-centred every tick on the most consistent one.
-    Reports solves/s, the force-estimate error and the tracking error."""
+    Reports solves/s (device time of the ticks: re-solves, plants, predictions
+    and the selection in the library, no host synchronisation per tick), the
+    force-estimate error and the tracking error."""
     import workload as w
     from paper_2510_07625_amd import hypotheses
     rng = np.random.default_rng([seed, 7])
@@ -407,7 +507,8 @@ def hypothesis_report(g, torch, P=32, Hs=(1, 8, 32), ticks=200, seed=4, sigma=12
         track = np.linalg.norm(r.states[:, :, :7] - qg[None], axis=2).mean(axis=1)
         ferr = np.linalg.norm(r.estimates - f_true[None], axis=2).mean(axis=1)
         cost = hypotheses.realized_cost(r, base)
-        out.append(dict(H=H, P=P, ticks=ticks, solves_per_s=P * H * ticks / dt_s,
+        out.append(dict(H=H, P=P, ticks=ticks, solves_per_s=P * H * ticks / (float(np.sum(r.tick_ms)) * 1e-3),
+                        wall_s=dt_s,
                         tick_p50_ms=float(np.median(r.tick_ms)), tick_p99_ms=float(np.percentile(r.tick_ms, 99)),
                         force_error_N=dict(start=float(ferr[0]), end=float(ferr[-20:].mean())),
                         realized_cost=dict(mean=float(cost.mean()), median=float(np.median(cost))),
@@ -444,7 +545,7 @@ def heatmap(g, torch, Ms=(1, 8, 32, 64, 128, 256, 512), Ns=(8, 16, 32, 64, 128),
     return rows
 
 
-def serving(g, torch, rates, duration_s, pool=256, iters=1, slots=3, deadline_s=1e-3, seed=0):
+def serving(g, torch, rates, duration_s, duration_python_s, pool=256, iters=1, slots=3, deadline_s=1e-3, seed=0):
     """Served MPC loop: Poisson arrivals over a pool of instances, each request
     warm-started from its instance's device-resident trajectory shifted one knot,
     goal perturbed by N(0, 0.05) rad; continuous batching over `slots` streams,
@@ -460,12 +561,15 @@ def serving(g, torch, rates, duration_s, pool=256, iters=1, slots=3, deadline_s=
     x0 = np.stack([s.xs for s in solves])
     for rate in rates:
         rng = np.random.default_rng([seed, int(rate)])
-        n = int(rate * duration_s)
-        t = np.cumsum(rng.exponential(1.0 / rate, n))
-        inst = rng.integers(pool, size=n)
-        reqs = [Request(i, int(inst[i]), float(t[i]), goals[inst[i]] + rng.normal(0.0, 0.05, goals.shape[1]))
-                for i in range(n)]
+        n_all = int(rate * max(duration_s, duration_python_s))
+        t = np.cumsum(rng.exponential(1.0 / rate, n_all))
+        inst = rng.integers(pool, size=n_all)
+        all_reqs = [Request(i, int(inst[i]), float(t[i]), goals[inst[i]] + rng.normal(0.0, 0.05, goals.shape[1]))
+                    for i in range(n_all)]
         for loop in ("python", "native"):
+            # The same stream; the Python scheduler runs its first seconds only.
+            n = int(rate * (duration_python_s if loop == "python" else duration_s))
+            reqs = all_reqs[:n]
             b.set_trajectories(X, U)
             b.reset_warm_start()
             torch.cuda.synchronize()
@@ -486,19 +590,46 @@ def serving(g, torch, rates, duration_s, pool=256, iters=1, slots=3, deadline_s=
     return out
 
 
-def cpu_baseline(n_solves=32, threads=None):
-    """The FP64 oracle (dense KKT LU per SQP iteration) on a bounded sample."""
+def cpu_model():
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        info = {}
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            info[k.strip()] = v.strip()
+        return dict(model=info.get("Model name", "?"), max_mhz=info.get("CPU max MHz", "?"),
+                    sockets=info.get("Socket(s)", "?"), threads_per_core=info.get("Thread(s) per core", "?"))
+    except Exception as e:  # pragma: no cover - lscpu missing
+        return dict(model=f"unknown ({e})")
+
+
+def cpu_baseline():
+    """The FP64 oracle as it stands, on bounded samples of the headline workload
+    (7-DoF, N = 32, 10 SQP iterations): its exact Riccati mode (the fair CPU
+    baseline: the same QP solved exactly by a block recursion) and its dense
+    KKT LU mode (the oracle of record), each on one core and on every core of
+    the host (one solve per thread). `value` is the Riccati mode on every
+    core."""
     import oracle
     import workload as w
     oracle.lib()
-    threads = threads or len(os.sched_getaffinity(0))
-    solves = w.chain_batch(0, n_solves)
-    t0 = time.perf_counter()
-    oracle.sqp_batch(solves, oracle.Params(sqp_iters=10, kkt_mode=0), threads=threads)
-    dt = time.perf_counter() - t0
-    return dict(value=n_solves / dt, unit="solves/s", cores=int(threads), kind="oracle",
-                sample=f"{n_solves} solves of the same workload (7-DoF, N=32, 10 SQP iterations, dense FP64 "
-                       f"KKT LU), one solve per thread, {dt:.1f} s wall")
+    cores = len(os.sched_getaffinity(0))
+    legs = {}
+    for name, mode, n1, nall in (("riccati", 2, 96, 16 * cores), ("dense_lu", 0, 12, 2 * cores)):
+        for tag, n_solves, threads in (("1_core", n1, 1), ("all_cores", nall, cores)):
+            solves = w.chain_batch(0, n_solves)
+            t0 = time.perf_counter()
+            oracle.sqp_batch(solves, oracle.Params(sqp_iters=10, kkt_mode=mode), threads=threads)
+            dt = time.perf_counter() - t0
+            legs[f"{name}_{tag}"] = dict(solves_per_s=n_solves / dt, solves=n_solves, threads=threads, wall_s=dt)
+            print(f"# cpu baseline {name} {tag}: {legs[f'{name}_{tag}']}", file=sys.stderr, flush=True)
+    best = legs["riccati_all_cores"]
+    return dict(value=best["solves_per_s"], unit="solves/s", cores=int(cores), kind="oracle",
+                sample=f"{best['solves']} solves of the headline workload (7-DoF, N=32, 10 SQP iterations), the "
+                       f"oracle's exact Riccati mode, one solve per thread on {cores} threads, "
+                       f"{best['wall_s']:.1f} s wall",
+                legs=legs, cpu=cpu_model())
 
 
 def main():
@@ -517,15 +648,18 @@ def main():
     ap.add_argument("--no-task-space", action="store_true", help="skip the task-space (figure-8) report")
     ap.add_argument("--task-closed-loop-ticks", type=int, default=300,
                     help="control ticks of the figure-8 closed loop (0 skips it)")
-    ap.add_argument("--heatmap", action="store_true",
-                    help="also time one SQP iteration over M in 1..512 x N in 8..128 (6-DoF chains)")
-    ap.add_argument("--hypotheses", action="store_true",
-                    help="also run the batched hypothesize-and-test over tip forces")
-    ap.add_argument("--rho-sweep", action="store_true",
-                    help="also run the batched rho sweep with line-search rho adaptation")
+    ap.add_argument("--no-heatmap", action="store_true",
+                    help="skip the map of one SQP iteration over M in 1..512 x N in 8..128 (6-DoF chains)")
+    ap.add_argument("--no-hypotheses", action="store_true",
+                    help="skip the batched hypothesize-and-test over tip forces")
+    ap.add_argument("--no-rho-sweep", action="store_true",
+                    help="skip the batched rho sweep with line-search rho adaptation")
+    ap.add_argument("--plain-reps", type=int, default=50, help="timed calls per M of the plain form")
     ap.add_argument("--closed-loop-ticks", type=int, default=1000, help="ticks of the closed-loop batch (0 skips)")
-    ap.add_argument("--serve-seconds", type=float, default=2.0,
-                    help="duration of each served-loop rate (0 skips the served loop)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="duration of each served-loop rate for the native loop (0 skips the served loop)")
+    ap.add_argument("--serve-seconds-python", type=float, default=2.0,
+                    help="duration of each served-loop rate for the Python scheduler")
     ap.add_argument("--serve-rates", type=str, default="2000,5000,10000,20000,50000")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a plain device copy of this many MiB (for HBM counter scaling)")
@@ -533,6 +667,7 @@ def main():
     if args.profile_run:
         args.no_sweep = args.no_cpu = True
         args.serve_seconds = 0
+        args.no_heatmap = args.no_hypotheses = args.no_rho_sweep = True
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; solves shard across GPUs without any exchange, "
                                    "so a multi-GPU run is M/G independent copies of the 1-GPU run",
@@ -559,11 +694,24 @@ def main():
     pcg = main_res["stats"]["pcg_iters"]
     flops_launch = sum(g.sqp_iteration_flops(7, 32, params.n_alpha, pcg[i]) for i in range(M))
     achieved = flops_launch / (kern.mean() * 1e-3)
+    prof = profiled_kernel(KERNEL_TRACE_SUMMARY)
     roof = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_ALU / 1e12, unit="TFLOP/s",
                 frac=achieved / PEAK_ALU, traffic=measured_traffic(),
                 kernel="gato::sqp_kernel<7, 1, double, false, false>",
                 flops_per_launch=flops_launch, avg_kernel_ms=float(kern.mean()),
-                pcg_iters_per_solve=float(pcg.sum(axis=1).mean()))
+                flops_count=dict(per_solve_sqp_iteration=g.sqp_iteration_flops(7, 32, params.n_alpha, [0]),
+                                 per_pcg_iteration=g.sqp_iteration_flops(7, 32, params.n_alpha, [1])
+                                 - g.sqp_iteration_flops(7, 32, params.n_alpha, [0]),
+                                 pcg_iterations_per_launch=int(pcg.sum())),
+                pcg_iters_per_solve=float(pcg.sum(axis=1).mean()),
+                pcg_iters_slowest_solve=int(pcg.sum(axis=1).max()))
+    try:
+        roof["lds"] = lds_report(g, float(kern.mean()), int(pcg.sum()), M=M)
+    except Exception as e:  # the probe is a measurement aid; its failure must not hide the headline
+        roof["lds"] = dict(error=str(e))
+    if prof is not None:
+        roof["profiled"] = dict(avg_kernel_ms=prof, frac=flops_launch / (prof * 1e-3) / PEAK_ALU,
+                                summary=os.path.relpath(KERNEL_TRACE_SUMMARY, ROOT))
     sweep, plain = [], []
     if not args.no_sweep:
         for m in SWEEP:
@@ -572,7 +720,7 @@ def main():
             a, b = _pcts(km)
             sweep.append(dict(M=m, solves_per_s=m / (km.mean() * 1e-3), p50_ms=a, p99_ms=b))
         for m in SWEEP:
-            ms = run_plain(g, torch, m, 3 if m >= 64 else 5, params)
+            ms = run_plain(g, torch, m, args.plain_reps, params)
             a, b = _pcts(ms)
             plain.append(dict(M=m, solves_per_s=m / (np.mean(ms) * 1e-3), p50_ms=a, p99_ms=b))
     e2e = [float("nan")] if args.profile_run else end_to_end_ms(g, torch, M, 10, params)
@@ -587,13 +735,13 @@ def main():
     task = {} if args.profile_run or args.no_task_space else task_space_report(g, torch)
     if task and args.task_closed_loop_ticks > 0:
         task["closed_loop"] = task_closed_loop_report(g, torch, ticks=args.task_closed_loop_ticks)
-    hmap = heatmap(g, torch) if args.heatmap else []
-    rsweep = rho_sweep(g, torch) if args.rho_sweep else []
-    hyps = hypothesis_report(g, torch) if args.hypotheses else []
+    hmap = [] if args.no_heatmap else heatmap(g, torch)
+    rsweep = [] if args.no_rho_sweep else rho_sweep(g, torch)
+    hyps = [] if args.no_hypotheses else hypothesis_report(g, torch)
     closed = {} if args.profile_run or args.closed_loop_ticks <= 0 else closed_loop_report(
         g, torch, ticks=args.closed_loop_ticks)
-    served = (serving(g, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds)
-              if args.serve_seconds > 0 else [])
+    served = (serving(g, torch, [float(r) for r in args.serve_rates.split(",")], args.serve_seconds,
+                      args.serve_seconds_python) if args.serve_seconds > 0 else [])
     out = {
         "metric": "SQP solves/s + p99 latency, 7-DoF N=32 batch 1-256, batched vs plain",
         "value": value,
@@ -612,6 +760,7 @@ def main():
                    "M": M, "N": 32, "n_dof": 7, "sqp_iters": 10, "pcg_tol": args.pcg_tol},
         "p50_ms": p50,
         "p99_ms": p99,
+        "status_bits": status_breakdown(g, main_res["stats"]),
         "end_to_end_ms": dict(zip(("p50", "p99"), _pcts(e2e))),
         "sweep_batched": sweep,
         "seeds_solves_per_s": {str(k): v for k, v in seeds.items()},

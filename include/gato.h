@@ -170,7 +170,12 @@ size_t gato_workspace_bytes(int n_dof, int N, const gato_params *p);
 int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs, const gato_params *p,
                       void *hip_stream, gato_batch **out);
 
-/* Frees all device memory of the batch (synchronises its stream). NULL is ignored. */
+/*
+ * Frees all device memory of the batch. Synchronises the whole device first
+ * (work of serving contexts on their own streams may still use the batch),
+ * then releases the captured graph, then the memory. Serving contexts of the
+ * batch must not be used afterwards. NULL is ignored.
+ */
 void gato_batch_destroy(gato_batch *b);
 
 /* Number of solves, and the padded maxima n_max, N_max of the batch. */
@@ -384,6 +389,37 @@ int gato_plant_step(gato_batch *b, int n, const int *d_slots, const float *d_x, 
 int gato_set_external_force(gato_batch *b, const double *h_f);
 
 /*
+ * Hypothesis selection of the disturbance case study (Sec. IV-D: the solves of
+ * a batch differ only in an assumed external force; after a control step the
+ * hypothesis whose model best explains the measured motion becomes the
+ * estimate and the hypotheses are re-centred on it). The batch holds P
+ * instances of H solves each, solve p H + j being hypothesis j of instance p
+ * (same robot). For each instance, in one kernel with no host
+ * synchronisation:
+ *   - hypothesis j scores the Euclidean distance, over the solve's own 2n
+ *     state entries and in FP64, between its one-step prediction
+ *     d_pred[p H + j] ([P H][nx_max], device; e.g. gato_plant_step of every
+ *     slot under its own force) and the measured state d_meas[p]
+ *     ([P][nx_max], device);
+ *   - the smallest distance wins (ties to the smaller j, so hypothesis 0
+ *     wins ties; non-finite distances never win; if none is finite, j = 0);
+ *   - the estimate moves to the winner: d_est[p] += d_off[j] (d_est [P][3],
+ *     FP64, device, in/out: the current estimates, of which hypothesis j
+ *     assumed d_est[p] + d_off[j]; d_off [H][3], FP64, device: the offsets of
+ *     the hypotheses from their estimate, d_off[0] = 0 by convention);
+ *   - the hypotheses are re-centred: solve p H + j assumes the force
+ *     d_est[p] + d_off[j] (rounded to FP32) in every later call, as if set by
+ *     gato_set_external_force;
+ *   - d_sel[p] = j (device, may be NULL); d_dist[p H + j] = the distances
+ *     (device FP64, may be NULL).
+ * Stream-ordered on hip_stream (NULL: the batch stream). Errors: GATO_EINVAL
+ * (P, H < 1, P H != M, NULL buffers, a solve that is not a serial chain, or
+ * the solves of an instance with different DoF), GATO_EDEVICE.
+ */
+int gato_select_hypotheses(gato_batch *b, int P, int H, const float *d_pred, const float *d_meas, const double *d_off,
+                           double *d_est, int *d_sel, double *d_dist, void *hip_stream);
+
+/*
  * Reference tip positions of the task-space term: d_pref [M][N_max][3]
  * (device, base frame, knot k of solve i at (i N_max + k) 3) is copied into
  * the batch on its stream, so the caller may reuse the buffer once the stream
@@ -438,9 +474,12 @@ int gato_set_dispatch(gato_batch *b, int mode);
  * inner products through device memory at every PCG iteration; the rest of the
  * SQP iteration is computed by each part alike, and part 0 writes the results.
  * The split applies to gato_step, gato_solve and gato_profile_phases as a
- * cooperative launch (every workgroup resident at once). Under gato_step_graph
- * or any stream capture, with parts = 1, and when even two workgroups per
- * solve do not fit, every solve runs on one workgroup. The inner products are
+ * cooperative launch (every workgroup resident at once), and to
+ * gato_step_graph of a mixed-shape batch as a cooperative kernel node (after a
+ * node that clears the exchange words). Under the caller's own stream
+ * capture, in gato_step_graph of a batch launched per shape group, with
+ * parts = 1, and when even two workgroups per solve do not fit, every solve
+ * runs on one workgroup. The inner products are
  * summed per part first, so results differ from the one-workgroup form at
  * rounding level. A part that waits too long for another sets
  * GATO_ST_EXCHANGE: every wait polls at most max_polls times (0: the default,
@@ -488,8 +527,10 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
  * gato_step through a HIP graph: the first call with a given argument tuple
  * (and dispatch mapping) captures the step's launch(es) into a graph and
  * instantiates it; later calls with the same tuple replay it with one graph
- * launch on the batch stream. A new tuple or mapping recaptures. Same
- * semantics, errors and stream ordering as gato_step.
+ * launch on the batch stream. A new tuple or mapping recaptures. A mixed-shape
+ * batch with long solves split across workgroups (gato_set_split) is built as
+ * two nodes: a kernel that clears the exchange words, then the split kernel as
+ * a cooperative node. Same semantics, errors and stream ordering as gato_step.
  */
 int gato_step_graph(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U, int n_iters,
                     gato_solve_stats *d_stats);

@@ -7,8 +7,11 @@ fallback: if the library is missing, loading it raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import sys
+import weakref
 from dataclasses import dataclass, field
 from typing import Sequence
 
@@ -17,6 +20,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgato.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "gato.h")
+HEADERS = (HEADER, os.path.join(os.path.dirname(HERE), "include", "gato_probe.h"))
 
 GATO_OK, GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE, GATO_EUNSUPPORTED = 0, -1, -2, -3, -4
 ST_PCG_MAXITER, ST_NONFINITE, ST_NO_DESCENT, ST_ADMIT_REJECT, ST_EXCHANGE = 1, 2, 4, 8, 16
@@ -72,7 +76,7 @@ EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "
            "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
            "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_serve_run", "gato_set_tip_reference",
            "gato_tip_positions", "gato_get_multipliers", "gato_set_multipliers", "gato_shift_warm_start",
-           "gato_last_error")
+           "gato_last_error", "gato_probe_lds", "gato_select_hypotheses")
 
 _lib = None
 
@@ -129,10 +133,28 @@ def lib() -> C.CDLL:
         L.gato_set_mapping.argtypes = [vp, ip, ip, ip]
         L.gato_autotune.argtypes = [vp, vp, vp, vp, vp, ip, ip]
         L.gato_step_graph.argtypes = [vp, vp, vp, vp, vp, ip, vp]
+        L.gato_select_hypotheses.argtypes = [vp, ip, ip, vp, vp, vp, vp, vp, vp, vp]
+        L.gato_probe_lds.argtypes = [ip, ip, C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.gato_last_error.argtypes = []
         L.gato_last_error.restype = C.c_char_p
         _lib = L
     return _lib
+
+
+# Live handles, released before the interpreter shuts down: serving contexts
+# first (their streams may still run work on a batch's memory), then batches.
+# At interpreter exit the HIP runtime itself may already be going away, so
+# finalizers that run after this point release nothing.
+_live_ctx: "weakref.WeakSet" = weakref.WeakSet()
+_live_batches: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _release_all():
+    for c in list(_live_ctx):
+        c.close()
+    for b in list(_live_batches):
+        b.close()
 
 
 def _check(rc: int) -> int:
@@ -199,33 +221,44 @@ def rbd_flops(n_dof: int):
 
 
 def sqp_iteration_flops(n: int, N: int, n_alpha: int, pcg_iters) -> float:
-    """Algorithmic FLOPs of one SQP iteration of one solve, counted once per knot.
+    """Algorithmic FLOPs of SQP iterations of one solve: what the method of
+    Algorithm 1 computes, counted once, independent of how a kernel arranges it.
 
     pcg_iters may be an array (one entry per SQP iteration); the result is the
-    sum over those iterations. Per knot: dynamics + 2n Jacobian columns + n
-    inverse-inertia columns (LQ), the Schur row products, the diagonal-block
-    inverse (2 nx^3), the two preconditioner off-diagonal blocks (4 nx^3 each);
-    per PCG iteration two block-tridiagonal matrix-vector products (6 nx FLOPs
-    per row each) plus vector updates and dot products (12 per row); step
-    recovery; and per line-search candidate and knot one forward dynamics plus
-    trial point, defect and cost.
+    sum over those iterations. Per SQP iteration:
+      * dynamics and derivatives at N-1 knots: forward dynamics, 2n columns of
+        the dynamics Jacobian and n columns of M^-1 (counted on the kernels'
+        own rigid-body templates, rbd_flops);
+      * Schur complement and preconditioner blocks (Eqs. (5)-(6)):
+        N (7 nx^3 + 2 nx^2 nu);
+      * per PCG iteration (Sec. II-B): one product with the block-tridiagonal
+        S~ and one with the block-tridiagonal P, 2 (3N - 2) nx^2 FLOPs each,
+        plus the vector updates and inner products, 10 N nx;
+      * step recovery (Eq. (4)): (N - 1)(2 nx^2 + 2 nx nu) + N nx;
+      * line search (Eqs. (3), (7)): n_alpha (N - 1) forward dynamics.
     """
     import numpy as _np
     f_fd, f_col, f_sol = rbd_flops(n)
     nx, nu = 2 * n, n
-    k = N - 1
-    lq = k * (f_fd + 2 * n * f_col + n * f_sol + 7 * nx + 3 * nu)
-    schur = k * (nx * nx * (nx + nu) * 2 + nx * (nx + nu) + nx + nx * (2 * (nx + nu) + 3))
-    inv = k * (2 * nx ** 3 + nx)
-    precond = N * (8 * nx ** 3 + 2 * nx * nx)
-    rows = N * nx
-    pcg_init = rows * (6 * nx + 2) + rows + 2 * rows * 6 * nx + 4 * rows
-    pcg_iter = rows * (12 * nx + 14)
-    step = rows * (2 * nx + 3) + k * nu * (2 * nx + 2)
-    ls = n_alpha * k * (f_fd + 2 * (2 * nx + nu) + 4 * nx + 3 * nx + 3 * nu) + n_alpha * (7 * nx + N)
-    fixed = lq + schur + inv + precond + pcg_init + step + ls
+    lq = (N - 1) * (f_fd + 2 * n * f_col + n * f_sol)
+    schur = N * (7 * nx ** 3 + 2 * nx * nx * nu)
+    step = (N - 1) * (2 * nx * nx + 2 * nx * nu) + N * nx
+    ls = n_alpha * (N - 1) * f_fd
+    pcg_iter = 4 * (3 * N - 2) * nx * nx + 10 * N * nx
+    fixed = lq + schur + step + ls
     its = _np.atleast_1d(_np.asarray(pcg_iters, dtype=_np.float64))
     return float(its.size * fixed + pcg_iter * its.sum())
+
+
+def probe_lds(pattern: int, iters: int = 4096):
+    """gato_probe_lds (include/gato_probe.h): delivered LDS bytes per clock per
+    CU and per second over the device, for pattern 0 (distinct addresses) or 1
+    (16-lane broadcast)."""
+    per_clk, per_s = C.c_double(), C.c_double()
+    rc = lib().gato_probe_lds(int(pattern), int(iters), C.byref(per_clk), C.byref(per_s))
+    if rc != 0:
+        raise GatoError(rc, "gato_probe_lds failed")
+    return per_clk.value, per_s.value
 
 
 def workspace_bytes(n_dof: int, N: int, params: Params | None = None) -> int:
@@ -277,6 +310,7 @@ class Batch:
         _check(lib().gato_batch_create(self.M, rob, prob, C.byref(prm), C.c_void_p(self.stream.cuda_stream),
                                        C.byref(handle)))
         self._h = handle
+        _live_batches.add(self)
         M, n, N = C.c_int(), C.c_int(), C.c_int()
         _check(lib().gato_batch_shape(self._h, C.byref(M), C.byref(n), C.byref(N)))
         self.n_max, self.N_max = n.value, N.value
@@ -317,11 +351,15 @@ class Batch:
         self._pref = pref          # keep it alive until the stream has copied it
 
     def close(self):
+        """gato_batch_destroy (synchronises the device first). Idempotent."""
         if getattr(self, "_h", None):
             lib().gato_batch_destroy(self._h)
             self._h = None
+        _live_batches.discard(self)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -510,6 +548,22 @@ class Batch:
         a = np.ascontiguousarray(np.broadcast_to(np.asarray(f, np.float64), (self.M, 3)))
         _check(lib().gato_set_external_force(self._h, a.ctypes.data_as(C.POINTER(C.c_double))))
 
+    def select_hypotheses(self, P: int, H: int, pred, meas, off, est, sel=None, dist=None, stream=None):
+        """gato_select_hypotheses: pred [P H, nx_max], meas [P, nx_max] float32; off [H, 3] and est
+        [P, 3] float64 (est updated in place); sel [P] int32 and dist [P H] float64 optional."""
+        import torch
+        self._chk(pred, (P * H, self.nx_max))
+        self._chk(meas, (P, self.nx_max))
+        self._chk(off, (H, 3), torch.float64)
+        self._chk(est, (P, 3), torch.float64)
+        if sel is not None:
+            self._chk(sel, (P,), torch.int32)
+        if dist is not None:
+            self._chk(dist, (P * H,), torch.float64)
+        st = stream.cuda_stream if stream is not None else None
+        _check(lib().gato_select_hypotheses(self._h, int(P), int(H), _dptr(pred), _dptr(meas), _dptr(off), _dptr(est),
+                                            _dptr(sel), _dptr(dist), C.c_void_p(st) if st else None))
+
     def reset_warm_start(self):
         _check(lib().gato_reset_warm_start(self._h))
 
@@ -549,6 +603,7 @@ class ServeContext:
         h = C.c_void_p()
         _check(lib().gato_serve_ctx_create(batch._h, self.capacity, self.n_iters, C.byref(h)))
         self._h = h
+        _live_ctx.add(self)
         p = [C.c_void_p() for _ in range(6)]
         _check(lib().gato_serve_ctx_buffers(self._h, *[C.byref(x) for x in p]))
         cap, nx, nu = self.capacity, batch.nx_max, batch.nu_max
@@ -584,8 +639,11 @@ class ServeContext:
         if getattr(self, "_h", None):
             lib().gato_serve_ctx_destroy(self._h)
             self._h = None
+        _live_ctx.discard(self)
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libgato.so")
 ARCH = os.environ.get("GATO_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["sqp_mixed_f64.hip", "sqp_mixed_f32.hip", "sqp_n7.hip", "sqp_n6.hip", "sqp_n3.hip", "sqp_task.hip", "sqp_mixed_task.hip",
            "gato_api.hip",
-           "gato_plant.hip", "gato_flops.cpp"]
+           "gato_plant.hip", "gato_flops.cpp", "gato_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

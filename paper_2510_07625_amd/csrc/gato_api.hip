@@ -108,6 +108,7 @@ struct gato_batch {
   unsigned *d_plant_status = nullptr;  // [M], used when the caller passes none
   double *d_rho = nullptr;             // [M] per-solve damping
   bool task = false;                   // some solve has a tip tracking term (task-space kernels)
+  bool fe_on_device = false;           // tip forces were last set on the device (gato_select_hypotheses)
   float *d_pref = nullptr;             // [M][N_max][3] reference tip positions
   // Launch groups: solves of one (n, kpt) shape, longest horizon first.
   struct Group {
@@ -121,6 +122,7 @@ struct gato_batch {
   // Split long solves (6-7 DoF, N > 64): four workgroups per solve
   // sharing the PCG through the exchange words, when the launch fits the chip.
   unsigned long long *d_xch = nullptr;
+  size_t xwords = 0;             // exchange words of all split solves
   int n_split = 0;               // solves that can split
   int split_parts = gato::kSplitParts;   // gato_set_split: 4 (split where possible) or 1
   int split_polls = 0;                   // polls before a wait gives up (0: the kernel's default)
@@ -136,11 +138,29 @@ struct gato_batch {
   unsigned mapping_gen = 0;
 };
 
+// Brings the host copy of the descriptors' tip forces up to date after they
+// were changed on the device, before the host copy is uploaded again.
+static int pull_device_forces(gato_batch *b) {
+  if (!b->fe_on_device) return GATO_OK;
+  std::vector<SolveDesc> d(b->M);
+  hipError_t e = b->stream ? hipStreamSynchronize(b->stream) : hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(d.data(), b->d_desc, b->M * sizeof(SolveDesc), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy(desc forces)");
+  for (int i = 0; i < b->M; ++i) {
+    for (int a = 0; a < 3; ++a) b->desc[i].chain.fe[a] = d[i].chain.fe[a];
+    b->desc[i].chain.has_fe = d[i].chain.has_fe;
+  }
+  b->fe_on_device = false;
+  return GATO_OK;
+}
+
 // Uploads the descriptors and rebuilds the launch groups and the decreasing-work
 // order from b->desc (after create and after every mapping change).
 static int rebuild_dispatch(gato_batch *b) {
   const int M = b->M;
   const auto &desc = b->desc;
+  const int frc = pull_device_forces(b);
+  if (frc != GATO_OK) return frc;
   hipError_t e = hipMemcpy(b->d_desc, desc.data(), M * sizeof(SolveDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(desc)");
   for (auto &g : b->groups) {
@@ -385,6 +405,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     off += l.total * (can_split ? gato::kSplitParts : 1);
   }
   b->ws_bytes = off;
+  b->xwords = (size_t)xwords;
   b->desc = desc;
 
   hipError_t e;
@@ -442,8 +463,15 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
 
 void gato_batch_destroy(gato_batch *b) {
   if (!b) return;
-  if (b->stream) (void)hipStreamSynchronize(b->stream);
-  else (void)hipDeviceSynchronize();
+  // Every stream that may still run work on this batch's memory (the batch
+  // stream, serving contexts' streams, the capture stream) is drained first;
+  // then the objects that refer to the memory (the instantiated graph and its
+  // capture stream) go before the memory itself.
+  (void)hipDeviceSynchronize();
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  b->cap_stream = nullptr;
   for (auto &g : b->groups) {
     if (g.d_order) (void)hipFree(g.d_order);
     for (int *o : g.d_order_split)
@@ -453,8 +481,6 @@ void gato_batch_destroy(gato_batch *b) {
   for (int *o : b->d_order_split_all)
     if (o) (void)hipFree(o);
   if (b->d_xch) (void)hipFree(b->d_xch);
-  if (b->graph) (void)hipGraphExecDestroy(b->graph);
-  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->d_ws) (void)hipFree(b->d_ws);
   if (b->d_lam) (void)hipFree(b->d_lam);
@@ -527,7 +553,7 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split 
   }
   gato::KArgs as = a;
   if (split) {
-    b->epoch = b->epoch % 65535u + 1u;
+    b->epoch = b->epoch % (gato::kGraphEpoch - 1u) + 1u;
     as.epoch = b->epoch;
     as.xch = b->d_xch;
     as.xspin = b->split_polls;
@@ -1111,6 +1137,26 @@ int gato_set_external_force(gato_batch *b, const double *h_f) {
   }
   e = hipMemcpy(b->d_desc, b->desc.data(), b->M * sizeof(SolveDesc), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(desc)");
+  b->fe_on_device = false;
+  return GATO_OK;
+}
+
+int gato_select_hypotheses(gato_batch *b, int P, int H, const float *d_pred, const float *d_meas, const double *d_off,
+                           double *d_est, int *d_sel, double *d_dist, void *hip_stream) {
+  if (!b) return fail(GATO_EINVAL, "batch is NULL");
+  if (P < 1 || H < 1 || (long)P * H != b->M) return fail(GATO_EINVAL, "P and H must be >= 1 with P H = M");
+  if (!d_pred || !d_meas || !d_off || !d_est) return fail(GATO_EINVAL, "device buffers must not be NULL");
+  for (int p = 0; p < P; ++p)
+    for (int j = 0; j < H; ++j) {
+      const SolveDesc &d = b->desc[(size_t)p * H + j];
+      if (d.chain.model != GATO_MODEL_SERIAL_CHAIN)
+        return fail(GATO_EINVAL, "external forces apply to serial chains only");
+      if (d.n != b->desc[(size_t)p * H].n) return fail(GATO_EINVAL, "the solves of an instance must share the robot");
+    }
+  hipStream_t s = hip_stream ? (hipStream_t)hip_stream : b->stream;
+  const hipError_t e = gato::launch_select(b->d_desc, P, H, 2 * b->n_max, d_pred, d_meas, d_off, d_est, d_sel, d_dist, s);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch (hypothesis selection)");
+  b->fe_on_device = true;
   return GATO_OK;
 }
 
@@ -1190,6 +1236,8 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
   if (rc) return rc;
   if (n_iters < 1 || reps < 1) return fail(GATO_EINVAL, "n_iters and reps must be >= 1");
   hipStream_t s = b->stream;
+  rc = pull_device_forces(b);
+  if (rc != GATO_OK) return rc;
   hipError_t e = s ? hipStreamSynchronize(s) : hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(e, "synchronize");
   // Buckets of (n, N) and their members.
@@ -1275,6 +1323,78 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
   return rebuild_dispatch(b);
 }
 
+}  // extern "C"
+
+namespace {
+
+// The step of a mixed-shape batch with split long solves as an explicit graph:
+// a kernel node that clears the exchange words, then the split kernel as a
+// cooperative kernel node (its workgroups resident together). *out stays null
+// when the split does not apply (the launch does not fit the device, or the
+// runtime refuses the cooperative attribute); the caller then captures the
+// one-workgroup form.
+int build_split_graph(gato_batch *b, const gato::KArgs &a, hipGraph_t *out) {
+  *out = nullptr;
+  if (!use_mixed(b) || b->split_parts != gato::kSplitParts || b->n_split == 0 || b->task) return GATO_OK;
+  const void *fn = b->p.schur_fp64 ? gato::sqp_mixed_f64_split_fn() : gato::sqp_mixed_f32_split_fn();
+  for (int q = 0; q < 2; ++q) {
+    const int grid = b->grid_split_all[q];
+    if (grid <= b->M) continue;
+    hipError_t e = gato::cooperative_fits(fn, grid);
+    if (e == hipErrorCooperativeLaunchTooLarge) continue;
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    gato::KArgs as = a;
+    as.split = q == 0 ? 4 : 2;
+    as.order = b->d_order_split_all[q];
+    as.epoch = gato::kGraphEpoch;
+    as.xch = b->d_xch;
+    as.xspin = b->split_polls;
+    hipGraph_t g = nullptr;
+    e = hipGraphCreate(&g, 0);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
+    double *fp = reinterpret_cast<double *>(b->d_xch);
+    size_t fn_words = b->xwords;
+    double fv = 0.0;
+    void *fargs[] = {&fp, &fn_words, &fv};
+    hipKernelNodeParams fparams;
+    std::memset(&fparams, 0, sizeof(fparams));
+    fparams.func = const_cast<void *>(gato::fill_kernel_fn());
+    fparams.gridDim = dim3((unsigned)((fn_words + 255) / 256));
+    fparams.blockDim = dim3(256);
+    fparams.kernelParams = fargs;
+    hipGraphNode_t n_fill = nullptr, n_sqp = nullptr;
+    e = hipGraphAddKernelNode(&n_fill, g, nullptr, 0, &fparams);
+    void *kargs[] = {&as};
+    hipKernelNodeParams kparams;
+    std::memset(&kparams, 0, sizeof(kparams));
+    kparams.func = const_cast<void *>(fn);
+    kparams.gridDim = dim3(grid);
+    kparams.blockDim = dim3(gato::kBlock);
+    kparams.kernelParams = kargs;
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&n_sqp, g, &n_fill, 1, &kparams);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      return hip_fail(e, "hipGraphAddKernelNode");
+    }
+    hipLaunchAttributeValue coop;
+    std::memset(&coop, 0, sizeof(coop));
+    coop.cooperative = 1;
+    e = hipGraphKernelNodeSetAttribute(n_sqp, hipKernelNodeAttributeCooperative, &coop);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipGraphDestroy(g);
+      return GATO_OK;
+    }
+    *out = g;
+    return GATO_OK;
+  }
+  return GATO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gato_step_graph(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U, int n_iters,
                     gato_solve_stats *d_stats) {
   int rc = check_io(b, d_xs, d_goal, d_X, d_U);
@@ -1304,16 +1424,20 @@ int gato_step_graph(gato_batch *b, const float *d_xs, const float *d_goal, float
     a.stats = d_stats;
     a.stats_stride = n_iters;
     a.mode = gato::kModeSqp;
-    e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    rc = launch_groups(b, a, b->cap_stream, false);
     hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->cap_stream, &g);
-    if (rc != GATO_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
+    rc = build_split_graph(b, a, &g);
+    if (rc != GATO_OK) return rc;
+    if (!g) {
+      e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+      rc = launch_groups(b, a, b->cap_stream, false);
+      e = hipStreamEndCapture(b->cap_stream, &g);
+      if (rc != GATO_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     }
-    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {

@@ -43,7 +43,7 @@ enum KernelMode { kModeSqp = 0, kModeLq = 1, kModeKkt = 2 };
 
 // Split solves: parts per solve and 64-bit exchange words per solve.
 constexpr int kSplitParts = 4;
-constexpr int kXWordsPerSolve = kSplitParts * (4 * 72 + 1024);
+constexpr int kXWordsPerSolve = kSplitParts * (8 * 104 + 1024);
 
 struct KArgs {
   const SolveDesc *desc;

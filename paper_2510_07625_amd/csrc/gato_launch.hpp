@@ -38,10 +38,27 @@ hipError_t launch_plant(const PlantArgs &a, hipStream_t s);
 
 // Fills n doubles with v.
 hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s);
+// The fill kernel (double *p, size_t n, double v; 256 threads per workgroup),
+// for launches built as graph nodes.
+const void *fill_kernel_fn();
+// The split mixed-shape kernels (one KArgs argument, kBlock threads).
+const void *sqp_mixed_f64_split_fn();
+const void *sqp_mixed_f32_split_fn();
+
+// Exchange-tag epoch of split launches replayed from a graph. Eager launches
+// cycle through 1..kGraphEpoch-1, so words a replay leaves behind never carry
+// an eager launch's tag; every replay clears the words before its kernel.
+constexpr unsigned kGraphEpoch = 65535u;
 
 // Shifts the resident trajectories and multipliers of n slots one knot.
 hipError_t launch_shift(const SolveDesc *desc, int M, int n, const int *slots, int N_max, int nx_max, int nu_max,
                         float *X, float *U, double *lam, hipStream_t s);
+
+// Hypothesis selection of P instances with H solves each (slots p H + j):
+// distances of the predictions to the measured states, argmin, estimate update
+// and re-centred forces in the device descriptors.
+hipError_t launch_select(SolveDesc *desc, int P, int H, int nx_max, const float *pred, const float *meas,
+                         const double *off, double *est, int *sel, double *dist, hipStream_t s);
 
 // Launches the tip kinematics of every knot: X [M][N_max][nx_max] -> P [M][N_max][3].
 hipError_t launch_tips(const SolveDesc *desc, int M, int N_max, int nx_max, const float *X, float *P,

@@ -145,7 +145,75 @@ __global__ __launch_bounds__(256) void shift_kernel(const SolveDesc *desc, int M
   }
 }
 
+// Hypothesis selection (gato_select_hypotheses): one wavefront per instance p.
+// Lane l scores hypotheses j = l, l + 64, ... by the Euclidean distance between
+// their one-step predictions and the measured state (FP64 sums in index
+// order), a butterfly takes the smallest distance (the smaller j on ties), the
+// estimate moves to that hypothesis and the instance's hypotheses are
+// re-centred on it in the device descriptors.
+__global__ __launch_bounds__(64) void select_kernel(SolveDesc *desc, int P, int H, int nx_max, const float *pred,
+                                                    const float *meas, const double *off, double *est, int *sel,
+                                                    double *dist) {
+  __shared__ double e[3];
+  const int p = blockIdx.x;
+  if (p >= P) return;   // uniform across the workgroup
+  const int lane = threadIdx.x;
+  const size_t first = (size_t)p * H;
+  const int nx = 2 * desc[first].n;
+  const float *ms = meas + (size_t)p * nx_max;
+  double best = INFINITY;
+  int bj = H;   // none yet
+  for (int j = lane; j < H; j += 64) {
+    const float *q = pred + (first + j) * nx_max;
+    double s = 0.0;
+    for (int i = 0; i < nx; ++i) {
+      const double d = (double)q[i] - (double)ms[i];
+      s += d * d;
+    }
+    const double dj = sqrt(s);
+    if (dist) dist[first + j] = dj;
+    if (dj < best) {   // j ascends per lane, so ties keep the smaller j; NaN never wins
+      best = dj;
+      bj = j;
+    }
+  }
+  for (int w = 32; w >= 1; w >>= 1) {
+    const double ob = __shfl_xor(best, w);
+    const int oj = __shfl_xor(bj, w);
+    if (ob < best || (ob == best && oj < bj)) {
+      best = ob;
+      bj = oj;
+    }
+  }
+  const int j = bj < H ? bj : 0;   // every distance non-finite: keep the estimate
+  if (lane < 3) {
+    const double v = est[(size_t)p * 3 + lane] + off[(size_t)j * 3 + lane];
+    est[(size_t)p * 3 + lane] = v;
+    e[lane] = v;
+  }
+  if (lane == 0 && sel) sel[p] = j;
+  __syncthreads();
+  for (int jj = lane; jj < H; jj += 64) {
+    Chain &c = desc[first + jj].chain;
+    float f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      f[a] = (float)(e[a] + off[(size_t)jj * 3 + a]);
+      c.fe[a] = f[a];
+    }
+    c.has_fe = (f[0] != 0.f || f[1] != 0.f || f[2] != 0.f) ? 1 : 0;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_select(SolveDesc *desc, int P, int H, int nx_max, const float *pred, const float *meas,
+                         const double *off, double *est, int *sel, double *dist, hipStream_t s) {
+  hipLaunchKernelGGL(select_kernel, dim3(P), dim3(64), 0, s, desc, P, H, nx_max, pred, meas, off, est, sel, dist);
+  return hipGetLastError();
+}
+
+const void *fill_kernel_fn() { return reinterpret_cast<const void *>(&fill_kernel); }
 
 hipError_t launch_fill(double *p, size_t n, double v, hipStream_t s) {
   if (n == 0) return hipSuccess;

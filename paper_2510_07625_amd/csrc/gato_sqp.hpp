@@ -173,6 +173,58 @@ __device__ __forceinline__ double lane_val(double v, int l) {
                           __builtin_amdgcn_readlane(__double2loint(v), l));
 }
 
+// ---- Products with the lane group's own vector (16-lane groups, FP64). Lane m
+// of a 16-lane row holds entry m of its knot's vector; v_fmac_f64 with a
+// row_newbcast:m DPP source multiplies every lane's coefficient by that entry
+// straight from lane m's register, so the knot's own block-row products need no
+// LDS round trip. The terms are accumulated in the same order as the LDS
+// form's loops, so the sums are the same bit for bit. Each product is one asm
+// statement that starts with the two wait states a DPP read needs after a VALU
+// write of its source (x is only read inside it).
+#define GATO_NB1(M, C) "v_fmac_f64_dpp %0, %1, %[c" #M "] row_newbcast:" #M " row_mask:0xf bank_mask:0xf\n\t"
+#define GATO_NB2(M, A) "v_fmac_f64_dpp %" #A ", %2, %[c" #M "] row_newbcast:" #M " row_mask:0xf bank_mask:0xf\n\t"
+#define GATO_C12(c) [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]), [c4] "v"(c[4]), [c5] "v"(c[5]), \
+    [c6] "v"(c[6]), [c7] "v"(c[7]), [c8] "v"(c[8]), [c9] "v"(c[9]), [c10] "v"(c[10]), [c11] "v"(c[11])
+#define GATO_C14(c) GATO_C12(c), [c12] "v"(c[12]), [c13] "v"(c[13])
+
+// acc += sum_m c[m] x_m, m = 0..NX-1 in order (x_m: x at lane m of the row).
+template <int NX>
+__device__ __forceinline__ void row_dot1(double &acc, double x, const double *c) {
+  static_assert(NX == 12 || NX == 14, "16-lane groups hold 12 or 14 rows");
+  if constexpr (NX == 14) {
+    asm volatile("s_nop 1\n\t" GATO_NB1(0, c) GATO_NB1(1, c) GATO_NB1(2, c) GATO_NB1(3, c) GATO_NB1(4, c)
+                 GATO_NB1(5, c) GATO_NB1(6, c) GATO_NB1(7, c) GATO_NB1(8, c) GATO_NB1(9, c) GATO_NB1(10, c)
+                 GATO_NB1(11, c) GATO_NB1(12, c) GATO_NB1(13, c)
+                 : "+v"(acc) : "v"(x), GATO_C14(c));
+  } else {
+    asm volatile("s_nop 1\n\t" GATO_NB1(0, c) GATO_NB1(1, c) GATO_NB1(2, c) GATO_NB1(3, c) GATO_NB1(4, c)
+                 GATO_NB1(5, c) GATO_NB1(6, c) GATO_NB1(7, c) GATO_NB1(8, c) GATO_NB1(9, c) GATO_NB1(10, c)
+                 GATO_NB1(11, c)
+                 : "+v"(acc) : "v"(x), GATO_C12(c));
+  }
+}
+
+// d0 += sum over even m of c[m] x_m, d1 += sum over odd m (two independent chains).
+template <int NX>
+__device__ __forceinline__ void row_dot2(double &d0, double &d1, double x, const double *c) {
+  static_assert(NX == 12 || NX == 14, "16-lane groups hold 12 or 14 rows");
+  if constexpr (NX == 14) {
+    asm volatile("s_nop 1\n\t" GATO_NB2(0, 0) GATO_NB2(1, 1) GATO_NB2(2, 0) GATO_NB2(3, 1) GATO_NB2(4, 0)
+                 GATO_NB2(5, 1) GATO_NB2(6, 0) GATO_NB2(7, 1) GATO_NB2(8, 0) GATO_NB2(9, 1) GATO_NB2(10, 0)
+                 GATO_NB2(11, 1) GATO_NB2(12, 0) GATO_NB2(13, 1)
+                 : "+v"(d0), "+v"(d1) : "v"(x), GATO_C14(c));
+  } else {
+    asm volatile("s_nop 1\n\t" GATO_NB2(0, 0) GATO_NB2(1, 1) GATO_NB2(2, 0) GATO_NB2(3, 1) GATO_NB2(4, 0)
+                 GATO_NB2(5, 1) GATO_NB2(6, 0) GATO_NB2(7, 1) GATO_NB2(8, 0) GATO_NB2(9, 1) GATO_NB2(10, 0)
+                 GATO_NB2(11, 1)
+                 : "+v"(d0), "+v"(d1) : "v"(x), GATO_C12(c));
+  }
+}
+#undef GATO_NB1
+#undef GATO_NB2
+#undef GATO_C12
+#undef GATO_C14
+
 // Sum over the wavefront (all 64 lanes must be active).
 template <class R>
 __device__ __forceinline__ R wave_sum(R v) {
@@ -245,8 +297,9 @@ __device__ __forceinline__ void block_sum(double (*red)[3][kBlock / 64], int &bu
 // invalidation) is needed. Exchange e uses slot e mod 4 of the writer; a part
 // reuses a slot only after completing later exchanges that every reader of the
 // slot had to take part in. Every wait is bounded.
-constexpr int kXSlot = 72;                    // words: left row [0, 32), right row [32, 64), sums [64, 70)
-constexpr int kXSlots = 4;
+constexpr int kXSlot = 104;                   // words: left row [0, 32), right row [32, 64), sums [64, 104)
+constexpr int kXSlots = 8;
+constexpr int kXSums = (kXSlot - 64) / 2;     // values of one part's sums region
 constexpr int kXLam = 1024;                   // words: multipliers of 32 knots x 16 rows
 constexpr int kXPart = kXSlots * kXSlot + kXLam;
 constexpr int kXParts = 4;
@@ -291,6 +344,690 @@ __device__ __forceinline__ bool xget(unsigned long long *w, unsigned tag, bool d
   return xget2(w, nullptr, tag, dead, spin, v, unused);
 }
 
+// ---- Split long solves, part-local form. A solve of N > 64 knots (6-7 DoF)
+// runs on four workgroups (parts); part j owns knots kf = 32 j .. kl (at most
+// 32, possibly none) and runs the one-knot-per-lane-group layout of a short
+// solve over them, with one halo knot on each side in LDS:
+//   * LQ of its own knots and of the knot left of them (whose A, B, e, q, r the
+//     first own Schur row needs), the defects of its own knots (the knot right
+//     of them is the halo state);
+//   * Schur rows, diagonal-block inverses and PCG rows of its own knots, held
+//     in registers as in a short solve; at both barriers of a PCG iteration
+//     the halo rows of the S~ and preconditioner operands and the partial
+//     inner products travel through device memory (the exchange of the
+//     one-workgroup split form, same words and tags);
+//   * after the PCG: the multipliers of the halo knots, then the step of the
+//     first own knot (the left part's right halo), so that every part holds
+//     the step at its own knots and both halos;
+//   * the line search over its own knots, the per-candidate partial merits
+//     (and the parts' failure flags) summed over the parts in a fixed order,
+//     so every part takes the same step, status and damping.
+// Part 0 writes the statistics; every part writes its own knots' trajectory
+// and multipliers. The same method as the one-workgroup solve; sums are taken
+// per part first, so results differ from it at rounding level.
+template <int ND>
+struct PartSmem {
+  using Sh = Shape<ND>;
+  static constexpr int G = Sh::G, NX = Sh::NX, NU = Sh::NU, NL = Sh::NL;
+  static constexpr int KS = Sh::SLOTS;   // own knots at most
+  static constexpr int KH = KS + 2;      // with the halo knots: local index li = k - kf + 1
+  float X[KH][G];
+  float U[KH][8];
+  float dX[KH][G];
+  float dU[KH][8];
+  float e[KH][G];
+  float qg[KH][G];
+  float rg[KH][8];
+  float qdd[KH][8];
+  float Lf[KH][NL];
+  double pv[KH][G];        // operand of S~ (own rows and halos)
+  double sv[KH][G];        // Q_k^-1 times pv
+  double rv[KH][G];        // preconditioner: D_k^-1 times its operand
+  double gv[KH][G];        // Q_k^-1 times rv
+  double piv[KS][G];
+  double red[2][3][kBlock / 64];
+  double mp0[KH];
+  double Qi[G], Qni[G];
+  double mp[kMaxAlpha][KH];
+  double xmp[kMaxAlpha + 1];        // terminal and initial terms of this part, per candidate (+ current)
+  double psum[kMaxAlpha + 1];       // this part's partial merits
+  double msum[kXParts][kXSums];     // every part's partial merits and flags
+  double merit[kMaxAlpha + 1];
+  float alpha[kMaxAlpha];
+  float xs[G], xg[G], c0[G];
+  int bad[2];
+  int xfail, xpad[3];
+  float A[KH][NX * NX];
+  float B[KH][NX * NU];
+};
+
+template <int ND>
+__device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs &a, int sid, int part,
+                                                                     char *smem_raw) {
+  using Sh = Shape<ND>;
+  using Real = double;
+  constexpr int NX = Sh::NX, NU = Sh::NU, G = Sh::G, SLOTS = Sh::SLOTS;
+  static_assert(G == 16, "the part-local split serves 6-7 DoF");
+  using SM = PartSmem<ND>;
+  SM &sm = *reinterpret_cast<SM *>(smem_raw);
+  const SolveDesc &D = a.desc[sid];
+  const Chain &ch = D.chain;
+  const int tid = threadIdx.x;
+  const int lane0 = tid % G;
+  const int slot0 = tid / G;
+  const int N = D.N;
+  const float h = D.dt;
+  const int n_alpha = a.n_alpha;
+  const int nparts = kXParts;
+  const bool writer = part == 0;
+  const int kf = part * SLOTS;                               // own knots kf .. kl
+  const int nloc = max(0, min(SLOTS, N - kf));
+  const int kl = kf + nloc - 1;
+  const bool has_l = part > 0 && nloc > 0;                    // a neighbour on the left / the right
+  const bool has_r = nloc > 0 && kl + 1 < N;
+  const size_t xoff = (size_t)sid * a.N_max * a.nx_max;
+  const size_t uoff = (size_t)sid * (a.N_max - 1) * a.nu_max;
+  double *gL = a.lam + xoff;
+  const int sh = a.shift;
+  // Knot of a local index and back.
+  auto kof = [&](int li) { return kf - 1 + li; };
+
+  // ---- Stage the iterate (own knots and both halos) and the solve constants.
+  for (int t = tid; t < (nloc + 2) * G; t += kBlock) {
+    const int li = t / G, j = t % G, k = kof(li);
+    const bool in = k >= 0 && k < N && j < NX && nloc > 0;
+    sm.X[li][j] = in ? a.X[xoff + (size_t)min(k + sh, N - 1) * a.nx_max + j] : 0.f;
+  }
+  for (int t = tid; t < (nloc + 1) * 8; t += kBlock) {
+    const int li = t / 8, j = t % 8, k = kof(li);
+    const bool in = k >= 0 && k <= N - 2 && j < NU && nloc > 0;
+    sm.U[li][j] = in ? a.U[uoff + (size_t)min(k + sh, N - 2) * a.nu_max + j] : 0.f;
+  }
+  if (tid < G) {
+    const bool in = tid < NX;
+    sm.xs[tid] = in ? a.xs[(size_t)sid * a.nx_max + tid] : 0.f;
+    sm.xg[tid] = (in && tid < ND) ? a.goal[(size_t)sid * a.nu_max + tid] : 0.f;
+  }
+  if (tid == 0) {
+    sm.bad[0] = 0;
+    sm.bad[1] = 0;
+    sm.xfail = 0;
+    float al = 1.f;
+    for (int i = 0; i < n_alpha; ++i) {
+      sm.alpha[i] = al;
+      al = al / a.beta;
+    }
+  }
+  const bool own0 = slot0 < nloc && lane0 < NX;
+  Real lam = (a.warm && own0) ? (Real)gL[min(kf + slot0 + sh, N - 1) * a.nx_max + lane0] : (Real)0;
+  int redbuf = 0;
+  unsigned xe = 0;
+  double rho = a.rho[sid];
+  unsigned long long *xb = a.xch + D.xch_off;
+  const int xspin = a.xspin > 0 ? a.xspin : kXSpin;
+  auto xtag = [&](unsigned e) { return ((a.epoch & 0xffffu) << 16) | (e & 0xffffu); };
+  auto xslot = [&](int q, unsigned e) { return xb + (size_t)q * kXPart + (size_t)(e % kXSlots) * kXSlot; };
+  __syncthreads();
+
+  for (int it = 0; it < a.iters; ++it) {
+    int lane = lane0, slot = slot0;
+    asm volatile("" : "+v"(lane), "+v"(slot));
+    const int k = kf + slot;                 // this group's own knot
+    const int li = slot + 1;
+    const bool own = slot < nloc;
+    if (!a.warm && it > 0) lam = (Real)0;
+    if (tid < G) {
+      sm.Qi[tid] = tid < NX ? 1.0 / (D.Qd[tid] + rho) : 0.0;
+      sm.Qni[tid] = tid < NX ? 1.0 / (D.QNd[tid] + rho) : 0.0;
+    }
+    int &bad_flag = sm.bad[it & 1];
+    unsigned long long *clk = (a.clk && tid == 0 && writer) ? a.clk + ((size_t)sid * a.iters + it) * 8 : nullptr;
+    unsigned long long cyc0 = 0;
+    if (clk) {
+      clk[0] = wall_clock64();
+      cyc0 = clock64();
+    }
+    // ================= 1. LQ at knots kq0..kq1 (the own knots and the one left of them).
+    const int kq0 = max(kf - 1, 0), kq1 = min(kl, N - 2);
+    const int nq = nloc > 0 ? kq1 - kq0 + 1 : 0;
+    for (int t = slot; t < nq; t += SLOTS) {
+      const int kk = kq0 + t, lq = kk - kf + 1;
+      if (lane == 0) {
+        float q[ND], qd[ND], u[ND], qdd[ND], L[ND][ND];
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+          q[i] = sm.X[lq][i];
+          qd[i] = sm.X[lq][ND + i];
+          u[i] = sm.U[lq][i];
+        }
+        const bool ok = forward_dynamics<ND>(ch, q, qd, u, qdd, L);
+#pragma unroll
+        for (int i = 0; i < ND; ++i) sm.qdd[lq][i] = qdd[i];
+#pragma unroll
+        for (int i = 0; i < ND; ++i)
+#pragma unroll
+          for (int j = 0; j <= i; ++j) sm.Lf[lq][i * (i + 1) / 2 + j] = L[i][j];
+        float viol = 0.f, cost = 0.f;
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+          const float e0 = (q[i] + h * qd[i]) - sm.X[lq + 1][i];
+          const float e1 = (qd[i] + h * qdd[i]) - sm.X[lq + 1][ND + i];
+          sm.e[lq][i] = e0;
+          sm.e[lq][ND + i] = e1;
+          viol += fabsf(e0) + fabsf(e1);
+        }
+#pragma unroll
+        for (int i = 0; i < NX; ++i) {
+          const float d = sm.X[lq][i] - sm.xg[i];
+          cost += 0.5f * D.Wq[i] * d * d;
+        }
+#pragma unroll
+        for (int i = 0; i < NU; ++i) cost += 0.5f * D.Wr[i] * u[i] * u[i];
+        if (kk >= kf) sm.mp0[lq] = (double)cost + (double)a.mu * (double)viol;
+        if (!ok || !isfinite(viol) || !isfinite(cost)) bad_flag = 1;
+      }
+      wave_sync();
+      if (lane < NX) {
+        float q[ND], qd[ND], qdd[ND], col[ND];
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+          q[i] = sm.X[lq][i];
+          qd[i] = sm.X[lq][ND + i];
+          qdd[i] = sm.qdd[lq][i];
+        }
+        id_tangent<ND>(ch, q, qd, qdd, lane, col);
+        float L[ND][ND];
+#pragma unroll
+        for (int i = 0; i < ND; ++i)
+#pragma unroll
+          for (int j = 0; j < ND; ++j) L[i][j] = (j <= i) ? sm.Lf[lq][i * (i + 1) / 2 + j] : 0.f;
+        chol_solve<ND>(L, col);
+        float *Ak = sm.A[lq];
+#pragma unroll
+        for (int i = 0; i < ND; ++i) {
+          Ak[i * NX + lane] = (i == lane ? 1.f : 0.f) + (lane == ND + i ? h : 0.f);
+          Ak[(ND + i) * NX + lane] = h * col[i] + (lane == ND + i ? 1.f : 0.f);
+        }
+        if (lane < ND) {
+          float mi[ND];
+#pragma unroll
+          for (int i = 0; i < ND; ++i) mi[i] = (i == lane) ? 1.f : 0.f;
+          chol_solve<ND>(L, mi);
+          float *Bk = sm.B[lq];
+#pragma unroll
+          for (int i = 0; i < ND; ++i) {
+            Bk[i * NU + lane] = 0.f;
+            Bk[(ND + i) * NU + lane] = h * mi[i];
+          }
+        }
+      }
+    }
+    // Gradients at the knots kq0..kl, the initial residual, the terminal and
+    // initial merit terms (owners of knot N - 1 and knot 0).
+    const int lq0 = kq0 - kf + 1;
+    for (int t = tid; t < (nloc > 0 ? nloc + 1 - lq0 : 0) * G; t += kBlock) {
+      const int lg = lq0 + t / G, j = t % G, kk = kof(lg);
+      const float *W = (kk < N - 1) ? D.Wq : D.Wn;
+      sm.qg[lg][j] = j < NX ? W[j] * (sm.X[lg][j] - sm.xg[j]) : 0.f;
+      if (kk < N - 1 && j < 8) sm.rg[lg][j] = j < NU ? D.Wr[j] * sm.U[lg][j] : 0.f;
+    }
+    if (tid < G) sm.c0[tid] = (tid < NX && kf == 0) ? sm.xs[tid] - sm.X[1][tid] : 0.f;
+    if (tid == kBlock - 1) {
+      double x0 = 0.0;
+      if (nloc > 0 && kl == N - 1) {
+        float cost = 0.f;
+        for (int i = 0; i < NX; ++i) {
+          const float d = sm.X[nloc][i] - sm.xg[i];
+          cost += 0.5f * D.Wn[i] * d * d;
+        }
+        x0 += (double)cost;
+      }
+      if (kf == 0) {
+        float viol = 0.f;
+        for (int i = 0; i < NX; ++i) viol += fabsf(sm.xs[i] - sm.X[1][i]);
+        x0 += (double)a.mu * (double)viol;
+      }
+      sm.xmp[n_alpha] = x0;
+    }
+    __syncthreads();
+    if (tid == 0) sm.bad[(it + 1) & 1] = 0;
+    if (clk) clk[1] = wall_clock64();
+
+    // ================= 2. Schur rows and diagonal-block inverses of the own knots.
+    Real th[NX], Pdf[NX];
+    float Am[NX], Ac[NX];
+    Real gam = 0, qown = 0;
+#pragma unroll
+    for (int m = 0; m < NX; ++m) {
+      th[m] = 0;
+      Am[m] = 0.f;
+      Ac[m] = 0.f;
+      Pdf[m] = 0;
+    }
+    if (own && lane < NX) {
+      const double *Qik = (k < N - 1) ? sm.Qi : sm.Qni;
+      qown = (Real)Qik[lane];
+      if (k == 0) {
+#pragma unroll
+        for (int m = 0; m < NX; ++m) th[m] = (m == lane) ? (Real)sm.Qi[lane] : (Real)0;
+        gam = (Real)sm.c0[lane] + (Real)sm.Qi[lane] * (Real)sm.qg[li][lane];
+      } else {
+        const float *A = sm.A[li - 1];
+        const float *B = sm.B[li - 1];
+        Real ArQ[NX], BrR[NU];
+#pragma unroll
+        for (int m = 0; m < NX; ++m) {
+          const float arow = A[lane * NX + m];
+          Am[m] = arow;
+          ArQ[m] = (Real)arow * (Real)sm.Qi[m];
+        }
+#pragma unroll
+        for (int m = 0; m < NU; ++m) BrR[m] = (Real)B[lane * NU + m] * (Real)D.Ri[m];
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+          Real t = (c == lane) ? (Real)Qik[lane] : (Real)0;
+#pragma unroll
+          for (int m = 0; m < NX; ++m) t += ArQ[m] * (Real)A[c * NX + m];
+#pragma unroll
+          for (int m = 0; m < NU; ++m) t += BrR[m] * (Real)B[c * NU + m];
+          th[c] = t;
+        }
+        Real z = (Real)sm.e[li - 1][lane] + (Real)Qik[lane] * (Real)sm.qg[li][lane];
+#pragma unroll
+        for (int m = 0; m < NX; ++m) z -= ArQ[m] * (Real)sm.qg[li - 1][m];
+#pragma unroll
+        for (int m = 0; m < NU; ++m) z -= BrR[m] * (Real)sm.rg[li - 1][m];
+        gam = z;
+      }
+      if (k < N - 1) {
+        const float *A = sm.A[li];
+#pragma unroll
+        for (int m = 0; m < NX; ++m) Ac[m] = A[m * NX + lane];
+      }
+    }
+    if (own) {
+      if (k == 0) {
+        const Real d0 = lane < NX ? (Real)1 / (Real)sm.Qi[lane] : (Real)0;
+#pragma unroll
+        for (int m = 0; m < NX; ++m) Pdf[m] = (m == lane) ? d0 : (Real)0;
+      } else {
+        Real row[NX];
+#pragma unroll
+        for (int c = 0; c < NX; ++c) row[c] = th[c];
+#pragma unroll
+        for (int pv = 0; pv < NX; ++pv) {
+          if (lane == pv) {
+#pragma unroll
+            for (int c = 0; c < NX; ++c) sm.piv[slot][c] = row[c];
+          }
+          wave_sync();
+          Real prow[NX];
+#pragma unroll
+          for (int c = 0; c < NX; ++c) prow[c] = sm.piv[slot][c];
+          wave_sync();
+          const Real pinv = (Real)1 / prow[pv];
+          if (lane == pv) {
+#pragma unroll
+            for (int c = 0; c < NX; ++c) row[c] = (c == pv) ? pinv : row[c] * pinv;
+          } else {
+            const Real f = row[pv] * pinv;
+#pragma unroll
+            for (int c = 0; c < NX; ++c) row[c] = (c == pv) ? -f : row[c] - f * prow[c];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < NX; ++c) Pdf[c] = row[c];
+      }
+    }
+    __syncthreads();
+    if (clk) clk[2] = wall_clock64();
+    if (clk) clk[3] = wall_clock64();
+
+    // ================= 4. PCG (pipelined arrangement), halos and sums through the exchange.
+    const bool rv_ok = own && lane < NX;
+    auto put_row = [&](double left, double right) {   // this group's row to the neighbours (exchange xe)
+      if (lane < NX) {
+        if (has_l && slot == 0) xput(xslot(part, xe) + 2 * lane, xtag(xe), left);
+        if (has_r && slot == nloc - 1) xput(xslot(part, xe) + 32 + 2 * lane, xtag(xe), right);
+      }
+    };
+    // Halo rows of exchange e into vl[0] (left neighbour's last knot) and
+    // vr[nloc + 1] (right neighbour's first knot), and, with sums, the three
+    // partials of every part summed in part order.
+    auto get_rows_sums = [&](unsigned e, bool sums, double (*vl)[G], double (*vr)[G], double &s0, double &s1,
+                             double &s2) {
+      const bool dead = sm.xfail != 0;
+      const int l = tid & 63;
+      const bool hl = has_l && slot == 0 && lane < NX;
+      const bool hr = has_r && slot == nloc - 1 && lane < NX;
+      unsigned long long *wh = hl ? xslot(part - 1, e) + 32 + 2 * lane : (hr ? xslot(part + 1, e) + 2 * lane : nullptr);
+      unsigned long long *wsum = (sums && l < 3 * nparts) ? xslot(l / 3, e) + 64 + 2 * (l % 3) : nullptr;
+      double vh = 0.0, v = 0.0;
+      if (wh || wsum) {
+        bool ok;
+        if (wh && wsum) ok = xget2(wh, wsum, xtag(e), dead, xspin, vh, v);
+        else if (wh) ok = xget(wh, xtag(e), dead, xspin, vh);
+        else ok = xget(wsum, xtag(e), dead, xspin, v);
+        if (!ok) sm.xfail = 1;
+      }
+      if (hl) vl[0][lane] = vh;
+      if (hr) vr[nloc + 1][lane] = vh;
+      wave_sync();
+      if (sums) {
+        s0 = (lane_val(v, 0) + lane_val(v, 3)) + (lane_val(v, 6) + lane_val(v, 9));
+        s1 = (lane_val(v, 1) + lane_val(v, 4)) + (lane_val(v, 7) + lane_val(v, 10));
+        s2 = (lane_val(v, 2) + lane_val(v, 5)) + (lane_val(v, 8) + lane_val(v, 11));
+      }
+    };
+    auto halo = [&](double (*vl)[G], double (*vr)[G]) {
+      double d0, d1, d2;
+      get_rows_sums(xe, false, vl, vr, d0, d1, d2);
+      ++xe;
+    };
+    auto share_S = [&](Real v) {
+      if (own) {
+        sm.pv[li][lane] = lane < NX ? v : (Real)0;
+        sm.sv[li][lane] = lane < NX ? qown * v : (Real)0;
+        put_row(v, qown * v);
+      }
+    };
+    auto apply_S = [&](Real v) -> Real {
+      Real d0 = 0, d1 = 0, l0 = 0, l1 = 0, u0 = 0, u1 = 0;
+      row_dot2<NX>(d0, d1, v, th);
+      if (k > 0) {
+#pragma unroll
+        for (int m = 0; m < NX; m += 2) {
+          l0 += (Real)Am[m] * sm.sv[li - 1][m];
+          l1 += (Real)Am[m + 1] * sm.sv[li - 1][m + 1];
+        }
+      }
+      if (k < N - 1) {
+#pragma unroll
+        for (int m = 0; m < NX; m += 2) {
+          u0 += (Real)Ac[m] * sm.pv[li + 1][m];
+          u1 += (Real)Ac[m + 1] * sm.pv[li + 1][m + 1];
+        }
+      }
+      return ((d0 + d1) - (l0 + l1)) - qown * (u0 + u1);
+    };
+    auto dinv = [&](Real x) -> Real {
+      Real acc = 0;
+      row_dot1<NX>(acc, x, Pdf);
+      return acc;
+    };
+    auto prepare_P = [&](Real v) {
+      if (own) {
+        const Real z = dinv(v);
+        sm.rv[li][lane] = lane < NX ? z : (Real)0;
+        sm.gv[li][lane] = lane < NX ? qown * z : (Real)0;
+        put_row(z, qown * z);
+      }
+    };
+    auto finish_P = [&](Real v) -> Real {
+      Real oz = 0;
+      if (k > 0) {
+#pragma unroll
+        for (int m = 0; m < NX; ++m) oz -= (Real)Am[m] * sm.gv[li - 1][m];
+      }
+      if (k < N - 1) {
+        Real t = 0;
+#pragma unroll
+        for (int m = 0; m < NX; ++m) t += (Real)Ac[m] * sm.rv[li + 1][m];
+        oz -= qown * t;
+      }
+      return dinv(v - oz);
+    };
+
+    Real r, u, w, vm = 0, vn = 0, vz = 0, vq = 0, vs = 0, vp = 0;
+    share_S(lam);
+    __syncthreads();
+    halo(sm.pv, sm.sv);
+    r = rv_ok ? gam - apply_S(lam) : (Real)0;
+    prepare_P(r);
+    __syncthreads();
+    halo(sm.rv, sm.gv);
+    u = rv_ok ? finish_P(r) : (Real)0;
+    __syncthreads();
+    prepare_P(gam);
+    __syncthreads();
+    halo(sm.rv, sm.gv);
+    const Real Pgam = rv_ok ? finish_P(gam) : (Real)0;
+    Real eta_ref = gam * Pgam;
+    const int max_it = a.pcg_max_iter > 0 ? a.pcg_max_iter : N * NX;
+    Real gma = 0, stop = 0;
+    int its = 0;
+    share_S(u);
+    __syncthreads();
+    halo(sm.pv, sm.sv);
+    w = rv_ok ? apply_S(u) : (Real)0;
+    eta_ref = wave_sum(eta_ref);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if ((tid & 63) == 0) sm.red[redbuf][2][wave] = eta_ref;
+    Real rg = 0, cga = 0;
+    for (;;) {
+#pragma unroll
+      for (int m = 0; m < NX; ++m) {
+        asm volatile("" : "+v"(Am[m]), "+v"(Ac[m]));
+        asm volatile("" : "+v"(Pdf[m]));
+      }
+      Real pr = r * u, pwu = w * u;
+      wave_sum2(pr, pwu);
+      if ((tid & 63) == 0) {
+        sm.red[redbuf][0][wave] = pr;
+        sm.red[redbuf][1][wave] = pwu;
+      }
+      prepare_P(w);
+      __syncthreads();
+      gma = pair_tree<kBlock / 64>(sm.red[redbuf][0]);
+      Real dlt = pair_tree<kBlock / 64>(sm.red[redbuf][1]);
+      {
+        const double e0 = (its == 0) ? pair_tree<kBlock / 64>(sm.red[redbuf][2]) : 0.0;
+        if (tid < 3) xput(xslot(part, xe) + 64 + 2 * tid, xtag(xe), tid == 0 ? gma : (tid == 1 ? dlt : e0));
+        double g_, d_, e_;
+        get_rows_sums(xe, true, sm.rv, sm.gv, g_, d_, e_);
+        ++xe;
+        gma = g_;
+        dlt = d_;
+        if (its == 0) stop = (Real)a.pcg_tol * (Real)a.pcg_tol * (Real)e_;
+      }
+      redbuf ^= 1;
+      if (!(gma > stop) || its >= max_it) break;
+      vm = rv_ok ? finish_P(w) : (Real)0;
+      share_S(vm);
+      const Real beta = gma * rg;
+      const Real alpha = gma / (dlt - gma * gma * cga);
+      __syncthreads();
+      halo(sm.pv, sm.sv);
+      vn = rv_ok ? apply_S(vm) : (Real)0;
+      vz = vn + beta * vz;
+      vq = vm + beta * vq;
+      vs = w + beta * vs;
+      vp = u + beta * vp;
+      lam += alpha * vp;
+      r -= alpha * vs;
+      u -= alpha * vq;
+      w -= alpha * vz;
+      cga = (Real)1 / (gma * alpha);
+      rg = alpha * cga;
+      ++its;
+    }
+    unsigned status = (gma > stop) ? GATO_ST_PCG_MAXITER : 0u;
+    if (clk) clk[4] = wall_clock64();
+
+    // ================= 5. Step dZ = -G^-1 (g - C^T lambda) at the own knots and the halos.
+    // Multipliers of the halo knots first (exchange), then the own steps and the
+    // left halo's step (this part holds its LQ data), then the right halo's step
+    // from the right part (its first own knot).
+    if (own) {
+      sm.pv[li][lane] = lane < NX ? lam : (Real)0;
+      put_row(lam, lam);
+    }
+    __syncthreads();
+    halo(sm.pv, sm.pv);
+    auto step_at = [&](int lg, int kk, Real lam_own, Real qk) {   // step of knot kk (local lg), row `lane`
+      Real sx = (Real)sm.qg[lg][lane] - lam_own;
+      if (kk < N - 1) {
+        const float *A = sm.A[lg];
+#pragma unroll
+        for (int m = 0; m < NX; ++m) sx += (Real)A[m * NX + lane] * sm.pv[lg + 1][m];
+      }
+      const float dx = (float)(-qk * sx);
+      sm.dX[lg][lane] = dx;
+      if (!isfinite(dx)) bad_flag = 1;
+      if (lane < NU && kk < N - 1) {
+        const float *B = sm.B[lg];
+        Real su = (Real)sm.rg[lg][lane];
+#pragma unroll
+        for (int m = 0; m < NX; ++m) su += (Real)B[m * NU + lane] * sm.pv[lg + 1][m];
+        const float du = (float)(-(Real)D.Ri[lane] * su);
+        sm.dU[lg][lane] = du;
+        if (!isfinite(du)) bad_flag = 1;
+      }
+    };
+    if (own && lane < NX) step_at(li, k, lam, qown);
+    if (has_l && slot == 0 && lane < NX) step_at(0, kf - 1, sm.pv[0][lane], (Real)sm.Qi[lane]);
+    __syncthreads();
+    if (own && slot == 0) put_row((double)sm.dX[1][lane], 0.0);
+    {
+      // (Only the rows towards the left travel; a part reads its right
+      // neighbour's first step into dX[nloc + 1].)
+      const bool dead = sm.xfail != 0;
+      if (has_r && slot == nloc - 1 && lane < NX) {
+        double v;
+        if (!xget(xslot(part + 1, xe) + 2 * lane, xtag(xe), dead, xspin, v)) sm.xfail = 1;
+        sm.dX[nloc + 1][lane] = (float)v;
+      }
+      ++xe;
+    }
+    __syncthreads();
+    if (clk) clk[5] = wall_clock64();
+
+    // ================= 6. Line search over the own knots; partial merits summed over the parts.
+    const int nst = (nloc > 0) ? min(kl, N - 2) - kf + 1 : 0;   // own knots with a control
+    const int ntask = n_alpha * max(nst, 0);
+    for (int t = tid; t < ntask; t += kBlock) {
+      const int i = t / nst, lg = 1 + (t - i * nst);
+      const float al = sm.alpha[i];
+      float q[ND], qd[ND], uu[ND], qdd[ND], L[ND][ND], xn[NX];
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        q[j] = sm.X[lg][j] + al * sm.dX[lg][j];
+        qd[j] = sm.X[lg][ND + j] + al * sm.dX[lg][ND + j];
+        uu[j] = sm.U[lg][j] + al * sm.dU[lg][j];
+      }
+#pragma unroll
+      for (int j = 0; j < NX; ++j) xn[j] = sm.X[lg + 1][j] + al * sm.dX[lg + 1][j];
+      forward_dynamics<ND>(ch, q, qd, uu, qdd, L);
+      float viol = 0.f, cost = 0.f;
+#pragma unroll
+      for (int j = 0; j < ND; ++j) {
+        viol += fabsf((q[j] + h * qd[j]) - xn[j]) + fabsf((qd[j] + h * qdd[j]) - xn[ND + j]);
+        const float d0 = q[j] - sm.xg[j], d1 = qd[j] - sm.xg[ND + j];
+        cost += 0.5f * D.Wq[j] * d0 * d0 + 0.5f * D.Wq[ND + j] * d1 * d1 + 0.5f * D.Wr[j] * uu[j] * uu[j];
+      }
+      sm.mp[i][lg] = (double)cost + (double)a.mu * (double)viol;
+    }
+    for (int i = tid; i < n_alpha; i += kBlock) {
+      const float al = sm.alpha[i];
+      double x0 = 0.0;
+      if (nloc > 0 && kl == N - 1) {
+        float cost = 0.f;
+        for (int j = 0; j < NX; ++j) {
+          const float d = (sm.X[nloc][j] + al * sm.dX[nloc][j]) - sm.xg[j];
+          cost += 0.5f * D.Wn[j] * d * d;
+        }
+        x0 += (double)cost;
+      }
+      if (kf == 0) {
+        float viol = 0.f;
+        for (int j = 0; j < NX; ++j) viol += fabsf(sm.xs[j] - (sm.X[1][j] + al * sm.dX[1][j]));
+        x0 += (double)a.mu * (double)viol;
+      }
+      sm.xmp[i] = x0;
+    }
+    __syncthreads();
+    if (tid <= n_alpha) {
+      double sum = 0.0;
+      for (int lg = 1; lg <= max(nst, 0); ++lg) sum += (tid == n_alpha) ? sm.mp0[lg] : sm.mp[tid][lg];
+      sm.psum[tid] = sum + sm.xmp[tid];
+    }
+    __syncthreads();
+    {
+      // Partial merits (n_alpha + 1), this part's non-finite flag and its
+      // exchange failure flag to every part; summed in part order.
+      const int nv = n_alpha + 3;
+      if (tid < nv) {
+        const double v = tid <= n_alpha ? sm.psum[tid] : (tid == n_alpha + 1 ? (double)bad_flag : (double)sm.xfail);
+        xput(xslot(part, xe) + 64 + 2 * tid, xtag(xe), v);
+      }
+      const bool dead = sm.xfail != 0;
+      if (tid < nv * nparts) {
+        const int q = tid / nv, v = tid % nv;
+        double x;
+        if (!xget(xslot(q, xe) + 64 + 2 * v, xtag(xe), dead, xspin, x)) sm.xfail = 1;
+        sm.msum[q][v] = x;
+      }
+      ++xe;
+      __syncthreads();
+      if (tid <= n_alpha) {
+        double m = 0.0;
+        for (int q = 0; q < nparts; ++q) m += sm.msum[q][tid];
+        sm.merit[tid] = m;
+      }
+      __syncthreads();
+    }
+    int best = -1;
+    for (int i = 0; i < n_alpha; ++i) {
+      const double m = sm.merit[i];
+      if (isfinite(m) && (best < 0 || m < sm.merit[best])) best = i;
+    }
+    bool any_bad = false, any_xfail = sm.xfail != 0;
+    for (int q = 0; q < nparts; ++q) {
+      any_bad = any_bad || sm.msum[q][n_alpha + 1] != 0.0;
+      any_xfail = any_xfail || sm.msum[q][n_alpha + 2] != 0.0;
+    }
+    const bool bad = any_bad || best < 0;
+    if (bad) status |= GATO_ST_NONFINITE;
+    else if (!(sm.merit[best] < sm.merit[n_alpha])) status |= GATO_ST_NO_DESCENT;
+    if (any_xfail) status |= GATO_ST_EXCHANGE;
+    const double rho_used = rho;
+    if (a.rho_adapt) rho = (status & (GATO_ST_NONFINITE | GATO_ST_NO_DESCENT)) ? fmin(2.0 * rho, 1e8) : rho / 3.0;
+    const float al = bad ? 0.f : sm.alpha[best];
+    if (!bad) {
+      for (int t = tid; t < (nloc + 2) * G; t += kBlock) {
+        const int lg = t / G, j = t % G, kk = kof(lg);
+        if (kk < 0 || kk >= N || nloc == 0) continue;
+        sm.X[lg][j] += al * sm.dX[lg][j];
+        if (kk < N - 1 && lg <= nloc && j < 8) sm.U[lg][j] += al * sm.dU[lg][j];
+      }
+    }
+    if (tid == 0 && a.stats && writer) {
+      gato_solve_stats st;
+      st.merit0 = (float)sm.merit[n_alpha];
+      st.merit = bad ? (float)sm.merit[n_alpha] : (float)sm.merit[best];
+      st.alpha = al;
+      st.pcg_iters = its;
+      st.status = status;
+      st.rho = (float)rho_used;
+      a.stats[(size_t)sid * a.stats_stride + it] = st;
+    }
+    __syncthreads();
+    if (clk) {
+      clk[6] = wall_clock64();
+      clk[7] = clock64() - cyc0;
+    }
+  }
+
+  // ---- Write back the own knots' iterate and multipliers, and the damping.
+  if (writer && a.rho_adapt && tid == 0) a.rho[sid] = rho;
+  for (int t = tid; t < nloc * G; t += kBlock) {
+    const int lg = 1 + t / G, j = t % G, kk = kof(lg);
+    if (j < NX) a.X[xoff + (size_t)kk * a.nx_max + j] = sm.X[lg][j];
+    if (kk < N - 1 && j < NU) a.U[uoff + (size_t)kk * a.nu_max + j] = sm.U[lg][j];
+  }
+  if (own0) gL[(kf + slot0) * a.nx_max + lane0] = (double)lam;
+}
+
 template <int ND, int KPT, class Real, bool TS = false, bool SPLIT = false>
 __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, int sid, int part, char *smem_raw) {
   using Sh = Shape<ND>;
@@ -320,6 +1057,15 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   const int nparts = a.split == 2 ? 2 : kXParts;
   const int psh = nparts == 2 ? 1 : 0;
   const bool split = kSplitOk && a.split && a.mode == kModeSqp && D.xch_off >= 0 && part >= 0 && part < nparts;
+  // Four parts of a long FP64 solve: the part-local form (one knot per lane
+  // group over the part's own knots).
+  if constexpr (kSplitOk && sizeof(Real) == 8) {
+    static_assert(sizeof(PartSmem<ND>) <= smem_bytes<ND, KPT, Real, TS>(), "LDS of a part");
+    if (split && a.split == 4 && !a.by_block) {
+      sqp_solve_part<ND>(a, sid, part, smem_raw);
+      return;
+    }
+  }
   const bool writer = !split || part == 0;
   char *ws = a.ws + D.ws_off + (split ? (int64_t)part * D.ws_part : 0);
   const size_t xoff = (size_t)sid * a.N_max * a.nx_max;
@@ -1082,14 +1828,25 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // chains are short and independent; with more knots the extra accumulators
     // would cost registers (spills), so the odd columns fold into the even sums.
     constexpr bool kSplit = (KPT == 1);
-    auto apply_S = [&](int p) -> Real {
+    // The knot's own block-row products (the diagonal block of S~ and the
+    // D^-1 products of the preconditioner) by DPP row broadcasts from the
+    // registers (16-lane groups, FP64); the neighbours' blocks still read the
+    // neighbours' published vectors from LDS.
+    constexpr bool kDpp = (G == 16) && (sizeof(Real) == 8);
+    // own: this lane's entry of the vector the product multiplies (the value
+    // share_S published in pv).
+    auto apply_S = [&](int p, Real own) -> Real {
       const int k = slot + p * SLOTS;
       if constexpr (kSplit) {
         Real d0 = 0, d1 = 0, l0 = 0, l1 = 0, u0 = 0, u1 = 0;
+        if constexpr (kDpp) {
+          row_dot2<NX>(d0, d1, own, th[p]);
+        } else {
 #pragma unroll
-        for (int m = 0; m < NX; m += 2) {
-          d0 += th[p][m] * sm.pv[k][m];
-          d1 += th[p][m + 1] * sm.pv[k][m + 1];
+          for (int m = 0; m < NX; m += 2) {
+            d0 += th[p][m] * sm.pv[k][m];
+            d1 += th[p][m + 1] * sm.pv[k][m + 1];
+          }
         }
         if (k > 0) {
 #pragma unroll
@@ -1108,10 +1865,14 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         return ((d0 + d1) - (l0 + l1)) - qown[p] * (u0 + u1);
       } else {
         Real acc = 0;
+        if constexpr (kDpp && !kThGlobal) {
+          row_dot1<NX>(acc, own, th[p]);
+        } else {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) {
-          if constexpr (kThGlobal) acc += Tblk(k)[lane * NX + m] * sm.pv[k][m];
-          else acc += th[p][m] * sm.pv[k][m];
+          for (int m = 0; m < NX; ++m) {
+            if constexpr (kThGlobal) acc += Tblk(k)[lane * NX + m] * sm.pv[k][m];
+            else acc += th[p][m] * sm.pv[k][m];
+          }
         }
         if (k > 0) {
 #pragma unroll
@@ -1161,12 +1922,19 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     //   finish:  t_k = v_k - (O z)_k, then (P v)_k = D_k^-1 t_k.
     auto group_dinv = [&](int p, Real x) -> Real {   // row `lane` of D_k^-1 times the group's x
       const int k = slot + p * SLOTS;
-      sm.tv[k][lane] = (lane < NX) ? x : (Real)0;
-      wave_sync();
       Real acc = 0;
+      if constexpr (kDpp) {
+        double c[NX];
 #pragma unroll
-      for (int m = 0; m < NX; ++m) acc += (Real)Pdf[p][m] * sm.tv[k][m];
-      wave_sync();
+        for (int m = 0; m < NX; ++m) c[m] = (double)Pdf[p][m];
+        row_dot1<NX>(acc, x, c);
+      } else {
+        sm.tv[k][lane] = (lane < NX) ? x : (Real)0;
+        wave_sync();
+#pragma unroll
+        for (int m = 0; m < NX; ++m) acc += (Real)Pdf[p][m] * sm.tv[k][m];
+        wave_sync();
+      }
       return acc;
     };
     auto prepare_P = [&](const Real *vals) {
@@ -1204,7 +1972,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     __syncthreads();
     if (xon) xhalo(sm.pv, sm.sv);
 #pragma unroll
-    for (int p = 0; p < KPT; ++p) r[p] = row_valid(p) ? gam[p] - apply_S(p) : (Real)0;
+    for (int p = 0; p < KPT; ++p) r[p] = row_valid(p) ? gam[p] - apply_S(p, lam[p]) : (Real)0;
     Real Pgam[KPT];   // P gamma~, for the reference norm
     if constexpr (kFactP) {
       prepare_P(r);
@@ -1267,7 +2035,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           Acc pw[1] = {0};
 #pragma unroll
           for (int p = 0; p < KPT; ++p) {
-            w[p] = row_valid(p) ? apply_S(p) : (Real)0;
+            w[p] = row_valid(p) ? apply_S(p, vp[p]) : (Real)0;
             pw[0] += (Acc)vp[p] * (Acc)w[p];
           }
           block_sum<1>(sm.red, redbuf, pw);
@@ -1318,7 +2086,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       if (xon) xhalo(sm.pv, sm.sv);
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
-        w[p] = row_valid(p) ? apply_S(p) : (Real)0;
+        w[p] = row_valid(p) ? apply_S(p, u[p]) : (Real)0;
         vz[p] = vq[p] = vs[p] = vp[p] = 0;
       }
       eta_ref = wave_sum(eta_ref);
@@ -1399,7 +2167,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         if (xon) xhalo(sm.pv, sm.sv);
 #pragma unroll
         for (int p = 0; p < KPT; ++p) {
-          vn[p] = row_valid(p) ? apply_S(p) : (Real)0;
+          vn[p] = row_valid(p) ? apply_S(p, vm[p]) : (Real)0;
           vz[p] = vn[p] + beta * vz[p];
           vq[p] = vm[p] + beta * vq[p];
           vs[p] = w[p] + beta * vs[p];

@@ -22,4 +22,9 @@ hipError_t launch_sqp_mixed_f64_split(int grid, const KArgs &a, hipStream_t s) {
                                     dim3(kBlock), args, 0, s);
 }
 
+// The split mixed-shape kernel itself, for launches built as graph nodes.
+const void *sqp_mixed_f64_split_fn() {
+  return reinterpret_cast<const void *>(&sqp_mixed_kernel<double, false, true>);
+}
+
 }  // namespace gato

@@ -17,8 +17,9 @@ in the assumed external force on the tip of the last link. Every control tick:
    spread over (0, 1] (hypothesis 0: the estimate itself), so that both the
    direction and the magnitude are explored around it.
 
-Device work is stream-ordered; the selection reads P H prediction errors back
-to the host each tick.
+Steps 3-4 run in the library (gato_select_hypotheses): the estimates and the
+hypotheses' forces stay on the device, and a tick is enqueued without any host
+synchronisation.
 """
 from __future__ import annotations
 
@@ -54,43 +55,46 @@ def run(batch, P: int, H: int, x0, goal, ticks: int, true_force, sigma: float = 
     """batch holds P H solves (slot p H + j); x0 [P, nx_max] and goal [P, nu_max]
     are device tensors; true_force(tick) returns the plants' true forces [P, 3]
     (numpy); f0 [P, 3] is the initial estimate (default zero)."""
-    import time
-
     import torch
     M = P * H
     assert batch.M == M
     dev = x0.device
     nx, nu, N = batch.nx_max, batch.nu_max, batch.N_max
-    off = offsets(H, seed) * sigma                                   # [H, 3]
-    est = np.zeros((P, 3)) if f0 is None else np.array(f0, np.float64).reshape(P, 3)
+    off_h = offsets(H, seed) * sigma                                 # [H, 3]
+    est0 = np.zeros((P, 3)) if f0 is None else np.array(f0, np.float64).reshape(P, 3)
+    batch.set_external_force((est0[:, None, :] + off_h[None, :, :]).reshape(M, 3))
+    off = torch.from_numpy(off_h).to(dev)
+    est = torch.from_numpy(est0.copy()).to(dev)
     slots = torch.arange(M, dtype=torch.int32, device=dev)
     inst_slots = (torch.arange(P, dtype=torch.int32, device=dev) * H).contiguous()
     Xo = torch.empty((M, N, nx), dtype=torch.float32, device=dev)
     Uo = torch.empty((M, N - 1, nu), dtype=torch.float32, device=dev)
     goal_m = goal.repeat_interleave(H, dim=0).contiguous()
-    x = x0.clone()
-    states, ests, sel, ctrl, tick_ms = [x.cpu().numpy()], [est.copy()], [], [], []
+    states = torch.empty((ticks + 1, P, nx), dtype=torch.float32, device=dev)
+    ests = torch.empty((ticks + 1, P, 3), dtype=torch.float64, device=dev)
+    sel = torch.empty((ticks, P), dtype=torch.int32, device=dev)
+    ctrl = torch.empty((ticks, P, nu), dtype=torch.float32, device=dev)
+    states[0].copy_(x0)
+    ests[0].copy_(est)
+    f_true = [torch.from_numpy(np.asarray(true_force(t), np.float32).reshape(P, 3)).to(dev) for t in range(ticks)]
+    evs = []
     for t in range(ticks):
-        t0 = time.perf_counter()
-        hyp = (est[:, None, :] + off[None, :, :]).reshape(M, 3)
-        batch.set_external_force(hyp)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        x = states[t]
         xs_m = x.repeat_interleave(H, dim=0).contiguous()
         batch.serve_step(slots, xs_m, goal_m, n_iters=n_iters, shift=1, Xout=Xo, Uout=Uo)
-        u = Uo[::H, 0].contiguous()                                    # hypothesis 0 of every instance
-        f_true = torch.from_numpy(np.asarray(true_force(t), np.float32).reshape(P, 3)).to(dev)
-        x_next = batch.plant_step(x, u, h=h, substeps=substeps, slots=inst_slots, fext=f_true)
-        pred = batch.plant_step(xs_m, u.repeat_interleave(H, dim=0).contiguous(), h=h, substeps=substeps,
+        ctrl[t].copy_(Uo[::H, 0])                                      # hypothesis 0 of every instance
+        batch.plant_step(x, ctrl[t], h=h, substeps=substeps, slots=inst_slots, fext=f_true[t], xn=states[t + 1])
+        pred = batch.plant_step(xs_m, ctrl[t].repeat_interleave(H, dim=0).contiguous(), h=h, substeps=substeps,
                                 slots=slots)                           # each solve's own hypothesis
-        err = (pred.view(P, H, nx) - x_next[:, None, :]).norm(dim=2)   # [P, H]
-        j = err.argmin(dim=1).cpu().numpy()
-        est = hyp.reshape(P, H, 3)[np.arange(P), j]
-        x = x_next
-        states.append(x.cpu().numpy())
-        ctrl.append(u.cpu().numpy())
-        ests.append(est.copy())
-        sel.append(j)
-        tick_ms.append((time.perf_counter() - t0) * 1e3)
-    return HypothesisRun(np.stack(states), np.stack(ests), np.stack(sel), np.stack(ctrl), tick_ms)
+        batch.select_hypotheses(P, H, pred, states[t + 1], off, est, sel=sel[t])
+        ests[t + 1].copy_(est)
+        e1.record()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    tick_ms = [a.elapsed_time(b) for a, b in evs]
+    return HypothesisRun(states.cpu().numpy(), ests.cpu().numpy(), sel.cpu().numpy(), ctrl.cpu().numpy(), tick_ms)
 
 
 def realized_cost(run: HypothesisRun, solves_per_instance, dt_weighting: bool = False) -> np.ndarray:
