@@ -52,7 +52,8 @@ class _Params(C.Structure):
 class _IterLog(C.Structure):
     _fields_ = [("merit0", C.c_double), ("merit", C.c_double), ("alpha", C.c_double), ("J", C.c_double),
                 ("c1", C.c_double), ("kkt_res", C.c_double), ("pcg_iters", C.c_int), ("status", C.c_int),
-                ("argmin", C.c_int), ("pad", C.c_int), ("rho", C.c_double), ("merits", C.c_double * MAX_ALPHA)]
+                ("argmin", C.c_int), ("pad", C.c_int), ("rho", C.c_double), ("merits", C.c_double * MAX_ALPHA),
+                ("pcg_stop", C.c_double), ("pcg_stop_prev", C.c_double)]
 
 
 @dataclass
@@ -104,7 +105,7 @@ def lib():
         L.orc_tip.argtypes = [rp, dp, dp, dp]
         L.orc_lq_hessian.argtypes = [rp, pp, C.c_double, dp, dp, dp, dp, dp]
         L.orc_sqp.argtypes = [rp, pp, C.POINTER(_Params), dp, dp, dp, dp, dp, C.POINTER(_IterLog), dp,
-                              C.POINTER(C.c_int)]
+                              C.POINTER(C.c_int), C.POINTER(C.c_int)]
         _lib = L
     return _lib
 
@@ -384,8 +385,13 @@ class SqpResult:
 
 
 def sqp(s, params: Params | None = None, X=None, U=None, lam=None, alpha_replay=None,
-        descent_replay=None) -> SqpResult:
-    """The SQP loop for one solve (Sec. II-A, Algorithm 1)."""
+        descent_replay=None, pcg_replay=None) -> SqpResult:
+    """The SQP loop for one solve (Sec. II-A, Algorithm 1). alpha_replay /
+    descent_replay / pcg_replay prescribe, per SQP iteration, the accepted
+    step, the descent decision of the rho adaptation and (Schur + PCG mode)
+    the PCG iteration count; each log entry keeps the oracle's own view of the
+    decision (merits, pcg_stop and pcg_stop_prev: the stopping value over its
+    threshold after the last PCG iteration and after the one before)."""
     p = params or Params()
     c = _Ctx(s)
     nx, N = 2 * s.n, s.N
@@ -402,12 +408,15 @@ def sqp(s, params: Params | None = None, X=None, U=None, lam=None, alpha_replay=
     rc = lib().orc_sqp(C.byref(c.robot), C.byref(c.prob), C.byref(prm), _ptr(xs), _ptr(qg), _ptr(X), _ptr(U),
                        _ptr(lamv), logs, _ptr(rep) if rep is not None else None,
                        (C.c_int * len(descent_replay))(*[int(v) for v in descent_replay])
-                       if descent_replay is not None else None)
+                       if descent_replay is not None else None,
+                       (C.c_int * len(pcg_replay))(*[int(v) for v in pcg_replay])
+                       if pcg_replay is not None else None)
     out = []
     for i in range(p.sqp_iters):
         L = logs[i]
         out.append(dict(merit0=L.merit0, merit=L.merit, alpha=L.alpha, J=L.J, c1=L.c1, kkt_res=L.kkt_res,
                         pcg_iters=L.pcg_iters, status=L.status, argmin=L.argmin, rho=L.rho,
+                        pcg_stop=L.pcg_stop, pcg_stop_prev=L.pcg_stop_prev,
                         merits=np.array(L.merits[:p.n_alpha])))
     return SqpResult(X=X, U=U, lam=lamv, logs=out, rc=rc)
 

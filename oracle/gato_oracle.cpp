@@ -110,6 +110,8 @@ typedef struct {
   int pad;
   double rho;          /* damping used in this iteration */
   double merits[ORC_MAX_ALPHA];
+  double pcg_stop;     /* r^T P r / (tol^2 gamma^T P gamma) after the last PCG iteration (<= 1: rule met) */
+  double pcg_stop_prev;/* the same one iteration earlier (> 1 when the rule first holds at the last one) */
 } orc_iter_log;
 
 }  // extern "C"
@@ -816,8 +818,13 @@ void tridiag_matvec(const std::vector<double> &A, const double *x, double *y, in
 }
 
 // Preconditioned conjugate gradient on S~ lambda = gamma~ (Sec. II-B) with the
-// stopping rule of reading R6. lam holds the initial guess on entry.
-int pcg(const Schur &s, double *lam, double tol, int max_iter, bool *hit_max) {
+// stopping rule of reading R6. lam holds the initial guess on entry. With
+// fixed_iters >= 0 the iteration count is prescribed instead (a replay of a
+// count decided elsewhere); ratio / ratio_prev (or NULL) receive the stopping
+// value r^T P r over tol^2 gamma^T P gamma after the last iteration and after
+// the one before it (infinity before the first).
+int pcg(const Schur &s, double *lam, double tol, int max_iter, bool *hit_max, int fixed_iters = -1,
+        double *ratio = nullptr, double *ratio_prev = nullptr) {
   const size_t dim = (size_t)s.N * s.nx;
   std::vector<double> r(dim), z(dim), p(dim), w(dim), pg(dim);
   auto S_times = [&](const double *x, double *y) { tridiag_matvec(s.S, x, y, s.nx, s.N); };
@@ -833,8 +840,10 @@ int pcg(const Schur &s, double *lam, double tol, int max_iter, bool *hit_max) {
   const double stop = tol * tol * eta_ref;
   int it = 0;
   *hit_max = false;
-  while (eta > stop) {
-    if (it >= max_iter) { *hit_max = true; break; }
+  double eta_prev = std::numeric_limits<double>::infinity();
+  while (fixed_iters >= 0 ? (it < fixed_iters && eta > 0.0) : eta > stop) {
+    if (fixed_iters < 0 && it >= max_iter) { *hit_max = true; break; }
+    eta_prev = eta;
     S_times(p.data(), w.data());
     double pw = 0.0;
     for (size_t i = 0; i < dim; ++i) pw += p[i] * w[i];
@@ -848,6 +857,8 @@ int pcg(const Schur &s, double *lam, double tol, int max_iter, bool *hit_max) {
     eta = eta_new;
     ++it;
   }
+  if (ratio) *ratio = eta / stop;
+  if (ratio_prev) *ratio_prev = eta_prev / stop;
   return it;
 }
 
@@ -1214,9 +1225,13 @@ double orc_merit(const orc_robot *rb, const orc_problem *pr, const double *xs, c
 // prescribes, per iteration, whether the line search counts as a descent for the
 // rho adaptation (1 descent, 0 none), so that a replay follows the same rho
 // sequence when two merits tie at FP32 resolution on the other side.
+// pcg_replay (or NULL; Schur + PCG mode only) prescribes the PCG iteration
+// count of each SQP iteration: the count is an integer that floating point
+// decides, so a replay takes the other side's decision and the log's
+// pcg_stop / pcg_stop_prev show whether the stopping rule holds there.
 int orc_sqp(const orc_robot *rb, const orc_problem *pr, const orc_params *prm, const double *xs,
             const double *qgoal, double *X, double *U, double *lam, orc_iter_log *log,
-            const double *alpha_replay, const int *descent_replay) {
+            const double *alpha_replay, const int *descent_replay, const int *pcg_replay) {
   const int n = rb->n, nx = 2 * n, nu = n, N = pr->N;
   const size_t nX = (size_t)N * nx, nU = (size_t)(N - 1) * nu;
   if (prm->n_alpha < 1 || prm->n_alpha > ORC_MAX_ALPHA) return -2;
@@ -1238,7 +1253,8 @@ int orc_sqp(const orc_robot *rb, const orc_problem *pr, const orc_params *prm, c
       if (!prm->warm_lambda) std::fill(lamv.begin(), lamv.end(), 0.0);
       bool hm = false;
       const int cap = prm->pcg_max_iter > 0 ? prm->pcg_max_iter : N * nx;
-      L.pcg_iters = pcg(s, lamv.data(), prm->pcg_tol, cap, &hm);
+      L.pcg_iters = pcg(s, lamv.data(), prm->pcg_tol, cap, &hm, pcg_replay ? pcg_replay[it] : -1, &L.pcg_stop,
+                        &L.pcg_stop_prev);
       if (hm) L.status |= ST_PCG_MAXITER;
       recover_step(lq, lamv.data(), dZ.data());
     } else {
