@@ -357,8 +357,10 @@ class Batch:
             self._h = None
         _live_batches.discard(self)
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (The default argument keeps the function reachable: at interpreter
+        # shutdown the module's globals, sys included, may already be gone.)
+        if _finalizing():
             return
         try:
             self.close()
@@ -641,8 +643,10 @@ class ServeContext:
             self._h = None
         _live_ctx.discard(self)
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (The default argument keeps the function reachable: at interpreter
+        # shutdown the module's globals, sys included, may already be gone.)
+        if _finalizing():
             return
         try:
             self.close()

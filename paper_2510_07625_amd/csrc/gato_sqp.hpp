@@ -1059,7 +1059,11 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   const bool split = kSplitOk && a.split && a.mode == kModeSqp && D.xch_off >= 0 && part >= 0 && part < nparts;
   // Four parts of a long FP64 solve: the part-local form (one knot per lane
   // group over the part's own knots).
-  if constexpr (kSplitOk && sizeof(Real) == 8) {
+  // The part-local form is switched off (kPartLocal): its results diverged
+  // from the oracle on the GPU (non-finite steps at N = 65..128); until the
+  // cause is found on the CPU, split solves take the four-knots-per-group form.
+  constexpr bool kPartLocal = false;
+  if constexpr (kPartLocal && kSplitOk && sizeof(Real) == 8) {
     static_assert(sizeof(PartSmem<ND>) <= smem_bytes<ND, KPT, Real, TS>(), "LDS of a part");
     if (split && a.split == 4 && !a.by_block) {
       sqp_solve_part<ND>(a, sid, part, smem_raw);
@@ -1634,14 +1638,18 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     // S~ product already holds.
     constexpr bool kFactP = KPT > 1 || TS || sizeof(Real) == 8;
     constexpr int KP = kFactP ? 1 : KPT;
-    // D^-1 rows: held in Real for one knot per lane group (FP64) and for the
-    // task-space variant, in FP32 (converted at use) otherwise. Rounding P to
-    // FP32 perturbs its smallest directions (P ~ S~^-1): on the headline batch
-    // the slowest solve then needs 9% more PCG iterations, on the far worse
-    // conditioned task-space systems 30-80% more, with a larger error at the
-    // same stopping value. With several knots per group, Real-held rows spill
-    // inside the PCG loop and cost more than they save.
-    constexpr bool kRealP = TS || (KPT == 1 && sizeof(Real) == 8);
+    // D^-1 rows: held in Real for one and two knots per lane group (FP64) and
+    // for the task-space variant, in FP32 (converted at use) otherwise.
+    // Rounding D^-1 to FP32 perturbs the preconditioner's smallest directions
+    // (P ~ S~^-1), which slows PCG and moves where a truncated PCG stops: on
+    // the headline batch the slowest solve needs 9% more iterations, at
+    // N = 64 up to 13% more, and the iterate at the stop then departs from the
+    // FP64 method's by up to 1e-3 after three SQP iterations (1e-5 with FP64
+    // rows); on the far worse conditioned task-space systems 30-80% more. With
+    // two knots per group the FP64 rows cost spills (288 against 208 B/lane,
+    // 22% per PCG iteration); with four they would cost far more, and long
+    // solves split across workgroups instead.
+    constexpr bool kRealP = TS || (KPT <= 2 && sizeof(Real) == 8);
     using PT = std::conditional_t<kRealP, Real, float>;
     PT Pm[KP][NX], Pp[KP][NX], Pdf[KPT][NX];
 #pragma unroll
@@ -2187,9 +2195,17 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         ++its;
       }
     }
+    bool xfail_any = false;   // some part of this solve gave up a wait
     if (xon) {
       xlam();
       xon = false;
+      // Every part's failure flag to every part: a part that gave up still
+      // publishes (without waiting), so a writer that did not give up learns
+      // that the rows it received were not the other parts' results.
+      __syncthreads();
+      double f0 = sm.xfail ? 1.0 : 0.0, f1 = 0.0, f2 = 0.0;
+      xsums(f0, f1, f2);
+      xfail_any = f0 != 0.0;
     }
     unsigned status = (gma > stop) ? GATO_ST_PCG_MAXITER : 0u;
     if (clk) clk[4] = wall_clock64();
@@ -2352,7 +2368,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         if (k < N - 1 && j < 8) sm.U[k][j] += al * sm.dU[k][j];
       }
     }
-    if (split && sm.xfail) status |= GATO_ST_EXCHANGE;
+    if (split && (sm.xfail || xfail_any)) status |= GATO_ST_EXCHANGE;
     if (tid == 0 && a.stats && writer) {
       gato_solve_stats st;
       st.merit0 = (float)sm.merit[n_alpha];
