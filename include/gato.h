@@ -545,6 +545,26 @@ int gato_step_graph(gato_batch *b, const float *d_xs, const float *d_goal, float
  */
 int gato_rbd_flops(int n_dof, double *out);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): gato_solve with the
+ * device staging of the statistics in a static device array of the library
+ * instead of a buffer the batch allocates on first use. Same arguments,
+ * results and return values as gato_solve; calls no hipMalloc, hipFree or
+ * other allocating routine (it launches a fill kernel, the SQP kernels, one
+ * device-to-host copy, and synchronises the batch stream when h_stats is
+ * given). The staging holds GATO_STATIC_STATS_MAX entries (24 bytes each,
+ * 1.5 MiB); every GPU the library runs this on keeps its own copy until the
+ * process ends, with the last call's contents. All calls on one GPU share it:
+ * calls that overlap in time on one GPU (other threads, other streams) race
+ * and must not be made. Errors: as gato_solve, and GATO_EINVAL when h_stats
+ * is non-NULL and M * sqp_iters exceeds GATO_STATIC_STATS_MAX (nothing is
+ * launched).
+ */
+#define GATO_STATIC_STATS_MAX 65536
+int gato_solve_static(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U,
+                      gato_solve_stats *h_stats);
+
 /* Thread-local message describing the last non-OK return (never NULL). */
 const char *gato_last_error(void);
 

@@ -76,7 +76,7 @@ EXPORTS = ("gato_default_params", "gato_workspace_bytes", "gato_batch_create", "
            "gato_serve_ctx_create", "gato_serve_ctx_destroy", "gato_serve_ctx_buffers", "gato_serve_ctx_submit",
            "gato_serve_ctx_query", "gato_serve_ctx_trajectories", "gato_serve_run", "gato_set_tip_reference",
            "gato_tip_positions", "gato_get_multipliers", "gato_set_multipliers", "gato_shift_warm_start",
-           "gato_last_error", "gato_probe_lds", "gato_select_hypotheses")
+           "gato_last_error", "gato_probe_lds", "gato_select_hypotheses", "gato_solve_static")
 
 _lib = None
 
@@ -101,6 +101,7 @@ def lib() -> C.CDLL:
         L.gato_batch_shape.argtypes = [vp, C.POINTER(ip), C.POINTER(ip), C.POINTER(ip)]
         L.gato_solve.argtypes = [vp, vp, vp, vp, vp, C.POINTER(SolveStats)]
         L.gato_step.argtypes = [vp, vp, vp, vp, vp, ip, vp]
+        L.gato_solve_static.argtypes = [vp, vp, vp, vp, vp, C.POINTER(SolveStats)]
         L.gato_step_plain.argtypes = [vp, vp, vp, vp, vp, ip, vp]
         L.gato_debug_lq.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.gato_debug_kkt.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -395,6 +396,17 @@ class Batch:
             arr = np.frombuffer(h, dtype=STATS_DTYPE).copy()
             return arr.reshape(self.M, max(self.params.sqp_iters, 1))
         _check(lib().gato_solve(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), None))
+        return None
+
+    def solve_static(self, xs, goal, X, U, stats: bool = True):
+        """gato_solve_static: gato_solve with the library's static statistics staging (allocates nothing)."""
+        self._io(xs, goal, X, U)
+        if stats:
+            h = (SolveStats * (self.M * max(self.params.sqp_iters, 1)))()
+            _check(lib().gato_solve_static(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), h))
+            arr = np.frombuffer(h, dtype=STATS_DTYPE).copy()
+            return arr.reshape(self.M, max(self.params.sqp_iters, 1))
+        _check(lib().gato_solve_static(self._h, _dptr(xs), _dptr(goal), _dptr(X), _dptr(U), None))
         return None
 
     def step(self, xs, goal, X, U, n_iters: int, d_stats=None, plain: bool = False, graph: bool = False):

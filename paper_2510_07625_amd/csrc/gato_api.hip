@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <deque>
+#include <mutex>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -1450,4 +1451,79 @@ int gato_step_graph(gato_batch *b, const float *d_xs, const float *d_goal, float
   if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
   return GATO_OK;
 }
+}  // extern "C"
+
+// ---- Allocation-free gato_solve (gato_solve_static). The device staging of the
+// per-iteration statistics is this file-scope array instead of a buffer the
+// batch allocates on demand; each device holds its own copy for the life of
+// the process. Host code never passes `scratch` itself to a kernel or a copy
+// (in host code the name is a stand-in, not a device address): it uses the
+// address hipGetSymbolAddress returns for the current device.
+namespace {
+
+constexpr size_t kScratchStats = GATO_STATIC_STATS_MAX;
+constexpr size_t kScratchBytes = kScratchStats * sizeof(gato_solve_stats);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on the current device (looked up once per device).
+int scratch_address(void **out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) return fail(GATO_EDEVICE, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return GATO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gato_solve_static(gato_batch *b, const float *d_xs, const float *d_goal, float *d_X, float *d_U,
+                      gato_solve_stats *h_stats) {
+  int rc = check_io(b, d_xs, d_goal, d_X, d_U);
+  if (rc) return rc;
+  const int iters = b->p.sqp_iters;
+  if (iters == 0) return GATO_OK;
+  const size_t need = (size_t)b->M * iters;
+  if (h_stats && need > kScratchStats)
+    return fail(GATO_EINVAL, "M * sqp_iters = " + std::to_string(need) + " exceeds the static statistics staging (" +
+                                 std::to_string(kScratchStats) + " entries)");
+  gato_solve_stats *ds = nullptr;
+  if (h_stats) {
+    void *p = nullptr;
+    rc = scratch_address(&p);
+    if (rc != GATO_OK) return rc;
+    ds = static_cast<gato_solve_stats *>(p);
+    // The staging keeps the previous call's contents: clear the part this call uses.
+    static_assert(sizeof(gato_solve_stats) % sizeof(double) == 0, "statistics are whole doubles");
+    const hipError_t e = gato::launch_fill(reinterpret_cast<double *>(ds),
+                                           need * sizeof(gato_solve_stats) / sizeof(double), 0.0, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch (clear statistics staging)");
+  }
+  rc = gato_step(b, d_xs, d_goal, d_X, d_U, iters, ds);
+  if (rc) return rc;
+  if (h_stats) {
+    hipError_t e = hipMemcpyAsync(h_stats, ds, need * sizeof(gato_solve_stats), hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(stats)");
+    e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (size_t i = 0; i < need; ++i)
+      if (h_stats[i].status) return 1;
+  }
+  return GATO_OK;
+}
+
 }  // extern "C"
