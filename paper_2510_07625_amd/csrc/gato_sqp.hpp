@@ -691,9 +691,12 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
         if (has_r && slot == nloc - 1) xput(xslot(part, xe) + 32 + 2 * lane, xtag(xe), right);
       }
     };
-    // Halo rows of exchange e into vl[0] (left neighbour's last knot) and
-    // vr[nloc + 1] (right neighbour's first knot), and, with sums, the three
-    // partials of every part summed in part order.
+    // Halo rows of exchange e, for an operand published as vl (the value) and
+    // vr (Q^-1 times it): the left neighbour's last knot sends its vr row,
+    // which lands in vr[0]; the right neighbour's first knot sends its vl row,
+    // which lands in vl[nloc + 1] (the products read vr[li - 1] and
+    // vl[li + 1]). With sums, the three partials of every part summed in part
+    // order.
     auto get_rows_sums = [&](unsigned e, bool sums, double (*vl)[G], double (*vr)[G], double &s0, double &s1,
                              double &s2) {
       const bool dead = sm.xfail != 0;
@@ -710,8 +713,8 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
         else ok = xget(wsum, xtag(e), dead, xspin, v);
         if (!ok) sm.xfail = 1;
       }
-      if (hl) vl[0][lane] = vh;
-      if (hr) vr[nloc + 1][lane] = vh;
+      if (hl) vr[0][lane] = vh;
+      if (hr) vl[nloc + 1][lane] = vh;
       wave_sync();
       if (sums) {
         s0 = (lane_val(v, 0) + lane_val(v, 3)) + (lane_val(v, 6) + lane_val(v, 9));
@@ -1057,13 +1060,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   const int nparts = a.split == 2 ? 2 : kXParts;
   const int psh = nparts == 2 ? 1 : 0;
   const bool split = kSplitOk && a.split && a.mode == kModeSqp && D.xch_off >= 0 && part >= 0 && part < nparts;
-  // Four parts of a long FP64 solve: the part-local form (one knot per lane
-  // group over the part's own knots).
-  // The part-local form is switched off (kPartLocal): its results diverged
-  // from the oracle on the GPU (non-finite steps at N = 65..128); until the
-  // cause is found on the CPU, split solves take the four-knots-per-group form.
-  constexpr bool kPartLocal = false;
-  if constexpr (kPartLocal && kSplitOk && sizeof(Real) == 8) {
+  // Four parts of a long FP64 solve run the part-local form (one knot per
+  // lane group over the part's own knots, FP64 D^-1 rows); two parts, and the
+  // all-FP32 variant, the four-knots-per-group form below.
+  if constexpr (kSplitOk && sizeof(Real) == 8) {
     static_assert(sizeof(PartSmem<ND>) <= smem_bytes<ND, KPT, Real, TS>(), "LDS of a part");
     if (split && a.split == 4 && !a.by_block) {
       sqp_solve_part<ND>(a, sid, part, smem_raw);

@@ -78,12 +78,19 @@ def test_split_solve_matches_the_oracle_and_the_one_workgroup_form(n, N):
               f"one-workgroup {s1[i]['pcg_iters'].tolist()}")
         assert ex <= 1e-4 and eu <= 1e-4, (i, ex, eu)
     # The same method: equal step sizes, multipliers close but summed in another
-    # order. Near the stopping value the PCG residual decreases slowly, so the
-    # summation order moves single counts by a few percent; the totals over the
-    # iterations stay within 5%.
+    # order. The four parts hold the preconditioner's D^-1 rows in FP64 like
+    # the FP64 oracle, the one-workgroup form at four knots per lane group in
+    # FP32 (which slows PCG by a few percent), so the split's PCG totals are
+    # held to the same-method oracle's (within 5%: near the stopping value the
+    # residual decreases slowly and rounding moves single counts) and the
+    # one-workgroup totals are printed.
     np.testing.assert_array_equal(ss["alpha"], s1["alpha"])
     ts, t1 = ss["pcg_iters"].sum(axis=1), s1["pcg_iters"].sum(axis=1)
-    assert np.all(np.abs(ts - t1) <= 0.05 * t1), (ts, t1)
+    to = np.array([sum(L["pcg_iters"] for L in oracle.sqp(
+        s, oracle.Params(sqp_iters=p.sqp_iters, kkt_mode=1, pcg_tol=p.pcg_tol),
+        alpha_replay=ss[i]["alpha"].astype(np.float64)).logs) for i, s in enumerate(solves)])
+    print(f"PCG totals: split {ts.tolist()}, FP64 oracle {to.tolist()}, one workgroup {t1.tolist()}")
+    assert np.all(np.abs(ts - to) <= 0.05 * to), (ts, to, t1)
     # Both stop at the PCG tolerance 1e-7 (R6), so their multipliers may differ
     # at that tolerance's order.
     scale = np.abs(l1).max()
