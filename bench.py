@@ -616,7 +616,7 @@ def cpu_baseline():
     oracle.lib()
     cores = len(os.sched_getaffinity(0))
     legs = {}
-    for name, mode, n1, nall in (("riccati", 2, 96, 16 * cores), ("dense_lu", 0, 12, 2 * cores)):
+    for name, mode, n1, nall in (("riccati", 2, 256, 48 * cores), ("dense_lu", 0, 24, 4 * cores)):
         for tag, n_solves, threads in (("1_core", n1, 1), ("all_cores", nall, cores)):
             solves = w.chain_batch(0, n_solves)
             t0 = time.perf_counter()

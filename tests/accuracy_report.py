@@ -4,10 +4,11 @@ A report, not a test (pytest does not collect it): run it on an MI355X as
 ``python tests/accuracy_report.py`` and it prints one JSON line with
 
 * the headline launch (M = 256 7-DoF chains, N = 32, 10 SQP iterations, PCG
-  tolerance 1e-5): the trajectory error of sampled solves against the exact
+  tolerance 1e-5): the trajectory error of every solve against the exact
   oracle (dense KKT LU) and against the oracle running the same method (Schur
-  + PCG at the same tolerance), the oracle replaying the GPU's accepted steps;
-  the FP64 method's own distance from the exact solve;
+  + PCG at the same tolerance), the oracle replaying the GPU's accepted steps
+  and PCG iteration counts; the FP64 method's own distance from the exact
+  solve;
 * every precision setting: the same trajectory error, and the KKT-solution
   error on identical QP data (the oracle's LQ data rounded once to FP32);
 * the uneven batch in its three precision settings: per (DoF, N) bucket,
@@ -57,21 +58,32 @@ def _launch(g, torch, solves, params):
     return out
 
 
-def trajectories(g, torch, solves, params, idx, exact_mode=0):
+def trajectories(g, torch, solves, params, idx, exact_mode=0, replay_counts=True):
+    """Sampled solves of one launch against the exact oracle and against the
+    same-method FP64 oracle replaying the GPU's accepted steps and (with
+    replay_counts) its PCG iteration counts. (The task-space kernel runs its
+    PCG on a congruent rewritten system, whose stopping decisions in floating
+    point are its own, so its comparison keeps the oracle's own counts.)"""
     X, U, st = _launch(g, torch, solves, params)
-    e_exact, e_same, e_method = [], [], []
-    for i in idx:
+
+    def one(i):
         s = solves[i]
         al = st[i]["alpha"].astype(np.float64)
         common = dict(sqp_iters=params.sqp_iters, mu=params.mu, beta=params.beta, n_alpha=params.n_alpha)
         exact = oracle.sqp(s, oracle.Params(kkt_mode=exact_mode, **common), alpha_replay=al)
         same = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=params.pcg_tol, warm_lambda=params.warm_lambda,
-                                           pcg_max_iter=params.pcg_max_iter, **common), alpha_replay=al)
-        e_exact.append(_rel(X[i], U[i], exact.X, exact.U))
-        e_same.append(_rel(X[i], U[i], same.X, same.U))
-        e_method.append(_rel(same.X, same.U, exact.X, exact.U))
+                                           pcg_max_iter=params.pcg_max_iter, **common), alpha_replay=al,
+                          pcg_replay=[int(c) for c in st[i]["pcg_iters"]] if replay_counts else None)
+        return (_rel(X[i], U[i], exact.X, exact.U), _rel(X[i], U[i], same.X, same.U),
+                _rel(same.X, same.U, exact.X, exact.U))
+
+    oracle.lib()
+    with ThreadPoolExecutor(16) as ex:
+        errs = list(ex.map(one, idx))
+    e_exact, e_same, e_method = zip(*errs)
     return dict(max_rel_traj_err_vs_exact=float(max(e_exact)), max_rel_traj_err_vs_same_method=float(max(e_same)),
-                same_method_vs_exact=float(max(e_method)), solves=[int(i) for i in idx],
+                median_rel_traj_err_vs_same_method=float(np.median(e_same)),
+                same_method_vs_exact=float(max(e_method)), solves=len(idx),
                 status_bits_set=int((st["status"] != 0).sum()))
 
 
@@ -115,7 +127,7 @@ def closed_loop(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, oracle_tic
     q = run.states.cpu().numpy()[:, :, :7].astype(np.float64)
     qg = np.stack([s.qgoal for s in solves])
     track = np.linalg.norm(q - qg[None], axis=2)
-    errs = []
+    errs, errs_same = [], []
     for t in rec:
         R = run.records[t]
         for i in idx:
@@ -123,9 +135,13 @@ def closed_loop(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, oracle_tic
             Xw = R["X_prev"][i].astype(np.float64)[np.minimum(np.arange(N) + 1, N - 1)]
             Uw = R["U_prev"][i].astype(np.float64)[np.minimum(np.arange(N - 1) + 1, N - 2)]
             st = dataclasses.replace(s, xs=R["xs"][i].astype(np.float64))
-            ref = oracle.sqp(st, oracle.Params(sqp_iters=iters, kkt_mode=2), X=Xw, U=Uw,
-                             alpha_replay=R["stats"][i]["alpha"].astype(np.float64))
+            al = R["stats"][i]["alpha"].astype(np.float64)
+            ref = oracle.sqp(st, oracle.Params(sqp_iters=iters, kkt_mode=2), X=Xw, U=Uw, alpha_replay=al)
             errs.append(_rel(R["X"][i], R["U"][i], ref.X, ref.U))
+            lam_w = R["lam_prev"][i][np.minimum(np.arange(N) + 1, N - 1)]
+            same = oracle.sqp(st, oracle.Params(sqp_iters=iters, kkt_mode=1, pcg_tol=1e-5), X=Xw, U=Uw, lam=lam_w,
+                              alpha_replay=al, pcg_replay=[int(c) for c in R["stats"][i]["pcg_iters"]])
+            errs_same.append(_rel(R["X"][i], R["U"][i], same.X, same.U))
 
     def oracle_loop(i):
         s = solves[i]
@@ -144,7 +160,8 @@ def closed_loop(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, oracle_tic
     with ThreadPoolExecutor(len(idx)) as ex:
         otrack = np.stack(list(ex.map(oracle_loop, idx)), axis=1)
     gtrack = track[:oracle_ticks + 1, idx]
-    return dict(tick_replay_max_rel_err_vs_exact=float(max(errs)), ticks_replayed=rec,
+    return dict(tick_replay_max_rel_err_vs_exact=float(max(errs)),
+                tick_replay_max_rel_err_vs_same_method=float(max(errs_same)), ticks_replayed=rec,
                 instances=[int(i) for i in idx],
                 oracle_loop=dict(ticks=oracle_ticks, max_abs_tracking_diff_rad=float(np.abs(otrack - gtrack).max()),
                                  mean_tracking_gpu=float(gtrack.mean()), mean_tracking_oracle=float(otrack.mean())))
@@ -153,7 +170,7 @@ def closed_loop(g, torch, M=256, N=64, ticks=1000, iters=3, sample=8, oracle_tic
 def task_space(g, torch, M=256, iters=10, idx=(0, 128, 255)):
     solves = w.figure8_batch(0, M)
     params = g.Params(sqp_iters=iters, pcg_tol=1e-5, pcg_max_iter=1000)
-    traj = trajectories(g, torch, solves, params, idx, exact_mode=2)
+    traj = trajectories(g, torch, solves, params, idx, exact_mode=2, replay_counts=False)
     # Step by step from the GPU's own iterates (cold PCG starts on both sides).
     p1 = g.Params(sqp_iters=iters, pcg_tol=1e-5, pcg_max_iter=1000, warm_lambda=0)
     b = g.Batch.from_solves(solves, p1)
@@ -209,7 +226,8 @@ def uneven(g, torch, M=128, seed=0, per_bucket=2):
             al = st[i]["alpha"].astype(np.float64)
             common = dict(sqp_iters=10, mu=params.mu, beta=params.beta, n_alpha=params.n_alpha)
             exact = oracle.sqp(s, oracle.Params(kkt_mode=2, **common), alpha_replay=al)
-            same = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=params.pcg_tol, **common), alpha_replay=al)
+            same = oracle.sqp(s, oracle.Params(kkt_mode=1, pcg_tol=params.pcg_tol, **common), alpha_replay=al,
+                              pcg_replay=[int(c) for c in st[i]["pcg_iters"]])
             n, N = s.n, s.N
             Xi, Ui = X[i, :N, :2 * n], U[i, :N - 1, :n]
             return _rel(Xi, Ui, same.X, same.U), _rel(Xi, Ui, exact.X, exact.U)
@@ -232,7 +250,7 @@ def main():
     out = {}
     solves = w.chain_batch(0, 256)
     params = g.Params(sqp_iters=10, pcg_tol=1e-5)
-    out["headline"] = trajectories(g, torch, solves, params, (0, 85, 170, 255))
+    out["headline"] = trajectories(g, torch, solves, params, range(256))
     print("# headline", out["headline"], file=sys.stderr, flush=True)
     prec = []
     for kw in PRECISIONS:
