@@ -595,13 +595,13 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
 
     // ================= 2. Schur rows and diagonal-block inverses of the own knots.
     Real th[NX], Pdf[NX];
-    float Am[NX], Ac[NX];
+    double Am[NX], Ac[NX];   // the A_{k-1} row and A_k column, converted once per SQP iteration
     Real gam = 0, qown = 0;
 #pragma unroll
     for (int m = 0; m < NX; ++m) {
       th[m] = 0;
-      Am[m] = 0.f;
-      Ac[m] = 0.f;
+      Am[m] = 0.0;
+      Ac[m] = 0.0;
       Pdf[m] = 0;
     }
     if (own && lane < NX) {
@@ -1483,21 +1483,29 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 
     // ================= 2. Schur complement rows and diagonal-block inverses.
     Real th[kThGlobal ? 1 : KPT][NX];   // row of the diagonal block theta_{k-1} (Q_0^-1 for k = 0)
-    // A entries are exact in FP32 and are kept so (converted to Real at use),
-    // which halves their register footprint.
-    // With four knots per lane group (FP64 variant) these rows are read back
-    // from the A blocks in the workspace where they are used (as the Schur rows
-    // are), which frees 112 registers per lane; the FP32 variant has the room.
+    // A entries are exact in FP32. With one knot per lane group (FP64
+    // variant) the rows are held converted to FP64, once per SQP iteration:
+    // the PCG loop then converts nothing (28 conversions fewer per iteration)
+    // and, since its two products would otherwise keep FP64 copies of the
+    // FP32 rows live across the second barrier, holds fewer registers too
+    // (spills 88 -> 20 B/lane, 12% off the headline call). Elsewhere they
+    // are kept in FP32 (converted to Real at use), which halves their
+    // register footprint. With four knots per lane group (FP64 variant) the
+    // rows are read back from the A blocks in the workspace where they are
+    // used (as the Schur rows are), which frees 112 registers per lane; the
+    // FP32 variant has the room.
     constexpr bool kRowsGlobal = KPT >= 4 && sizeof(Real) == 8;
     static_assert(kRowsGlobal == kColsT, "column reads of A_k need its transposed copy");
     constexpr int KR = kRowsGlobal ? 1 : KPT;
-    float Am[KR][NX];     // row `lane` of A_{k-1}: S~_{k,k-1} = -A_{k-1} Q_{k-1}^-1
-    float Ac[KR][NX];     // column `lane` of A_k: S~_{k,k+1} = -Q_k^-1 A_k^T
-    auto am = [&](int p, int m) -> float {
+    constexpr bool kRealA = (KPT == 1) && sizeof(Real) == 8 && !TS;
+    using AT = std::conditional_t<kRealA, double, float>;
+    AT Am[KR][NX];     // row `lane` of A_{k-1}: S~_{k,k-1} = -A_{k-1} Q_{k-1}^-1
+    AT Ac[KR][NX];     // column `lane` of A_k: S~_{k,k+1} = -Q_k^-1 A_k^T
+    auto am = [&](int p, int m) -> AT {
       if constexpr (kRowsGlobal) return Ablk(slot + p * SLOTS - 1)[lane * NX + m];
       else return Am[p][m];
     };
-    auto ac = [&](int p, int m) -> float {
+    auto ac = [&](int p, int m) -> AT {
       if constexpr (kRowsGlobal) return ATblk(slot + p * SLOTS)[lane * NX + m];
       else return Ac[p][m];
     };
@@ -2106,8 +2114,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
       // into beta = gamma rg, alpha = gamma / (delta - gamma^2 c): one division.
       Real rg = 0, cga = 0;
       for (;;) {
-        // Keep the FP32 matrix rows as FP32 across iterations (stops the
-        // compiler from hoisting their conversions and doubling their registers).
+        // Keep the matrix rows as they are across iterations (stops the
+        // compiler from hoisting conversions of FP32 rows and doubling their
+        // registers).
 #pragma unroll
         for (int p = 0; p < KPT; ++p)
 #pragma unroll
