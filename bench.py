@@ -360,6 +360,54 @@ def task_space_report(g, torch, M=256, N=32, iters=10, steps=10, seed=0, pcg_tol
     return out
 
 
+def task_uneven_report(g, torch, M=128, iters=10, steps=3, seed=0, pcg_tol=1e-5, pcg_max_iter=1000):
+    """Uneven task-space batch: the DoF and horizons of the uneven batch (3-7 DoF,
+    16-128 knots), every solve tracking a figure-8 with the tip, `iters` SQP
+    iterations per call. Its long solves (6-7 DoF, N > 64) run only split
+    (four workgroups each, part-local); the step is timed eager and as the
+    graph replay (the split kernel as a cooperative node), which gives
+    `solves_per_s`. (Per-bucket errors against the oracle come from
+    tests/accuracy_report.py.)"""
+    import workload as w
+    solves = w.figure8_uneven_batch(seed, M=M)
+    b = g.Batch.from_solves(solves, g.Params(sqp_iters=iters, pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter))
+    xs, goal, X0, U0 = g.pack_inputs(solves)
+    X, U = X0.clone(), U0.clone()
+    st = b.stats_buffer(iters)
+
+    def timed(graph):
+        ms = []
+        for r in range(steps + 1):
+            X.copy_(X0)
+            U.copy_(U0)
+            b.reset_warm_start()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            b.step(xs, goal, X, U, iters, st, graph=graph)
+            e1.record()
+            torch.cuda.synchronize()
+            if r:
+                ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    t_eager = timed(False)
+    t_graph = timed(True)
+    stats = g.Batch.decode_stats(st, M, iters)
+    b.close()
+    status = {k: int(((stats["status"] & bit) != 0).sum()) for k, bit in
+              (("pcg_maxiter", g.ST_PCG_MAXITER), ("nonfinite", g.ST_NONFINITE), ("exchange", g.ST_EXCHANGE),
+               ("no_descent", g.ST_NO_DESCENT))}
+    out = dict(M=M, sqp_iters=iters, pcg_tol=pcg_tol, pcg_max_iter=pcg_max_iter,
+               long_split_solves=sum(1 for sv in solves if sv.n >= 6 and sv.N > 64),
+               eager_ms=t_eager, graph_ms=t_graph, solves_per_s=M / (t_graph * 1e-3), status_bits=status,
+               pcg_iters_per_solve_by_bucket={f"{n}x{N}": float(np.mean([stats["pcg_iters"][i].sum()
+                                                                         for i, sv in enumerate(solves)
+                                                                         if (sv.n, sv.N) == (n, N)]))
+                                              for n, N in sorted({(sv.n, sv.N) for sv in solves})})
+    print(f"# task uneven {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def task_closed_loop_report(g, torch, M=256, N=32, ticks=300, iters=3, seed=0, pcg_tol=1e-5, pcg_max_iter=1000):
     """Figure-8 MPC: M 7-DoF chains track a figure-8 with the tip in closed loop
     (RK4 plant, 10 sub-steps of 1 ms per 10 ms tick), each tick re-solving with
@@ -733,6 +781,8 @@ def main():
     prec = [] if args.profile_run or args.no_precision else precision_report(g, torch, M, 5, args.pcg_tol)
     uneven = {} if args.profile_run or args.no_uneven else uneven_report(g, torch)
     task = {} if args.profile_run or args.no_task_space else task_space_report(g, torch)
+    if task:
+        task["uneven"] = task_uneven_report(g, torch)
     if task and args.task_closed_loop_ticks > 0:
         task["closed_loop"] = task_closed_loop_report(g, torch, ticks=args.task_closed_loop_ticks)
     hmap = [] if args.no_heatmap else heatmap(g, torch)

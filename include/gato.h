@@ -87,10 +87,14 @@ typedef struct {
  * of the tip of the last link in the base frame, W = Wee_diag for k < N-1 and
  * WeeN_diag at the last knot, pref set with gato_set_tip_reference (zero until
  * then). The QP uses the exact gradient and the Gauss-Newton Hessian J^T W J
- * of this term, so each Q_k gets a dense joint block. Serial chains only, at
- * most 2 knots per lane group (N <= 64 for 6-7 DoF, 128 for 3 DoF); a batch
- * with such a term runs the task-space kernels for all its solves (no stage
- * entry points). Both NULL: no such term (zero-initialise the struct).
+ * of this term, so each Q_k gets a dense joint block. Serial chains only; a
+ * batch with such a term runs the task-space kernels for all its solves (no
+ * stage entry points). Its long solves (6-7 DoF, N > 64) run only on four
+ * workgroups each (see gato_set_split), which needs schur_fp64 = 1 and the
+ * whole batch (one workgroup per short solve, four per long one) resident on
+ * the device at once (otherwise gato_batch_create returns GATO_EUNSUPPORTED);
+ * such a batch takes no serving steps. Both NULL: no such term
+ * (zero-initialise the struct).
  */
 typedef struct {
   int N;               /* knot points, 2..GATO_MAX_KNOTS */
@@ -265,7 +269,8 @@ int gato_get_trajectories(gato_batch *b, float *d_X, float *d_U);
  * d_stats ([n_req][n_iters]). Launched on hip_stream (NULL: the batch stream)
  * so that several steps on disjoint slots can overlap. Batches that mix shapes
  * run through the mixed-shape kernel. A slot outside 0..M-1 is skipped (its
- * outputs are left as they were). Errors: GATO_EINVAL.
+ * outputs are left as they were). Errors: GATO_EINVAL, GATO_EUNSUPPORTED (a
+ * batch with long solves with tip tracking).
  */
 int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d_xs, const float *d_goal,
                     int n_iters, int shift, float *d_Xout, float *d_Uout, gato_solve_stats *d_stats,
@@ -466,27 +471,33 @@ int gato_set_dispatch(gato_batch *b, int mode);
 
 /*
  * Multi-CU split of long solves. A solve with four knots per lane group (6-7
- * DoF, N > 64) in a batch without tip tracking runs on four workgroups (parts
- * = 4, the default), each holding the PCG rows of 32 knots, or on two, each
- * holding those of 64 knots, when four workgroups per solve do not fit the
- * device at once. The parts run the PCG of Sec. III-B (the same Eq. (5)
- * system, preconditioner and stopping rule) together, exchanging halo rows and
- * inner products through device memory at every PCG iteration; the rest of the
- * SQP iteration is computed by each part alike, and part 0 writes the results.
+ * DoF, N > 64) runs on four workgroups (parts = 4, the default), each holding
+ * the PCG rows of 32 knots, or on two, each holding those of 64 knots, when
+ * four workgroups per solve do not fit the device at once. The parts run the
+ * PCG of Sec. III-B (the same Eq. (5) system, preconditioner and stopping
+ * rule) together, exchanging halo rows and inner products through device
+ * memory at every PCG iteration. With four parts and schur_fp64 = 1 each part
+ * forms the LQ data, Schur rows, step and line-search terms of its own 32
+ * knots (and of the knots next to them), the merits are summed over the
+ * parts, and each part writes its own knots' results; otherwise every part
+ * computes the rest of the SQP iteration alike and part 0 writes the results.
  * The split applies to gato_step, gato_solve and gato_profile_phases as a
  * cooperative launch (every workgroup resident at once), and to
  * gato_step_graph of a mixed-shape batch as a cooperative kernel node (after a
  * node that clears the exchange words). Under the caller's own stream
  * capture, in gato_step_graph of a batch launched per shape group, with
  * parts = 1, and when even two workgroups per solve do not fit, every solve
- * runs on one workgroup. The inner products are
+ * of a batch without tip tracking runs on one workgroup; long solves with tip
+ * tracking run only on four parts in one launch of the whole batch, so
+ * there those cases return GATO_EUNSUPPORTED. The inner products are
  * summed per part first, so results differ from the one-workgroup form at
  * rounding level. A part that waits too long for another sets
  * GATO_ST_EXCHANGE: every wait polls at most max_polls times (0: the default,
  * 131072 polls, about 0.1 s), after which the part stops waiting for the rest
  * of the call and its results are invalid. A batch allocates four workspaces
  * and an exchange area (42 KB) per such solve. Errors: GATO_EINVAL (parts not
- * 1 or 4, max_polls < 0).
+ * 1 or 4, max_polls < 0), GATO_EUNSUPPORTED (parts = 1 in a batch with long
+ * solves with tip tracking).
  */
 int gato_set_split(gato_batch *b, int parts, int max_polls);
 
@@ -507,8 +518,10 @@ int gato_buckets(const gato_batch *b, gato_bucket *out, int cap, int *n_out);
 
 /*
  * Sets the knots-per-group mapping of one bucket by hand. kpt must be 1, 2 or
- * 4 (at most 2 for 3 DoF) and at least the minimum for N. Errors: GATO_EINVAL (no such bucket, or
- * kpt not allowed).
+ * 4 (at most 2 for 3 DoF) and at least the minimum for N; in a batch with tip
+ * tracking, 4 only where it is the minimum (N > 64). Errors: GATO_EINVAL (no
+ * such bucket, or kpt not allowed), GATO_EUNSUPPORTED (kpt 4 with tip tracking
+ * at N <= 64).
  */
 int gato_set_mapping(gato_batch *b, int n_dof, int N, int kpt);
 
@@ -516,7 +529,8 @@ int gato_set_mapping(gato_batch *b, int n_dof, int N, int kpt);
  * Autotuner: for every (n_dof, N) bucket, times each allowed kpt on the
  * bucket's own solves (mixed-shape kernel, n_iters SQP iterations from d_X,
  * d_U, reps timed runs after one warm-up, HIP events, the median kept) and
- * keeps the fastest. d_X and d_U are read only (the runs use copies); the PCG
+ * keeps the fastest (buckets of long solves with tip tracking have one mapping
+ * and are not timed). d_X and d_U are read only (the runs use copies); the PCG
  * warm start is cleared afterwards. Synchronous; allocates temporary device
  * memory. Errors: GATO_EINVAL, GATO_ENOMEM, GATO_EDEVICE.
  */

@@ -109,6 +109,7 @@ struct gato_batch {
   unsigned *d_plant_status = nullptr;  // [M], used when the caller passes none
   double *d_rho = nullptr;             // [M] per-solve damping
   bool task = false;                   // some solve has a tip tracking term (task-space kernels)
+  bool task_long = false;              // ... and some solve is long (6-7 DoF, N > 64): it runs only split
   bool fe_on_device = false;           // tip forces were last set on the device (gato_select_hypotheses)
   float *d_pref = nullptr;             // [M][N_max][3] reference tip positions
   // Launch groups: solves of one (n, kpt) shape, longest horizon first.
@@ -370,16 +371,33 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     N_max = std::max(N_max, q.N);
   }
 
-  bool task = false;
+  bool task = false, task_long = false;
   for (const auto &d : desc) task = task || d.task;
-  if (task)
-    for (int i = 0; i < M; ++i)
-      if (desc[i].kpt > gato::kTaskKptMax)
-        return fail(GATO_EUNSUPPORTED, "solve " + std::to_string(i) +
-                                           ": batches with tip tracking are compiled for N <= 64 (6-7 DoF)");
+  int n_long = 0;
+  for (int i = 0; i < M; ++i) {
+    if (desc[i].kpt == 4) ++n_long;
+    if (!task || desc[i].kpt <= gato::kTaskKptMax) continue;
+    // Long solves of a batch with tip tracking run only as four parts of a
+    // split launch (the part-local form is FP64).
+    if (!prm.schur_fp64)
+      return fail(GATO_EUNSUPPORTED, "solve " + std::to_string(i) +
+                                         ": batches with tip tracking take N > 64 (6-7 DoF) with schur_fp64 = 1 only");
+    task_long = true;
+  }
+  if (task_long) {
+    // All workgroups of that launch (one per short solve, four per long one)
+    // must be resident together.
+    const hipError_t e0 = gato::cooperative_fits(gato::sqp_mixed_task_split_fn(), M + (gato::kSplitParts - 1) * n_long);
+    if (e0 == hipErrorCooperativeLaunchTooLarge)
+      return fail(GATO_EUNSUPPORTED, "a batch with tip tracking and long solves must fit the device at once: " +
+                                         std::to_string(M + (gato::kSplitParts - 1) * n_long) +
+                                         " workgroups (one per short solve, four per long one) do not");
+    if (e0 != hipSuccess) return hip_fail(e0, "occupancy query");
+  }
   gato_batch *b = new gato_batch();
   b->M = M;
   b->task = task;
+  b->task_long = task_long;
   b->n_max = n_max;
   b->N_max = N_max;
   b->p = prm;
@@ -396,7 +414,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
     desc[i].offAT = (int64_t)l.offAT;
     // Long solves (four knots per lane group) can split: a workspace per part
     // and an exchange area.
-    const bool can_split = desc[i].kpt == 4 && !task;
+    const bool can_split = desc[i].kpt == 4 && (!task || prm.schur_fp64);
     desc[i].ws_part = can_split ? (int64_t)l.total : 0;
     desc[i].xch_off = can_split ? xwords : -1;
     if (can_split) {
@@ -558,6 +576,18 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split 
     as.epoch = b->epoch;
     as.xch = b->d_xch;
     as.xspin = b->split_polls;
+  }
+  if (b->task_long) {
+    // Long task-space solves have no one-workgroup kernel: the whole batch is
+    // one split launch of the task-space mixed-shape kernel.
+    if (!split)
+      return fail(GATO_EUNSUPPORTED, "long solves with tip tracking run only split: not under stream capture "
+                                     "(gato_step_graph builds the split launch)");
+    as.split = gato::kSplitParts;
+    as.order = b->d_order_split_all[0];
+    const hipError_t e = gato::launch_sqp_mixed_task_split(b->grid_split_all[0], as, s);
+    if (e != hipSuccess) return hip_fail(e, "kernel launch (split)");
+    return GATO_OK;
   }
   if (use_mixed(b)) {
     for (int q = 0; split && q < 2; ++q) {
@@ -766,6 +796,7 @@ int gato_serve_step(gato_batch *b, int n_req, const int *d_slots, const float *d
   if (!d_slots || !d_xs || !d_goal) return fail(GATO_EINVAL, "slots, xs and goal must not be NULL");
   if (n_iters < 1) return fail(GATO_EINVAL, "n_iters must be >= 1");
   if (shift < 0 || shift > 1) return fail(GATO_EINVAL, "shift must be 0 or 1");
+  if (b->task_long) return fail(GATO_EUNSUPPORTED, "serving takes no long solves with tip tracking (they run only split)");
   gato::KArgs a = base_args(b);
   a.xs = d_xs;
   a.goal = d_goal;
@@ -1183,6 +1214,7 @@ int gato_set_split(gato_batch *b, int parts, int max_polls) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (parts != 1 && parts != gato::kSplitParts) return fail(GATO_EINVAL, "parts must be 1 or 4");
   if (max_polls < 0) return fail(GATO_EINVAL, "max_polls must be >= 0");
+  if (parts == 1 && b->task_long) return fail(GATO_EUNSUPPORTED, "long solves with tip tracking run only split");
   b->split_parts = parts;
   b->split_polls = max_polls;
   return GATO_OK;
@@ -1217,8 +1249,8 @@ int gato_buckets(const gato_batch *b, gato_bucket *out, int cap, int *n_out) {
 int gato_set_mapping(gato_batch *b, int n_dof, int N, int kpt) {
   if (!b) return fail(GATO_EINVAL, "batch is NULL");
   if (!kpt_allowed(n_dof, N, kpt)) return fail(GATO_EINVAL, "kpt must be 1, 2 or 4 and cover N");
-  if (b->task && kpt > gato::kTaskKptMax)
-    return fail(GATO_EUNSUPPORTED, "tip tracking kernels are compiled for kpt 1 and 2");
+  if (b->task && kpt > gato::kTaskKptMax && gato::kpt_for(n_dof, N) <= gato::kTaskKptMax)
+    return fail(GATO_EUNSUPPORTED, "tip tracking kernels are compiled for kpt 1 and 2 (4: only N > 64, split)");
   bool any = false;
   for (auto &d : b->desc)
     if (d.n == n_dof && d.N == N) {
@@ -1281,6 +1313,8 @@ int gato_autotune(gato_batch *b, const float *d_xs, const float *d_goal, const f
   for (size_t k = 0; k < keys.size(); ++k) {
     const int n = keys[k].first, N = keys[k].second;
     auto &v = mem[k];
+    // Long task-space solves have one mapping (four knots per lane group, split).
+    if (b->task && gato::kpt_for(n, N) > gato::kTaskKptMax) continue;
     std::stable_sort(v.begin(), v.end());
     e = hipMemcpy(order, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipMemcpy(order)"); }
@@ -1336,9 +1370,11 @@ namespace {
 // one-workgroup form.
 int build_split_graph(gato_batch *b, const gato::KArgs &a, hipGraph_t *out) {
   *out = nullptr;
-  if (!use_mixed(b) || b->split_parts != gato::kSplitParts || b->n_split == 0 || b->task) return GATO_OK;
-  const void *fn = b->p.schur_fp64 ? gato::sqp_mixed_f64_split_fn() : gato::sqp_mixed_f32_split_fn();
-  for (int q = 0; q < 2; ++q) {
+  if (b->split_parts != gato::kSplitParts || b->n_split == 0) return GATO_OK;
+  if (b->task ? !b->task_long : !use_mixed(b)) return GATO_OK;
+  const void *fn = b->task ? gato::sqp_mixed_task_split_fn()
+                           : (b->p.schur_fp64 ? gato::sqp_mixed_f64_split_fn() : gato::sqp_mixed_f32_split_fn());
+  for (int q = 0; q < (b->task ? 1 : 2); ++q) {
     const int grid = b->grid_split_all[q];
     if (grid <= b->M) continue;
     hipError_t e = gato::cooperative_fits(fn, grid);
@@ -1384,6 +1420,8 @@ int build_split_graph(gato_batch *b, const gato::KArgs &a, hipGraph_t *out) {
     if (e != hipSuccess) {
       (void)hipGetLastError();
       (void)hipGraphDestroy(g);
+      if (b->task_long) return fail(GATO_EUNSUPPORTED, "the runtime refuses a cooperative graph node (long solves "
+                                                       "with tip tracking run only split)");
       return GATO_OK;
     }
     *out = g;

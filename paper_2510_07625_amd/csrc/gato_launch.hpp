@@ -17,6 +17,10 @@ hipError_t launch_sqp(int nd, int kpt, bool f64, int grid, const KArgs &a, hipSt
 hipError_t launch_sqp_task(int nd, int kpt, bool f64, int grid, const KArgs &a, hipStream_t s);
 // The mixed-shape kernel of the task-space variant.
 hipError_t launch_sqp_mixed_task(int grid, bool f64, const KArgs &a, hipStream_t s);
+// Its split form (FP64; a cooperative launch, as the other split kernels).
+hipError_t launch_sqp_mixed_task_split(int grid, const KArgs &a, hipStream_t s);
+// Largest knots per lane group of the one-workgroup task-space kernels; longer
+// task-space solves run only split.
 constexpr int kTaskKptMax = 2;
 
 // hipSuccess when `grid` workgroups of kernel f fit the device at once (the
@@ -44,6 +48,7 @@ const void *fill_kernel_fn();
 // The split mixed-shape kernels (one KArgs argument, kBlock threads).
 const void *sqp_mixed_f64_split_fn();
 const void *sqp_mixed_f32_split_fn();
+const void *sqp_mixed_task_split_fn();
 
 // Exchange-tag epoch of split launches replayed from a graph. Eager launches
 // cycle through 1..kGraphEpoch-1, so words a replay leaves behind never carry

@@ -344,6 +344,170 @@ __device__ __forceinline__ bool xget(unsigned long long *w, unsigned tag, bool d
   return xget2(w, nullptr, tag, dead, spin, v, unused);
 }
 
+// ---- Task-space variant: the tip term of one knot, by the knot's lane group.
+// Tip position and Jacobian (lane j: one dual-number pass seeded on q_j), the
+// residual p(q) - pref and its cost (lane 0), then H = diag(Q_q + rho) +
+// J^T W J, its Cholesky factor L (column by column, lane i holding row i,
+// pivots broadcast through tq) and L^-1 (lane j forming column j by forward
+// substitution). x: the knot's state; Jt, pe, mt, tq, Lc, Li: its LDS rows.
+template <int ND>
+__device__ __forceinline__ void tip_factor(const Chain &ch, const float *x, const float *pr, const float *We,
+                                           const double *Qd, double rho, int lane, float (*Jt)[8], float *pe,
+                                           double *mt, double *tq, double *Lc, double *Li, int &bad_flag) {
+  if (lane < ND) {
+    dual<float> qv[ND], pt[3];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) qv[i] = dual<float>{x[i], i == lane ? 1.f : 0.f};
+    tip_position<ND>(ch, qv, pt);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Jt[c][lane] = pt[c].d;
+    if (lane == 0) {
+      double tc = 0.0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float d = pt[c].v - pr[c];
+        pe[c] = d;
+        tc += 0.5 * (double)We[c] * (double)d * (double)d;
+      }
+      *mt = tc;
+      if (!isfinite(tc)) bad_flag = 1;
+    }
+  }
+  wave_sync();
+  double hr[ND], lr[ND];
+#pragma unroll
+  for (int j = 0; j < ND; ++j) {
+    double t = (j == lane) ? Qd[j] + rho : 0.0;
+    if (lane < ND) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) t += (double)We[c] * (double)Jt[c][lane] * (double)Jt[c][j];
+    }
+    hr[j] = t;
+    lr[j] = 0.0;
+  }
+#pragma unroll
+  for (int c = 0; c < ND; ++c) {
+    if (lane == c) tq[0] = hr[c];
+    wave_sync();
+    const double piv = tq[0];
+    wave_sync();
+    if (lane == 0 && !(piv > 0.0)) bad_flag = 1;
+    const double dinv = 1.0 / sqrt(piv);
+    const double l = (lane >= c && lane < ND) ? hr[c] * dinv : 0.0;   // L[lane][c]
+    lr[c] = l;
+    if (lane < ND) tq[lane] = l;
+    wave_sync();
+#pragma unroll
+    for (int j = c + 1; j < ND; ++j) hr[j] -= l * tq[j];
+    wave_sync();
+  }
+  if (lane < ND) {
+#pragma unroll
+    for (int j = 0; j < ND; ++j)
+      if (j <= lane) Lc[tri(lane, j)] = lr[j];
+  }
+  wave_sync();
+  if (lane < ND) {
+    // Column `lane` of L^-1: rows lane..ND-1 of the solution of L x = e_lane.
+    double xs[ND];
+#pragma unroll
+    for (int i = 0; i < ND; ++i) {
+      double t = (i == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int m = 0; m < i; ++m)
+        if (m >= lane) t -= Lc[tri(i, m)] * xs[m];
+      xs[i] = (i >= lane) ? t / Lc[tri(i, i)] : 0.0;
+      if (i >= lane) Li[tri(i, lane)] = xs[i];
+    }
+  }
+}
+
+// Rewrites knot k's QP data in y_k = T_k^-1 x_k, lane `lane` owning state row
+// `lane`: row `lane` of A_k -> T_{k+1}^-1 A_k T_k and e_k -> T_{k+1}^-1 e_k
+// (when the knot has a successor, `succ`; L1 = L_{k+1}), q_k (with the tip
+// term J^T W (p - pref) added) -> T_k^T q_k, and c_0 -> T_0^-1 c_0 (at the
+// first knot, `first`). The joint rows of A_k are [I, hI] by construction of
+// the Euler step. Lk, Lik: L_k and L_k^-1; tq: the knot's LDS exchange row.
+// (Every pointer is valid; the flags say which rows are rewritten, so that
+// the LDS accesses keep their address space.)
+template <int ND>
+__device__ __forceinline__ void tip_rewrite(int lane, bool succ, bool first, float h, const double *Lk,
+                                            const double *Lik, const double *L1, float *Ar, float *e, float *qg,
+                                            float *c0, const float (*Jt)[8], const float *pe, const float *We,
+                                            double *tq) {
+  constexpr int NX = 2 * ND;
+  if (succ && lane < NX) {
+    if (lane < ND) {
+      // Row `lane` of [L_{k+1}^T L_k^-T, h L_{k+1}^T].
+#pragma unroll
+      for (int c = 0; c < ND; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int m = 0; m <= c; ++m)
+          if (m >= lane) t += L1[tri(m, lane)] * Lik[tri(c, m)];
+        Ar[c] = (float)t;
+        Ar[ND + c] = c >= lane ? (float)((double)h * L1[tri(c, lane)]) : 0.f;
+      }
+    } else {
+      // Velocity row: its joint columns times L_k^-T.
+      float ar[ND];
+#pragma unroll
+      for (int m = 0; m < ND; ++m) ar[m] = Ar[m];
+#pragma unroll
+      for (int c = 0; c < ND; ++c) {
+        double t = 0.0;
+#pragma unroll
+        for (int m = 0; m <= c; ++m) t += (double)ar[m] * Lik[tri(c, m)];
+        Ar[c] = (float)t;
+      }
+    }
+  }
+  double ev = 0.0, cv = 0.0;
+  if (lane < ND) {
+    double g = (double)qg[lane];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) g += (double)Jt[c][lane] * (double)We[c] * (double)pe[c];
+    tq[lane] = g;
+#pragma unroll
+    for (int m = 0; m < ND; ++m) {
+      if (m >= lane) {
+        if (succ) ev += L1[tri(m, lane)] * (double)e[m];
+        if (first) cv += Lk[tri(m, lane)] * (double)c0[m];
+      }
+    }
+  }
+  wave_sync();
+  if (lane < ND) {
+    double qh = 0.0;
+#pragma unroll
+    for (int m = 0; m < ND; ++m)
+      if (m <= lane) qh += Lik[tri(lane, m)] * tq[m];
+    qg[lane] = (float)qh;
+    if (succ) e[lane] = (float)ev;
+    if (first) c0[lane] = (float)cv;
+  }
+  wave_sync();
+}
+
+// The multipliers of a knot between the two sets of variables (joint rows,
+// lane `lane` holding row `lane`): lambda^ = T_k^T lambda (to y, forward) and
+// lambda = T_k^-T lambda^ (back). tq: the knot's LDS exchange row.
+template <int ND>
+__device__ __forceinline__ double tip_lambda(int lane, bool forward, const double *Lk, const double *Lik, double *tq,
+                                             double lam) {
+  if (lane < ND) tq[lane] = lam;
+  wave_sync();
+  double t = lam;
+  if (lane < ND) {
+    t = 0.0;
+#pragma unroll
+    for (int m = 0; m < ND; ++m)
+      if (m <= lane) t += (forward ? Lik[tri(lane, m)] : Lk[tri(lane, m)]) * tq[m];
+  }
+  wave_sync();
+  return t;
+}
+
 // ---- Split long solves, part-local form. A solve of N > 64 knots (6-7 DoF)
 // runs on four workgroups (parts); part j owns knots kf = 32 j .. kl (at most
 // 32, possibly none) and runs the one-knot-per-lane-group layout of a short
@@ -401,7 +565,30 @@ struct PartSmem {
   float B[KH][NX * NU];
 };
 
+// LDS of the task-space part-local form, placed after PartSmem: the factors
+// L_k, L_k^-1 and tip data of the own knots and both halos (the left halo's
+// rewritten A, e and q and the last own knot's rewritten A need them).
 template <int ND>
+struct PartTsSmem {
+  static constexpr int KH = Shape<ND>::SLOTS + 2, NL = Shape<ND>::NL;
+  double Lc[KH][NL];
+  double Li[KH][NL];
+  double tq[KH][8];
+  double mt[KH];
+  float Jt[KH][3][8];
+  float pr[KH][4];
+  float pe[KH][4];
+};
+template <int ND>
+constexpr size_t part_ts_offset() {
+  return (sizeof(PartSmem<ND>) + 15) & ~(size_t)15;
+}
+template <int ND, bool TS>
+constexpr size_t part_smem_bytes() {
+  return TS ? part_ts_offset<ND>() + sizeof(PartTsSmem<ND>) : sizeof(PartSmem<ND>);
+}
+
+template <int ND, bool TS>
 __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs &a, int sid, int part,
                                                                      char *smem_raw) {
   using Sh = Shape<ND>;
@@ -410,6 +597,8 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
   static_assert(G == 16, "the part-local split serves 6-7 DoF");
   using SM = PartSmem<ND>;
   SM &sm = *reinterpret_cast<SM *>(smem_raw);
+  // Only dereferenced by the task-space form, whose LDS holds it.
+  PartTsSmem<ND> &ts = *reinterpret_cast<PartTsSmem<ND> *>(smem_raw + part_ts_offset<ND>());
   const SolveDesc &D = a.desc[sid];
   const Chain &ch = D.chain;
   const int tid = threadIdx.x;
@@ -448,6 +637,14 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
     sm.xs[tid] = in ? a.xs[(size_t)sid * a.nx_max + tid] : 0.f;
     sm.xg[tid] = (in && tid < ND) ? a.goal[(size_t)sid * a.nu_max + tid] : 0.f;
   }
+  if constexpr (TS) {
+    // Reference tip positions of the own and halo knots (not shifted).
+    for (int t = tid; t < (nloc + 2) * 4; t += kBlock) {
+      const int li = t / 4, c = t % 4, k = kof(li);
+      const bool in = k >= 0 && k < N && c < 3 && nloc > 0;
+      ts.pr[li][c] = in ? a.pref[((size_t)sid * a.N_max + k) * 3 + c] : 0.f;
+    }
+  }
   if (tid == 0) {
     sm.bad[0] = 0;
     sm.bad[1] = 0;
@@ -477,8 +674,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
     const bool own = slot < nloc;
     if (!a.warm && it > 0) lam = (Real)0;
     if (tid < G) {
-      sm.Qi[tid] = tid < NX ? 1.0 / (D.Qd[tid] + rho) : 0.0;
-      sm.Qni[tid] = tid < NX ? 1.0 / (D.QNd[tid] + rho) : 0.0;
+      // (Task-space form: the joint block of the rewritten Q_k is the identity.)
+      const bool unit = TS && tid < ND;
+      sm.Qi[tid] = tid < NX ? (unit ? 1.0 : 1.0 / (D.Qd[tid] + rho)) : 0.0;
+      sm.Qni[tid] = tid < NX ? (unit ? 1.0 : 1.0 / (D.QNd[tid] + rho)) : 0.0;
     }
     int &bad_flag = sm.bad[it & 1];
     unsigned long long *clk = (a.clk && tid == 0 && writer) ? a.clk + ((size_t)sid * a.iters + it) * 8 : nullptr;
@@ -589,8 +788,35 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
       }
       sm.xmp[n_alpha] = x0;
     }
+    if constexpr (TS) {
+      // The tip terms and the factors L_k, L_k^-1 of the own knots and both halos.
+      const int lt0 = kf > 0 ? 0 : 1, lt1 = has_r ? nloc + 1 : nloc;
+      const int nt = nloc > 0 ? lt1 - lt0 + 1 : 0;
+      for (int t = slot; t < nt; t += SLOTS) {
+        const int lg = lt0 + t, kk = kof(lg);
+        tip_factor<ND>(ch, sm.X[lg], ts.pr[lg], (kk < N - 1) ? D.We : D.WeN, (kk < N - 1) ? D.Qd : D.QNd, rho,
+                       lane, ts.Jt[lg], ts.pe[lg], &ts.mt[lg], ts.tq[lg], ts.Lc[lg], ts.Li[lg], bad_flag);
+      }
+    }
     __syncthreads();
     if (tid == 0) sm.bad[(it + 1) & 1] = 0;
+    if constexpr (TS) {
+      // Tip costs of the own knots into the merit terms; the QP data of the
+      // own knots and the left halo rewritten in y_k = T_k^-1 x_k; then the
+      // own warm-start multipliers (lambda^ = T_k^T lambda).
+      const int nc = (nloc > 0) ? min(kl, N - 2) - kf + 1 : 0;   // own knots with a control
+      for (int t = tid; t < nc; t += kBlock) sm.mp0[1 + t] += ts.mt[1 + t];
+      if (tid == 0 && nloc > 0 && kl == N - 1) sm.xmp[n_alpha] += ts.mt[nloc];
+      const int nr = nloc > 0 ? nloc + 1 - lq0 : 0;
+      for (int t = slot; t < nr; t += SLOTS) {
+        const int lg = lq0 + t, kk = kof(lg);
+        const bool succ = kk < N - 1;
+        tip_rewrite<ND>(lane, succ, kk == 0, h, ts.Lc[lg], ts.Li[lg], ts.Lc[succ ? lg + 1 : lg], sm.A[lg] + lane * NX,
+                        sm.e[lg], sm.qg[lg], sm.c0, ts.Jt[lg], ts.pe[lg], succ ? D.We : D.WeN, ts.tq[lg]);
+      }
+      __syncthreads();
+      if (own) lam = tip_lambda<ND>(lane, true, ts.Lc[li], ts.Li[li], ts.tq[li], lam);
+    }
     if (clk) clk[1] = wall_clock64();
 
     // ================= 2. Schur rows and diagonal-block inverses of the own knots.
@@ -877,6 +1103,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
       const float dx = (float)(-qk * sx);
       sm.dX[lg][lane] = dx;
       if (!isfinite(dx)) bad_flag = 1;
+      if constexpr (TS) {
+        if (lane < ND) ts.tq[lg][lane] = (double)(-qk * sx);
+      }
       if (lane < NU && kk < N - 1) {
         const float *B = sm.B[lg];
         Real su = (Real)sm.rg[lg][lane];
@@ -889,6 +1118,30 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
     };
     if (own && lane < NX) step_at(li, k, lam, qown);
     if (has_l && slot == 0 && lane < NX) step_at(0, kf - 1, sm.pv[0][lane], (Real)sm.Qi[lane]);
+    if constexpr (TS) {
+      // Back to x: dx_k = T_k dy_k (joint rows L_k^-T dy) at the own knots and
+      // the left halo, and lambda = T_k^-T lambda^ at the own knots.
+      auto to_x = [&](int lg) {
+        wave_sync();
+        double t = 0.0;
+        if (lane < ND) {
+#pragma unroll
+          for (int m = 0; m < ND; ++m)
+            if (m >= lane) t += ts.Li[lg][tri(m, lane)] * ts.tq[lg][m];
+        }
+        wave_sync();
+        if (lane < ND) {
+          const float dx = (float)t;
+          sm.dX[lg][lane] = dx;
+          if (!isfinite(dx)) bad_flag = 1;
+        }
+      };
+      if (own) {
+        to_x(li);
+        lam = tip_lambda<ND>(lane, false, ts.Lc[li], ts.Li[li], ts.tq[li], lam);
+      }
+      if (has_l && slot == 0) to_x(0);
+    }
     __syncthreads();
     if (own && slot == 0) put_row((double)sm.dX[1][lane], 0.0);
     {
@@ -928,6 +1181,15 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
         const float d0 = q[j] - sm.xg[j], d1 = qd[j] - sm.xg[ND + j];
         cost += 0.5f * D.Wq[j] * d0 * d0 + 0.5f * D.Wq[ND + j] * d1 * d1 + 0.5f * D.Wr[j] * uu[j] * uu[j];
       }
+      if constexpr (TS) {
+        float pt[3];
+        tip_position<ND>(ch, q, pt);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float d = pt[c] - ts.pr[lg][c];
+          cost += 0.5f * D.We[c] * d * d;
+        }
+      }
       sm.mp[i][lg] = (double)cost + (double)a.mu * (double)viol;
     }
     for (int i = tid; i < n_alpha; i += kBlock) {
@@ -938,6 +1200,17 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
         for (int j = 0; j < NX; ++j) {
           const float d = (sm.X[nloc][j] + al * sm.dX[nloc][j]) - sm.xg[j];
           cost += 0.5f * D.Wn[j] * d * d;
+        }
+        if constexpr (TS) {
+          float q[ND], pt[3];
+#pragma unroll
+          for (int j = 0; j < ND; ++j) q[j] = sm.X[nloc][j] + al * sm.dX[nloc][j];
+          tip_position<ND>(ch, q, pt);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float d = pt[c] - ts.pr[nloc][c];
+            cost += 0.5f * D.WeN[c] * d * d;
+          }
         }
         x0 += (double)cost;
       }
@@ -1066,7 +1339,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
   if constexpr (kSplitOk && sizeof(Real) == 8) {
     static_assert(sizeof(PartSmem<ND>) <= smem_bytes<ND, KPT, Real, TS>(), "LDS of a part");
     if (split && a.split == 4 && !a.by_block) {
-      sqp_solve_part<ND>(a, sid, part, smem_raw);
+      sqp_solve_part<ND, false>(a, sid, part, smem_raw);
       return;
     }
   }
@@ -1278,80 +1551,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         sm.mp0[N - 1] = (double)cost + (double)a.mu * (double)viol;
       }
       if constexpr (TS) {
-        // Tip position and Jacobian at every knot (lane j: one dual-number pass
-        // seeded on q_j), then H_k = diag(Q_q + rho) + J^T W J, its Cholesky
-        // factor L_k (column by column, lane i holding row i) and L_k^-1
-        // (lane j forming column j by forward substitution).
-        for (int k = slot; k < N; k += SLOTS) {
-          const float *We = (k < N - 1) ? D.We : D.WeN;
-          const double *Qd = (k < N - 1) ? D.Qd : D.QNd;
-          if (lane < ND) {
-            dual<float> qv[ND], pt[3];
-#pragma unroll
-            for (int i = 0; i < ND; ++i) qv[i] = dual<float>{sm.X[k][i], i == lane ? 1.f : 0.f};
-            tip_position<ND>(ch, qv, pt);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ts.Jt[k][c][lane] = pt[c].d;
-            if (lane == 0) {
-              double tc = 0.0;
-#pragma unroll
-              for (int c = 0; c < 3; ++c) {
-                const float d = pt[c].v - ts.pr[k][c];
-                ts.pe[k][c] = d;
-                tc += 0.5 * (double)We[c] * (double)d * (double)d;
-              }
-              ts.mt[k] = tc;
-              if (!isfinite(tc)) bad_flag = 1;
-            }
-          }
-          wave_sync();
-          double hr[ND], lr[ND];
-#pragma unroll
-          for (int j = 0; j < ND; ++j) {
-            double t = (j == lane) ? Qd[j] + rho : 0.0;
-            if (lane < ND) {
-#pragma unroll
-              for (int c = 0; c < 3; ++c) t += (double)We[c] * (double)ts.Jt[k][c][lane] * (double)ts.Jt[k][c][j];
-            }
-            hr[j] = t;
-            lr[j] = 0.0;
-          }
-#pragma unroll
-          for (int c = 0; c < ND; ++c) {
-            if (lane == c) ts.tq[k][0] = hr[c];
-            wave_sync();
-            const double piv = ts.tq[k][0];
-            wave_sync();
-            if (lane == 0 && !(piv > 0.0)) bad_flag = 1;
-            const double dinv = 1.0 / sqrt(piv);
-            const double l = (lane >= c && lane < ND) ? hr[c] * dinv : 0.0;   // L[lane][c]
-            lr[c] = l;
-            if (lane < ND) ts.tq[k][lane] = l;
-            wave_sync();
-#pragma unroll
-            for (int j = c + 1; j < ND; ++j) hr[j] -= l * ts.tq[k][j];
-            wave_sync();
-          }
-          if (lane < ND) {
-#pragma unroll
-            for (int j = 0; j < ND; ++j)
-              if (j <= lane) ts.Lc[k][tri(lane, j)] = lr[j];
-          }
-          wave_sync();
-          if (lane < ND) {
-            // Column `lane` of L^-1: rows lane..ND-1 of the solution of L x = e_lane.
-            double x[ND];
-#pragma unroll
-            for (int i = 0; i < ND; ++i) {
-              double t = (i == lane) ? 1.0 : 0.0;
-#pragma unroll
-              for (int m = 0; m < i; ++m)
-                if (m >= lane) t -= ts.Lc[k][tri(i, m)] * x[m];
-              x[i] = (i >= lane) ? t / ts.Lc[k][tri(i, i)] : 0.0;
-              if (i >= lane) ts.Li[k][tri(i, lane)] = x[i];
-            }
-          }
-        }
+        // The tip terms and the factors L_k, L_k^-1 of every knot.
+        for (int k = slot; k < N; k += SLOTS)
+          tip_factor<ND>(ch, sm.X[k], ts.pr[k], (k < N - 1) ? D.We : D.WeN, (k < N - 1) ? D.Qd : D.QNd, rho, lane,
+                         ts.Jt[k], ts.pe[k], &ts.mt[k], ts.tq[k], ts.Lc[k], ts.Li[k], bad_flag);
       }
       if (a.mode == kModeLq) {
         __syncthreads();
@@ -1402,79 +1605,16 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     if (tid == 0) sm.bad[(it + 1) & 1] = 0;
     if constexpr (TS) {
       for (int t = tid; t < N; t += kBlock) sm.mp0[t] += ts.mt[t];
-      // Rewrite the QP in y_k = T_k^-1 x_k, lane `lane` owning state row `lane`.
-      // The joint rows of A_k are [I, hI] by construction of the Euler step.
+      // Rewrite the QP in y_k = T_k^-1 x_k, and the warm-start multipliers
+      // (lambda^ = T_k^T lambda).
 #pragma unroll
       for (int p = 0; p < KPT; ++p) {
         const int k = slot + p * SLOTS;
         if (k < N) {
-          const double *Lk = ts.Lc[k];
-          const double *Lik = ts.Li[k];
-          const double *L1 = ts.Lc[k < N - 1 ? k + 1 : k];
-          if (k < N - 1 && lane < NX) {
-            float *Ar = Ablk(k) + lane * NX;
-            if (lane < ND) {
-              // Row `lane` of [L_{k+1}^T L_k^-T, h L_{k+1}^T].
-#pragma unroll
-              for (int c = 0; c < ND; ++c) {
-                double t = 0.0;
-#pragma unroll
-                for (int m = 0; m <= c; ++m)
-                  if (m >= lane) t += L1[tri(m, lane)] * Lik[tri(c, m)];
-                Ar[c] = (float)t;
-                Ar[ND + c] = c >= lane ? (float)((double)h * L1[tri(c, lane)]) : 0.f;
-              }
-            } else {
-              // Velocity row: its joint columns times L_k^-T.
-              float ar[ND];
-#pragma unroll
-              for (int m = 0; m < ND; ++m) ar[m] = Ar[m];
-#pragma unroll
-              for (int c = 0; c < ND; ++c) {
-                double t = 0.0;
-#pragma unroll
-                for (int m = 0; m <= c; ++m) t += (double)ar[m] * Lik[tri(c, m)];
-                Ar[c] = (float)t;
-              }
-            }
-          }
-          double ev = 0.0, cv = 0.0;
-          if (lane < ND) {
-            const float *We = (k < N - 1) ? D.We : D.WeN;
-            double g = (double)sm.qg[k][lane];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) g += (double)ts.Jt[k][c][lane] * (double)We[c] * (double)ts.pe[k][c];
-            ts.tq[k][lane] = g;
-#pragma unroll
-            for (int m = 0; m < ND; ++m) {
-              if (m >= lane) {
-                if (k < N - 1) ev += L1[tri(m, lane)] * (double)sm.e[k][m];
-                if (k == 0) cv += Lk[tri(m, lane)] * (double)sm.c0[m];
-              }
-            }
-          }
-          wave_sync();
-          if (lane < ND) {
-            double qh = 0.0;
-#pragma unroll
-            for (int m = 0; m < ND; ++m)
-              if (m <= lane) qh += Lik[tri(lane, m)] * ts.tq[k][m];
-            sm.qg[k][lane] = (float)qh;
-            if (k < N - 1) sm.e[k][lane] = (float)ev;
-            if (k == 0) sm.c0[lane] = (float)cv;
-          }
-          wave_sync();
-          // Warm-start multipliers: lambda^ = T_k^T lambda.
-          if (lane < ND) ts.tq[k][lane] = (double)lam[p];
-          wave_sync();
-          if (lane < ND) {
-            double t = 0.0;
-#pragma unroll
-            for (int m = 0; m < ND; ++m)
-              if (m <= lane) t += Lik[tri(lane, m)] * ts.tq[k][m];
-            lam[p] = (Real)t;
-          }
-          wave_sync();
+          const bool succ = k < N - 1;
+          tip_rewrite<ND>(lane, succ, k == 0, h, ts.Lc[k], ts.Li[k], ts.Lc[succ ? k + 1 : k], Ablk(k) + lane * NX,
+                          sm.e[k], sm.qg[k], sm.c0, ts.Jt[k], ts.pe[k], succ ? D.We : D.WeN, ts.tq[k]);
+          lam[p] = (Real)tip_lambda<ND>(lane, true, ts.Lc[k], ts.Li[k], ts.tq[k], (double)lam[p]);
         }
       }
       __syncthreads();
@@ -2441,17 +2581,24 @@ __global__ __launch_bounds__(kBlock) void sqp_kernel(KArgs a) {
 // The LDS footprint is the largest specialisation's; every specialisation
 // already runs one workgroup per CU, so occupancy is unchanged. (For 3 DoF,
 // two knots per 8-lane group already cover the maximum horizon; the
-// task-space variant is compiled for one and two knots per group.)
+// task-space variant is compiled for one and two knots per group, and its
+// long solves (6-7 DoF, N > 64) run only split, in the part-local form.)
 template <class Real, bool TS>
 constexpr size_t mixed_smem_bytes() {
   size_t m = 0;
   const size_t s[] = {smem_bytes<3, 1, Real, TS>(), smem_bytes<3, 2, Real, TS>(),
                       smem_bytes<6, 1, Real, TS>(), smem_bytes<6, 2, Real, TS>(),
-                      TS ? 0 : smem_bytes<6, 4, Real, false>(),
+                      TS ? part_smem_bytes<6, true>() : smem_bytes<6, 4, Real, false>(),
                       smem_bytes<7, 1, Real, TS>(), smem_bytes<7, 2, Real, TS>(),
-                      TS ? 0 : smem_bytes<7, 4, Real, false>()};
+                      TS ? part_smem_bytes<7, true>() : smem_bytes<7, 4, Real, false>()};
   for (size_t v : s) m = v > m ? v : m;
   return m;
+}
+
+// A long task-space solve runs only as the four parts of a split SQP launch
+// in FP64 (the host builds no other launch of one).
+__device__ __forceinline__ bool task_split_ok(const KArgs &a, const SolveDesc &D, int part) {
+  return a.split == kXParts && a.mode == kModeSqp && !a.by_block && D.xch_off >= 0 && part >= 0 && part < kXParts;
 }
 
 template <class Real, bool TS = false, bool SPLIT = false>
@@ -2477,9 +2624,15 @@ __global__ __launch_bounds__(kBlock) void sqp_mixed_kernel(KArgs a) {
     case 7 * 8 + 2: sqp_solve<7, 2, Real, TS>(a, sid, part, smem); break;
     case 6 * 8 + 4:
       if constexpr (!TS) sqp_solve<6, 4, Real, false, SPLIT>(a, sid, part, smem);
+      else if constexpr (SPLIT && sizeof(Real) == 8) {
+        if (task_split_ok(a, D, part)) sqp_solve_part<6, true>(a, sid, part, smem);
+      }
       break;
     case 7 * 8 + 4:
       if constexpr (!TS) sqp_solve<7, 4, Real, false, SPLIT>(a, sid, part, smem);
+      else if constexpr (SPLIT && sizeof(Real) == 8) {
+        if (task_split_ok(a, D, part)) sqp_solve_part<7, true>(a, sid, part, smem);
+      }
       break;
     default: break;  // the host only builds the shapes above
   }

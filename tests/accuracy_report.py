@@ -16,7 +16,9 @@ A report, not a test (pytest does not collect it): run it on an MI355X as
 * the closed-loop batch: sampled ticks replayed in the oracle from the same
   plant state and warm start, and the oracle's own closed loop for 150 ticks;
 * the task-space (figure-8) launch: sampled trajectories and, step by step,
-  each GPU step against the exact step of the GPU's own iterate.
+  each GPU step against the exact step of the GPU's own iterate;
+* the uneven batch with figure-8 tracking (long solves split): per (DoF, N)
+  bucket, the same step-by-step errors.
 
 The benchmark itself never runs the oracle (apart from its CPU-throughput
 leg); these are the figures quoted beside its numbers.
@@ -196,6 +198,56 @@ def task_space(g, torch, M=256, iters=10, idx=(0, 128, 255)):
     return traj
 
 
+def task_uneven(g, torch, M=128, iters=10, seed=0, per_bucket=2):
+    """The uneven batch with figure-8 tip tracking (its long solves split,
+    part-local), step by step from the GPU's own iterates with cold PCG starts
+    on both sides, as for the task-space launch: per (DoF, N) bucket, the
+    largest error of a GPU step of `per_bucket` sampled solves against the
+    exact step of the same iterate, beside the FP64 method's own error (its
+    PCG at the same tolerance)."""
+    solves = w.figure8_uneven_batch(seed, M=M)
+    buckets = {}
+    for i, s in enumerate(solves):
+        buckets.setdefault((s.n, s.N), []).append(i)
+    idx = sorted(i for v in buckets.values() for i in v[:per_bucket])
+    p1 = g.Params(sqp_iters=iters, pcg_tol=1e-5, pcg_max_iter=1000, warm_lambda=0)
+    b = g.Batch.from_solves(solves, p1)
+    xs, goal, X, U = g.pack_inputs(solves)
+    st_buf = b.stats_buffer(1)
+    err = {i: [0.0, 0.0] for i in idx}
+    bits = 0
+    oracle.lib()
+    for it in range(iters):
+        x0, u0 = X.cpu().numpy().astype(np.float64), U.cpu().numpy().astype(np.float64)
+        b.step(xs, goal, X, U, 1, st_buf)
+        torch.cuda.synchronize()
+        st = g.Batch.decode_stats(st_buf, M, 1)[:, 0]
+        bits += int((st["status"] & (g.ST_NONFINITE | g.ST_EXCHANGE | g.ST_PCG_MAXITER) != 0).sum())
+        x1, u1 = X.cpu().numpy().astype(np.float64), U.cpu().numpy().astype(np.float64)
+
+        def one(i):
+            s, al = solves[i], float(st[i]["alpha"])
+            n, N = s.n, s.N
+            xa, ua, xb, ub = x0[i, :N, :2 * n], u0[i, :N - 1, :n], x1[i, :N, :2 * n], u1[i, :N - 1, :n]
+            dXe, dUe, _, _, _ = oracle.qp_step(s, xa, ua, mode=2)
+            dXm, dUm, _, _, _ = oracle.qp_step(s, xa, ua, mode=1, pcg_tol=1e-5, pcg_max_iter=8000)
+            sx, su = np.abs(xa + al * dXe).max(), np.abs(ua + al * dUe).max()
+            e = max(np.abs(xb - (xa + al * dXe)).max() / sx, np.abs(ub - (ua + al * dUe)).max() / su)
+            e_m = al * max(np.abs(dXm - dXe).max() / sx, np.abs(dUm - dUe).max() / su)
+            return i, e, e_m
+
+        with ThreadPoolExecutor(16) as ex:
+            for i, e, e_m in ex.map(one, idx):
+                err[i][0] = max(err[i][0], e)
+                err[i][1] = max(err[i][1], e_m)
+    b.close()
+    out = {f"{n}x{N}": dict(step_vs_exact=float(max(err[i][0] for i in v[:per_bucket])),
+                            method_step_vs_exact=float(max(err[i][1] for i in v[:per_bucket])), count=len(v))
+           for (n, N), v in sorted(buckets.items())}
+    out["failure_bits_set"] = bits
+    return out
+
+
 def uneven(g, torch, M=128, seed=0, per_bucket=2):
     """The uneven batch of the benchmark (one mixed-shape launch, long solves
     split) in each of its precision settings: per (DoF, N) bucket, the largest
@@ -266,6 +318,8 @@ def main():
     print("# closed loop", out["closed_loop"], file=sys.stderr, flush=True)
     out["task_space"] = task_space(g, torch)
     print("# task space", out["task_space"], file=sys.stderr, flush=True)
+    out["task_uneven"] = task_uneven(g, torch)
+    print("# task uneven", out["task_uneven"], file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

@@ -148,6 +148,14 @@ def figure8_batch(seed: int, M: int, n: int = 7, N: int = 32, dt: float = DEFAUL
     return [figure8_solve(seed, i, n=n, N=N, dt=dt) for i in range(M)]
 
 
+def figure8_uneven_batch(seed: int, M: int = 128, dofs=(3, 6, 7), horizons=(16, 32, 64, 128),
+                         dt: float = DEFAULT_DT) -> list[Solve]:
+    """The DoF and horizons of :func:`uneven_batch` (the same draws), every
+    solve tracking a figure-8 with the tip as in :func:`figure8_solve`."""
+    return [figure8_solve(seed, i, n=s.n, N=s.N, dt=dt)
+            for i, s in enumerate(uneven_batch(seed, M=M, dofs=dofs, horizons=horizons, dt=dt))]
+
+
 def double_integrator_solve(seed: int, i: int, n: int = 3, N: int = 8, dt: float = 0.05,
                             spring_k: float = 1.0) -> Solve:
     """A linear chain of unit masses coupled by springs (q'' = u - k T q).
