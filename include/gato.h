@@ -90,10 +90,11 @@ typedef struct {
  * of this term, so each Q_k gets a dense joint block. Serial chains only; a
  * batch with such a term runs the task-space kernels for all its solves (no
  * stage entry points). Its long solves (6-7 DoF, N > 64) run only on four
- * workgroups each (see gato_set_split), which needs schur_fp64 = 1 and the
- * whole batch (one workgroup per short solve, four per long one) resident on
- * the device at once (otherwise gato_batch_create returns GATO_EUNSUPPORTED);
- * such a batch takes no serving steps. Both NULL: no such term
+ * workgroups each (see gato_set_split), which needs schur_fp64 = 1 (otherwise
+ * gato_batch_create returns GATO_EUNSUPPORTED); a step of such a batch is one
+ * cooperative launch per range of whole solves that fits the device (one
+ * workgroup per short solve, four per long one), and the batch takes no
+ * serving steps. Both NULL: no such term
  * (zero-initialise the struct).
  */
 typedef struct {

@@ -131,6 +131,10 @@ struct gato_batch {
   unsigned epoch = 0;            // tag epoch of the last split launch (1..65535)
   int *d_order_split_all[2] = {nullptr, nullptr};   // four / two blocks per split solve
   int grid_split_all[2] = {0, 0};
+  // Batches with long task-space solves: consecutive ranges (offset, length)
+  // of the four-part order, each made of whole solves and resident on the
+  // device at once; one cooperative launch per range.
+  std::vector<std::pair<int, int>> task_chunks;
   int dispatch = GATO_DISPATCH_AUTO;
   std::vector<float> tuned_ms;  // per solve: the tuned time of its bucket (0 if never tuned)
   // Captured step (gato_step_graph).
@@ -201,12 +205,34 @@ static int rebuild_dispatch(gato_batch *b) {
   std::stable_sort(all.begin(), all.end(), longer);
   e = hipMemcpy(b->d_order_all, all.data(), M * sizeof(int), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpy(order)");
+  b->task_chunks.clear();
   if (b->n_split > 0) {
     for (int q = 0; q < 2; ++q) {
       const std::vector<int> xall = expand(all, q == 0 ? 4 : 2);
       e = upload(xall, &b->d_order_split_all[q]);
       if (e != hipSuccess) return hip_fail(e, "split order");
       b->grid_split_all[q] = (int)xall.size();
+      if (q == 0 && b->task_long) {
+        // The largest prefixes of whole solves that fit the device at once.
+        int cap = 0;
+        e = gato::cooperative_capacity(gato::sqp_mixed_task_split_fn(), &cap);
+        if (e != hipSuccess) return hip_fail(e, "occupancy query");
+        if (cap < gato::kSplitParts) return fail(GATO_EUNSUPPORTED, "the four parts of a long solve do not fit the device");
+        int start = 0, len = 0;
+        for (size_t t = 0; t < xall.size();) {
+          const bool parts = ((unsigned)xall[t] >> 24) == 0 && desc[xall[t] & 0xffffff].xch_off >= 0 &&
+                             desc[xall[t] & 0xffffff].kpt == 4;
+          const int w = parts ? gato::kSplitParts : 1;   // a solve's consecutive entries
+          if (len + w > cap) {
+            b->task_chunks.push_back({start, len});
+            start += len;
+            len = 0;
+          }
+          len += w;
+          t += w;
+        }
+        if (len > 0) b->task_chunks.push_back({start, len});
+      }
     }
   }
   std::vector<std::vector<int>> members(64);
@@ -373,9 +399,7 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
 
   bool task = false, task_long = false;
   for (const auto &d : desc) task = task || d.task;
-  int n_long = 0;
   for (int i = 0; i < M; ++i) {
-    if (desc[i].kpt == 4) ++n_long;
     if (!task || desc[i].kpt <= gato::kTaskKptMax) continue;
     // Long solves of a batch with tip tracking run only as four parts of a
     // split launch (the part-local form is FP64).
@@ -383,16 +407,6 @@ int gato_batch_create(int M, const gato_robot *robots, const gato_problem *probs
       return fail(GATO_EUNSUPPORTED, "solve " + std::to_string(i) +
                                          ": batches with tip tracking take N > 64 (6-7 DoF) with schur_fp64 = 1 only");
     task_long = true;
-  }
-  if (task_long) {
-    // All workgroups of that launch (one per short solve, four per long one)
-    // must be resident together.
-    const hipError_t e0 = gato::cooperative_fits(gato::sqp_mixed_task_split_fn(), M + (gato::kSplitParts - 1) * n_long);
-    if (e0 == hipErrorCooperativeLaunchTooLarge)
-      return fail(GATO_EUNSUPPORTED, "a batch with tip tracking and long solves must fit the device at once: " +
-                                         std::to_string(M + (gato::kSplitParts - 1) * n_long) +
-                                         " workgroups (one per short solve, four per long one) do not");
-    if (e0 != hipSuccess) return hip_fail(e0, "occupancy query");
   }
   gato_batch *b = new gato_batch();
   b->M = M;
@@ -583,10 +597,13 @@ int launch_groups(gato_batch *b, gato::KArgs a, hipStream_t s, bool allow_split 
     if (!split)
       return fail(GATO_EUNSUPPORTED, "long solves with tip tracking run only split: not under stream capture "
                                      "(gato_step_graph builds the split launch)");
+    // One cooperative launch per range of whole solves that fits the device.
     as.split = gato::kSplitParts;
-    as.order = b->d_order_split_all[0];
-    const hipError_t e = gato::launch_sqp_mixed_task_split(b->grid_split_all[0], as, s);
-    if (e != hipSuccess) return hip_fail(e, "kernel launch (split)");
+    for (const auto &c : b->task_chunks) {
+      as.order = b->d_order_split_all[0] + c.first;
+      const hipError_t e = gato::launch_sqp_mixed_task_split(c.second, as, s);
+      if (e != hipSuccess) return hip_fail(e, "kernel launch (split)");
+    }
     return GATO_OK;
   }
   if (use_mixed(b)) {
@@ -1364,10 +1381,11 @@ namespace {
 
 // The step of a mixed-shape batch with split long solves as an explicit graph:
 // a kernel node that clears the exchange words, then the split kernel as a
-// cooperative kernel node (its workgroups resident together). *out stays null
-// when the split does not apply (the launch does not fit the device, or the
-// runtime refuses the cooperative attribute); the caller then captures the
-// one-workgroup form.
+// cooperative kernel node (its workgroups resident together), or, for long
+// task-space solves, one such node per range of whole solves that fits the
+// device, in sequence. *out stays null when the split does not apply (the
+// launch does not fit the device, or the runtime refuses the cooperative
+// attribute); the caller then captures the one-workgroup form.
 int build_split_graph(gato_batch *b, const gato::KArgs &a, hipGraph_t *out) {
   *out = nullptr;
   if (b->split_parts != gato::kSplitParts || b->n_split == 0) return GATO_OK;
@@ -1377,17 +1395,22 @@ int build_split_graph(gato_batch *b, const gato::KArgs &a, hipGraph_t *out) {
   for (int q = 0; q < (b->task ? 1 : 2); ++q) {
     const int grid = b->grid_split_all[q];
     if (grid <= b->M) continue;
-    hipError_t e = gato::cooperative_fits(fn, grid);
-    if (e == hipErrorCooperativeLaunchTooLarge) continue;
-    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    std::vector<std::pair<int, int>> ranges;
+    if (b->task) {
+      ranges = b->task_chunks;
+    } else {
+      const hipError_t e = gato::cooperative_fits(fn, grid);
+      if (e == hipErrorCooperativeLaunchTooLarge) continue;
+      if (e != hipSuccess) return hip_fail(e, "occupancy query");
+      ranges.push_back({0, grid});
+    }
     gato::KArgs as = a;
     as.split = q == 0 ? 4 : 2;
-    as.order = b->d_order_split_all[q];
     as.epoch = gato::kGraphEpoch;
     as.xch = b->d_xch;
     as.xspin = b->split_polls;
     hipGraph_t g = nullptr;
-    e = hipGraphCreate(&g, 0);
+    hipError_t e = hipGraphCreate(&g, 0);
     if (e != hipSuccess) return hip_fail(e, "hipGraphCreate");
     double *fp = reinterpret_cast<double *>(b->d_xch);
     size_t fn_words = b->xwords;
@@ -1399,26 +1422,36 @@ int build_split_graph(gato_batch *b, const gato::KArgs &a, hipGraph_t *out) {
     fparams.gridDim = dim3((unsigned)((fn_words + 255) / 256));
     fparams.blockDim = dim3(256);
     fparams.kernelParams = fargs;
-    hipGraphNode_t n_fill = nullptr, n_sqp = nullptr;
-    e = hipGraphAddKernelNode(&n_fill, g, nullptr, 0, &fparams);
-    void *kargs[] = {&as};
-    hipKernelNodeParams kparams;
-    std::memset(&kparams, 0, sizeof(kparams));
-    kparams.func = const_cast<void *>(fn);
-    kparams.gridDim = dim3(grid);
-    kparams.blockDim = dim3(gato::kBlock);
-    kparams.kernelParams = kargs;
-    if (e == hipSuccess) e = hipGraphAddKernelNode(&n_sqp, g, &n_fill, 1, &kparams);
+    hipGraphNode_t prev = nullptr;
+    e = hipGraphAddKernelNode(&prev, g, nullptr, 0, &fparams);
+    bool refused = false;
+    for (size_t r = 0; e == hipSuccess && r < ranges.size(); ++r) {
+      as.order = b->d_order_split_all[q] + ranges[r].first;
+      void *kargs[] = {&as};   // (the node copies its arguments when it is added)
+      hipKernelNodeParams kparams;
+      std::memset(&kparams, 0, sizeof(kparams));
+      kparams.func = const_cast<void *>(fn);
+      kparams.gridDim = dim3(ranges[r].second);
+      kparams.blockDim = dim3(gato::kBlock);
+      kparams.kernelParams = kargs;
+      hipGraphNode_t n_sqp = nullptr;
+      e = hipGraphAddKernelNode(&n_sqp, g, &prev, 1, &kparams);
+      if (e != hipSuccess) break;
+      hipLaunchAttributeValue coop;
+      std::memset(&coop, 0, sizeof(coop));
+      coop.cooperative = 1;
+      if (hipGraphKernelNodeSetAttribute(n_sqp, hipKernelNodeAttributeCooperative, &coop) != hipSuccess) {
+        (void)hipGetLastError();
+        refused = true;
+        break;
+      }
+      prev = n_sqp;
+    }
     if (e != hipSuccess) {
       (void)hipGraphDestroy(g);
       return hip_fail(e, "hipGraphAddKernelNode");
     }
-    hipLaunchAttributeValue coop;
-    std::memset(&coop, 0, sizeof(coop));
-    coop.cooperative = 1;
-    e = hipGraphKernelNodeSetAttribute(n_sqp, hipKernelNodeAttributeCooperative, &coop);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
+    if (refused) {
       (void)hipGraphDestroy(g);
       if (b->task_long) return fail(GATO_EUNSUPPORTED, "the runtime refuses a cooperative graph node (long solves "
                                                        "with tip tracking run only split)");

@@ -23,18 +23,29 @@ hipError_t launch_sqp_mixed_task_split(int grid, const KArgs &a, hipStream_t s);
 // task-space solves run only split.
 constexpr int kTaskKptMax = 2;
 
-// hipSuccess when `grid` workgroups of kernel f fit the device at once (the
-// condition of a cooperative launch), hipErrorCooperativeLaunchTooLarge when
-// they do not (nothing is launched then).
-inline hipError_t cooperative_fits(const void *f, int grid) {
+// The number of workgroups of kernel f (kBlock threads) that fit the current
+// device at once.
+inline hipError_t cooperative_capacity(const void *f, int *cap) {
   int per_cu = 0, dev = 0, cus = 0;
+  *cap = 0;
   hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0);
   if (e != hipSuccess) return e;
   e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (e != hipSuccess) return e;
-  return (long)per_cu * cus >= grid ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
+  *cap = per_cu * cus;
+  return hipSuccess;
+}
+
+// hipSuccess when `grid` workgroups of kernel f fit the device at once (the
+// condition of a cooperative launch), hipErrorCooperativeLaunchTooLarge when
+// they do not (nothing is launched then).
+inline hipError_t cooperative_fits(const void *f, int grid) {
+  int cap = 0;
+  const hipError_t e = cooperative_capacity(f, &cap);
+  if (e != hipSuccess) return e;
+  return cap >= grid ? hipSuccess : hipErrorCooperativeLaunchTooLarge;
 }
 
 // Launches the closed-loop plant step (RK4, one thread per instance).

@@ -137,10 +137,38 @@ def test_long_task_space_limits_are_reported():
     with pytest.raises(g.GatoError):
         b.serve_step(slots, xs, goal)
     b.close()
-    # More long solves than the device holds at once (four workgroups each).
-    many = [w.figure8_solve(25, i % 2, n=7, N=128) for i in range(70)]
-    with pytest.raises(g.GatoError):
-        g.Batch.from_solves(many)
+
+
+def test_long_task_space_batch_beyond_one_launch_runs_in_ranges():
+    # 70 long solves need 280 workgroups at once, more than the device holds:
+    # the step runs as consecutive cooperative launches of whole solves, eagerly
+    # and as graph nodes. Solves are independent, so every solve's result equals
+    # the same solve's in a batch of four bit for bit, and graph replays equal
+    # the eager launches.
+    _say("task split beyond one launch")
+    distinct = [w.figure8_solve(25, i, n=7, N=128) for i in range(4)]
+    many = [w.figure8_solve(25, i % 4, n=7, N=128) for i in range(70)]
+    p = g.Params(sqp_iters=2, pcg_tol=1e-7, pcg_max_iter=8000)
+
+    def run(solves, graph):
+        b = g.Batch.from_solves(solves, p)
+        xs, goal, X, U = g.pack_inputs(solves)
+        st = b.stats_buffer(p.sqp_iters)
+        b.reset_warm_start()
+        b.step(xs, goal, X, U, p.sqp_iters, st, graph=graph)
+        torch.cuda.synchronize()
+        out = X.cpu().numpy(), U.cpu().numpy(), g.Batch.decode_stats(st, len(solves), p.sqp_iters)
+        b.close()
+        return out
+
+    Xs, Us, ss = run(distinct, False)
+    for graph in (False, True):
+        X, U, st = run(many, graph)
+        assert not (st["status"] & (g.ST_EXCHANGE | g.ST_NONFINITE)).any()
+        for i in range(len(many)):
+            np.testing.assert_array_equal(X[i], Xs[i % 4])
+            np.testing.assert_array_equal(U[i], Us[i % 4])
+            np.testing.assert_array_equal(st["pcg_iters"][i], ss["pcg_iters"][i % 4])
 
 
 def test_full_size_uneven_task_batch_step_by_step():
