@@ -489,14 +489,16 @@ int gato_set_dispatch(gato_batch *b, int mode);
  * capture, in gato_step_graph of a batch launched per shape group, with
  * parts = 1, and when even two workgroups per solve do not fit, every solve
  * of a batch without tip tracking runs on one workgroup; long solves with tip
- * tracking run only on four parts in one launch of the whole batch, so
- * there those cases return GATO_EUNSUPPORTED. The inner products are
+ * tracking run only on four parts (a batch that does not fit the device at
+ * once takes consecutive launches over ranges of whole solves), so under the
+ * caller's capture and with parts = 1 they return GATO_EUNSUPPORTED. The
+ * inner products are
  * summed per part first, so results differ from the one-workgroup form at
  * rounding level. A part that waits too long for another sets
  * GATO_ST_EXCHANGE: every wait polls at most max_polls times (0: the default,
  * 131072 polls, about 0.1 s), after which the part stops waiting for the rest
  * of the call and its results are invalid. A batch allocates four workspaces
- * and an exchange area (42 KB) per such solve. Errors: GATO_EINVAL (parts not
+ * and an exchange area (58 KB) per such solve. Errors: GATO_EINVAL (parts not
  * 1 or 4, max_polls < 0), GATO_EUNSUPPORTED (parts = 1 in a batch with long
  * solves with tip tracking).
  */
