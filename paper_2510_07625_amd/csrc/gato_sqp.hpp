@@ -225,6 +225,21 @@ __device__ __forceinline__ void row_dot2(double &d0, double &d1, double x, const
 #undef GATO_C12
 #undef GATO_C14
 
+// The PCG's step-length quotients: a / b through the hardware reciprocal and
+// two Newton steps (about an ulp from the rounded quotient). In the FP64
+// one-knot-per-group loop this takes 1.4% off the headline call against the
+// correctly rounded division, whose longer dependent chain sits between the
+// inner products and the vector updates of every iteration.
+__device__ __forceinline__ double div_pcg(double a, double b) {
+  double r = __builtin_amdgcn_rcp(b);
+  double e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-b, r, 1.0);
+  r = fma(r, e, r);
+  return a * r;
+}
+__device__ __forceinline__ float div_pcg(float a, float b) { return a / b; }
+
 // Sum over the wavefront (all 64 lanes must be active).
 template <class R>
 __device__ __forceinline__ R wave_sum(R v) {
@@ -1064,7 +1079,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
       vm = rv_ok ? finish_P(w) : (Real)0;
       share_S(vm);
       const Real beta = gma * rg;
-      const Real alpha = gma / (dlt - gma * gma * cga);
+      const Real alpha = div_pcg(gma, dlt - gma * gma * cga);
       __syncthreads();
       halo(sm.pv, sm.sv);
       vn = rv_ok ? apply_S(vm) : (Real)0;
@@ -1076,7 +1091,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
       r -= alpha * vs;
       u -= alpha * vq;
       w -= alpha * vz;
-      cga = (Real)1 / (gma * alpha);
+      cga = div_pcg((Real)1, gma * alpha);
       rg = alpha * cga;
       ++its;
     }
@@ -2318,7 +2333,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
         // (kpt > 1: the plain quotients, whose operands are short-lived; rg and
         // cga then hold gamma_prev and alpha_prev.)
         const Real beta = kSplit ? gma * rg : ((its == 0) ? (Real)0 : gma / rg);
-        const Real alpha = kSplit ? gma / (dlt - gma * gma * cga)
+        const Real alpha = kSplit ? div_pcg(gma, dlt - gma * gma * cga)
                                   : ((its == 0) ? gma / dlt : gma / (dlt - beta * gma / cga));
         __syncthreads();
         if (xon) xhalo(sm.pv, sm.sv);
@@ -2335,7 +2350,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           w[p] -= alpha * vz[p];
         }
         if constexpr (kSplit) {
-          cga = (Real)1 / (gma * alpha);
+          cga = div_pcg((Real)1, gma * alpha);
           rg = alpha * cga;
         } else {
           rg = gma;
