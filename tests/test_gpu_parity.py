@@ -182,6 +182,24 @@ def test_sqp_trajectory_parity_tight_tolerance(n, N, M):
         assert st[i]["merit"][-1] < st[i]["merit0"][0]
 
 
+# The line search of Eq. (7) at its limits: one candidate (the full step only)
+# and the largest candidate set, with a step ratio other than the default.
+@pytest.mark.parametrize("n_alpha,beta", [(1, 2.0), (16, 1.5)])
+def test_line_search_candidate_count_limits(n_alpha, beta):
+    _say(f"line search n_alpha={n_alpha} beta={beta}")
+    solves = [w.chain_solve(3, i, n=6, N=24) for i in range(2)]
+    p = g.Params(sqp_iters=6, pcg_tol=1e-7, n_alpha=n_alpha, beta=beta)
+    Xg, Ug, st = _run_gpu(solves, p)
+    for i, s in enumerate(solves):
+        _replay_check(s, Xg[i], Ug[i], st[i], p)
+        assert not (st[i]["status"] & (g.ST_NONFINITE | g.ST_PCG_MAXITER)).any()
+    candidates = beta ** -np.arange(n_alpha, dtype=np.float64)
+    for a in st["alpha"].ravel():
+        assert np.isclose(candidates, float(a), rtol=1e-6).any(), (a, candidates)
+    if n_alpha == 1:
+        assert (st["alpha"] == 1.0).all()
+
+
 @pytest.mark.parametrize("n,N,M", [(7, 32, 4), (6, 48, 2)])
 def test_sqp_trajectory_at_config_tolerance(n, N, M):
     # PCG tolerance 1e-5 (the benchmark setting). The reference is the oracle

@@ -98,6 +98,27 @@ def test_split_solve_matches_the_oracle_and_the_one_workgroup_form(n, N):
     assert not np.array_equal(ls, l1), "the split path did not run"
 
 
+def test_split_line_search_with_the_largest_candidate_set():
+    # Sixteen step candidates: every part's partial merits and flags
+    # (n_alpha + 3 values) fill the sums region of its exchange slot.
+    _say("split n_alpha=16")
+    solves = [w.chain_solve(31, i, n=6, N=100) for i in range(2)]
+    p = g.Params(sqp_iters=4, pcg_tol=1e-7, n_alpha=16, beta=1.5)
+    Xs, Us, ss, _ = _run(solves, p, 4)
+    assert not (ss["status"] & (g.ST_EXCHANGE | g.ST_NONFINITE | g.ST_PCG_MAXITER)).any(), ss["status"]
+    for i, s in enumerate(solves):
+        ref = oracle.sqp(s, oracle.Params(sqp_iters=p.sqp_iters, kkt_mode=2, n_alpha=16, beta=1.5),
+                         alpha_replay=ss[i]["alpha"].astype(np.float64))
+        ex = np.abs(Xs[i][:s.N, :2 * s.n] - ref.X).max() / np.abs(ref.X).max()
+        eu = np.abs(Us[i][:s.N - 1, :s.n] - ref.U).max() / np.abs(ref.U).max()
+        print(f"solve {i}: alphas {ss[i]['alpha'].tolist()}, X {ex:.2e} U {eu:.2e}")
+        assert ex <= 1e-4 and eu <= 1e-4, (i, ex, eu)
+        for it, L in enumerate(ref.logs):
+            ms = L["merits"]
+            j = int(round(-np.log(float(ss[i]["alpha"][it])) / np.log(1.5)))
+            assert ms[j] - ms.min() <= 1e-5 * abs(ms.min()) + 1e-6, (i, it, j, int(np.argmin(ms)))
+
+
 @pytest.mark.parametrize("fp64", [1, 0])
 def test_split_uneven_batch_mixed_equals_grouped(fp64):
     # Split and one-workgroup solves in one mixed-shape launch, and per shape group.
