@@ -183,12 +183,13 @@ def test_sqp_trajectory_parity_tight_tolerance(n, N, M):
 
 
 # The line search of Eq. (7) at its limits: one candidate (the full step only)
-# and the largest candidate set, with a step ratio other than the default.
-@pytest.mark.parametrize("n_alpha,beta", [(1, 2.0), (16, 1.5)])
-def test_line_search_candidate_count_limits(n_alpha, beta):
-    _say(f"line search n_alpha={n_alpha} beta={beta}")
+# and the largest candidate set, with a step ratio other than the default; and
+# a lighter weight mu of the constraint violation in the merit of Eq. (3).
+@pytest.mark.parametrize("n_alpha,beta,mu", [(1, 2.0, 10.0), (16, 1.5, 10.0), (8, 2.0, 1.0)])
+def test_line_search_candidate_count_limits(n_alpha, beta, mu):
+    _say(f"line search n_alpha={n_alpha} beta={beta} mu={mu}")
     solves = [w.chain_solve(3, i, n=6, N=24) for i in range(2)]
-    p = g.Params(sqp_iters=6, pcg_tol=1e-7, n_alpha=n_alpha, beta=beta)
+    p = g.Params(sqp_iters=6, pcg_tol=1e-7, n_alpha=n_alpha, beta=beta, mu=mu)
     Xg, Ug, st = _run_gpu(solves, p)
     for i, s in enumerate(solves):
         _replay_check(s, Xg[i], Ug[i], st[i], p)
