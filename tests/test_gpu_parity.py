@@ -167,8 +167,10 @@ def _replay_check(s, Xg, Ug, st, p_gpu, tol=1e-4, check_merit=True):
 
 
 # (7, 128): the longest horizon, four knots per lane group with the Schur rows
-# read back from the workspace; (7, 2): a single control, no off-diagonal blocks.
-@pytest.mark.parametrize("n,N,M", [(7, 32, 3), (3, 20, 2), (6, 48, 2), (7, 64, 1), (7, 128, 1), (7, 2, 2)])
+# read back from the workspace; (7, 2): a single control, no off-diagonal blocks;
+# (7, 33): two knots per lane group with a single knot in the second pass.
+@pytest.mark.parametrize("n,N,M", [(7, 32, 3), (3, 20, 2), (6, 48, 2), (7, 64, 1), (7, 128, 1), (7, 2, 2),
+                                   (7, 33, 2)])
 def test_sqp_trajectory_parity_tight_tolerance(n, N, M):
     # PCG tolerance 1e-7: the exact (dense LU) oracle is the reference, 1e-4.
     _say(f"sqp tight n={n} N={N} M={M}")
