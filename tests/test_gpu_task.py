@@ -51,7 +51,8 @@ def _replay(s, Xg, Ug, st, p, kkt_mode=0, pcg_tol=1e-6):
     return ex, eu, ref
 
 
-@pytest.mark.parametrize("n,N,M", [(7, 32, 3), (6, 48, 2), (7, 64, 1), (3, 100, 2), (7, 2, 2)])
+# (7, 33): two knots per lane group with a single knot in the second pass.
+@pytest.mark.parametrize("n,N,M", [(7, 32, 3), (6, 48, 2), (7, 64, 1), (3, 100, 2), (7, 2, 2), (7, 33, 2)])
 def test_task_space_trajectory_parity(n, N, M):
     _say(f"task sqp n={n} N={N} M={M}")
     solves = [w.figure8_solve(3, i, n=n, N=N) for i in range(M)]
