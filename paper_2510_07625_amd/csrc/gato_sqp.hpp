@@ -11,9 +11,11 @@
 //   2. Schur complement (Eqs. (5)-(6)): lane j forms row j of theta_{k-1} and
 //      entry j of gamma~ in FP64, then the group inverts the diagonal block by
 //      Gauss-Jordan elimination (SPD, no pivoting).
-//   3. Stair preconditioner (Eq. (6)): the lanes of knot k+1 form the
-//      off-diagonal block -D_{k+1}^-1 phi_k D_k^-1 once; knot k reads its
-//      transpose. The paper's single grid-wide synchronisation becomes a
+//   3. Stair preconditioner (Eq. (6)): the FP64 variants apply it factored,
+//      P v = D^-1 (v - O D^-1 v) with O the off-diagonal blocks of S~, so only
+//      the rows of D^-1 are kept; the all-FP32 variant's lanes of knot k+1 form
+//      the off-diagonal block -D_{k+1}^-1 phi_k D_k^-1 once and knot k reads
+//      its transpose. The paper's single grid-wide synchronisation becomes a
 //      workgroup barrier.
 //   4. PCG on S~ lambda = gamma~ (Sec. II-B, III-B) in the pipelined
 //      arrangement: the inner products of an iteration are reduced together
@@ -25,8 +27,9 @@
 //   6. Line search (Eqs. (3), (7)): lane (alpha, knot) evaluates one trial
 //      knot; a fixed-order reduction gives each candidate's merit.
 // The Schur rows, gamma~, the block inverses, the PCG vectors and its inner
-// products use Real (double; float for the all-FP32 variant). Dynamics, line
-// search and the preconditioner blocks use float.
+// products use Real (double; float for the all-FP32 variant). Dynamics and the
+// line search's trial points use float; the explicit preconditioner blocks of
+// the all-FP32 variant (and the D^-1 rows of four knots per lane group) too.
 //
 // Task-space variant (TS): a tip tracking term 1/2 |p(q_k) - pref_k|^2_W per
 // knot makes the joint block of Q_k dense, H_k = diag(Q_q + rho) + J^T W J
