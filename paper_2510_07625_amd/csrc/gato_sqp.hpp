@@ -47,6 +47,7 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 #include "gato_internal.hpp"
 
@@ -227,6 +228,71 @@ __device__ __forceinline__ void row_dot2(double &d0, double &d1, double x, const
 #undef GATO_NB2
 #undef GATO_C12
 #undef GATO_C14
+
+// t[c] += s_c * mul for every column c of the group (s_c: s at lane c of the
+// row), one term of the row-by-matrix products that form the Schur diagonal
+// block: lane c holds row c of the matrix, so its entries need no LDS copy.
+#define GATO_RB(C) "v_fmac_f64_dpp %" #C ", %[s], %[m] row_newbcast:" #C " row_mask:0xf bank_mask:0xf\n\t"
+template <int NX>
+__device__ __forceinline__ void col_fma(double *t, double s, double mul) {
+  static_assert(NX == 12 || NX == 14, "16-lane groups hold 12 or 14 rows");
+  if constexpr (NX == 14) {
+    asm volatile("s_nop 1\n\t" GATO_RB(0) GATO_RB(1) GATO_RB(2) GATO_RB(3) GATO_RB(4) GATO_RB(5) GATO_RB(6)
+                 GATO_RB(7) GATO_RB(8) GATO_RB(9) GATO_RB(10) GATO_RB(11) GATO_RB(12) GATO_RB(13)
+                 : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]),
+                   "+v"(t[7]), "+v"(t[8]), "+v"(t[9]), "+v"(t[10]), "+v"(t[11]), "+v"(t[12]), "+v"(t[13])
+                 : [s] "v"(s), [m] "v"(mul));
+  } else {
+    asm volatile("s_nop 1\n\t" GATO_RB(0) GATO_RB(1) GATO_RB(2) GATO_RB(3) GATO_RB(4) GATO_RB(5) GATO_RB(6)
+                 GATO_RB(7) GATO_RB(8) GATO_RB(9) GATO_RB(10) GATO_RB(11)
+                 : "+v"(t[0]), "+v"(t[1]), "+v"(t[2]), "+v"(t[3]), "+v"(t[4]), "+v"(t[5]), "+v"(t[6]),
+                   "+v"(t[7]), "+v"(t[8]), "+v"(t[9]), "+v"(t[10]), "+v"(t[11])
+                 : [s] "v"(s), [m] "v"(mul));
+  }
+}
+#undef GATO_RB
+
+// One Gauss-Jordan pivot of a lane group (16-lane groups, FP64; lane r holds
+// row r): every lane takes the pivot row from lane PV's registers by row
+// broadcasts fused into its update, row_c += pivot_c * nf (nf = -f off the
+// pivot lane, 0 on it), so no row travels through LDS. The terms and their
+// rounding are those of the LDS form.
+#define GATO_GJ(C) "v_fmac_f64_dpp %" #C ", %" #C ", %[nf] row_newbcast:%[pv] row_mask:0xf bank_mask:0xf\n\t"
+template <int PV, int NX>
+__device__ __forceinline__ void gj_pivot(double *row, int lane) {
+  static_assert(NX == 12 || NX == 14, "16-lane groups hold 12 or 14 rows");
+  double pp = -0.0;   // -0 + x * 1 is x exactly
+  asm volatile("s_nop 1\n\tv_fmac_f64_dpp %0, %1, %2 row_newbcast:%3 row_mask:0xf bank_mask:0xf"
+               : "+v"(pp) : "v"(row[PV]), "v"(1.0), "i"(PV));
+  const double pinv = 1.0 / pp;
+  const double f = row[PV] * pinv;
+  const double nf = (lane == PV) ? 0.0 : -f;
+  if constexpr (NX == 14) {
+    asm volatile("s_nop 1\n\t" GATO_GJ(0) GATO_GJ(1) GATO_GJ(2) GATO_GJ(3) GATO_GJ(4) GATO_GJ(5) GATO_GJ(6)
+                 GATO_GJ(7) GATO_GJ(8) GATO_GJ(9) GATO_GJ(10) GATO_GJ(11) GATO_GJ(12) GATO_GJ(13)
+                 : "+v"(row[0]), "+v"(row[1]), "+v"(row[2]), "+v"(row[3]), "+v"(row[4]), "+v"(row[5]),
+                   "+v"(row[6]), "+v"(row[7]), "+v"(row[8]), "+v"(row[9]), "+v"(row[10]), "+v"(row[11]),
+                   "+v"(row[12]), "+v"(row[13])
+                 : [nf] "v"(nf), [pv] "i"(PV));
+  } else {
+    asm volatile("s_nop 1\n\t" GATO_GJ(0) GATO_GJ(1) GATO_GJ(2) GATO_GJ(3) GATO_GJ(4) GATO_GJ(5) GATO_GJ(6)
+                 GATO_GJ(7) GATO_GJ(8) GATO_GJ(9) GATO_GJ(10) GATO_GJ(11)
+                 : "+v"(row[0]), "+v"(row[1]), "+v"(row[2]), "+v"(row[3]), "+v"(row[4]), "+v"(row[5]),
+                   "+v"(row[6]), "+v"(row[7]), "+v"(row[8]), "+v"(row[9]), "+v"(row[10]), "+v"(row[11])
+                 : [nf] "v"(nf), [pv] "i"(PV));
+  }
+  if (lane == PV) {
+#pragma unroll
+    for (int c = 0; c < NX; ++c)
+      if (c != PV) row[c] = row[c] * pinv;
+  }
+  row[PV] = (lane == PV) ? pinv : -f;
+}
+template <int NX, int... PV>
+__device__ __forceinline__ void gj_dpp(double *row, int lane, std::integer_sequence<int, PV...>) {
+  (gj_pivot<PV, NX>(row, lane), ...);
+}
+#undef GATO_GJ
 
 // The PCG's step-length quotients: a / b through the hardware reciprocal and
 // two Newton steps (about an ulp from the rounded quotient). Every FP64 PCG
@@ -1707,14 +1773,28 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           }
 #pragma unroll
           for (int m = 0; m < NU; ++m) BrR[m] = (Real)B[lane * NU + m] * (Real)D.Ri[m];
+          if constexpr (kRealA && G == 16) {
+            // Entry (lane, c) of theta: the rows of A_{k-1} and B_{k-1} that
+            // lane c holds, read by row broadcasts (same terms, same order).
+            double Br[NU];
 #pragma unroll
-          for (int c = 0; c < NX; ++c) {
-            Real t = (c == lane) ? (Real)Qik[lane] : (Real)0;
+            for (int m = 0; m < NU; ++m) Br[m] = (double)B[lane * NU + m];
 #pragma unroll
-            for (int m = 0; m < NX; ++m) t += ArQ[m] * (Real)A[c * NX + m];
+            for (int c = 0; c < NX; ++c) thr[c] = (c == lane) ? (Real)Qik[lane] : (Real)0;
 #pragma unroll
-            for (int m = 0; m < NU; ++m) t += BrR[m] * (Real)B[c * NU + m];
-            thr[c] = t;
+            for (int m = 0; m < NX; ++m) col_fma<NX>(thr, Am[p][m], ArQ[m]);
+#pragma unroll
+            for (int m = 0; m < NU; ++m) col_fma<NX>(thr, Br[m], BrR[m]);
+          } else {
+#pragma unroll
+            for (int c = 0; c < NX; ++c) {
+              Real t = (c == lane) ? (Real)Qik[lane] : (Real)0;
+#pragma unroll
+              for (int m = 0; m < NX; ++m) t += ArQ[m] * (Real)A[c * NX + m];
+#pragma unroll
+              for (int m = 0; m < NU; ++m) t += BrR[m] * (Real)B[c * NU + m];
+              thr[c] = t;
+            }
           }
           Real z = (Real)sm.e[km][lane] + (Real)Qik[lane] * (Real)sm.qg[k][lane];
 #pragma unroll
@@ -1746,6 +1826,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             T row[NX];
 #pragma unroll
             for (int c = 0; c < NX; ++c) row[c] = (T)thr[c];
+            if constexpr (std::is_same_v<T, double> && G == 16 && !TS) {
+              gj_dpp<NX>(row, lane, std::make_integer_sequence<int, NX>{});
+            } else {
 #pragma unroll
             for (int pv = 0; pv < NX; ++pv) {
               if (lane == pv) {
@@ -1766,6 +1849,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
                 for (int c = 0; c < NX; ++c) row[c] = (c == pv) ? -f : row[c] - f * prow[c];
               }
+            }
             }
 #pragma unroll
             for (int c = 0; c < NX; ++c) Pd[p][c] = (Real)row[c];
