@@ -1773,7 +1773,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
           }
 #pragma unroll
           for (int m = 0; m < NU; ++m) BrR[m] = (Real)B[lane * NU + m] * (Real)D.Ri[m];
-          if constexpr (kRealA && G == 16) {
+          if constexpr (sizeof(Real) == 8 && G == 16 && !kRowsGlobal) {
             // Entry (lane, c) of theta: the rows of A_{k-1} and B_{k-1} that
             // lane c holds, read by row broadcasts (same terms, same order).
             double Br[NU];
@@ -1782,7 +1782,7 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
 #pragma unroll
             for (int c = 0; c < NX; ++c) thr[c] = (c == lane) ? (Real)Qik[lane] : (Real)0;
 #pragma unroll
-            for (int m = 0; m < NX; ++m) col_fma<NX>(thr, Am[p][m], ArQ[m]);
+            for (int m = 0; m < NX; ++m) col_fma<NX>(thr, (double)Am[p][m], ArQ[m]);
 #pragma unroll
             for (int m = 0; m < NU; ++m) col_fma<NX>(thr, Br[m], BrR[m]);
           } else {
