@@ -208,6 +208,26 @@ __device__ __forceinline__ void row_dot1(double &acc, double x, const double *c)
   }
 }
 
+// acc -= sum_m c[m] x_m, m = 0..NX-1 in order (the same roundings as
+// acc = fma(-c[m], x_m, acc) term by term).
+#define GATO_NBN(M, C) "v_fmac_f64_dpp %0, -%1, %[c" #M "] row_newbcast:" #M " row_mask:0xf bank_mask:0xf\n\t"
+template <int NX>
+__device__ __forceinline__ void row_dot1_sub(double &acc, double x, const double *c) {
+  static_assert(NX == 12 || NX == 14, "16-lane groups hold 12 or 14 rows");
+  if constexpr (NX == 14) {
+    asm volatile("s_nop 1\n\t" GATO_NBN(0, c) GATO_NBN(1, c) GATO_NBN(2, c) GATO_NBN(3, c) GATO_NBN(4, c)
+                 GATO_NBN(5, c) GATO_NBN(6, c) GATO_NBN(7, c) GATO_NBN(8, c) GATO_NBN(9, c) GATO_NBN(10, c)
+                 GATO_NBN(11, c) GATO_NBN(12, c) GATO_NBN(13, c)
+                 : "+v"(acc) : "v"(x), GATO_C14(c));
+  } else {
+    asm volatile("s_nop 1\n\t" GATO_NBN(0, c) GATO_NBN(1, c) GATO_NBN(2, c) GATO_NBN(3, c) GATO_NBN(4, c)
+                 GATO_NBN(5, c) GATO_NBN(6, c) GATO_NBN(7, c) GATO_NBN(8, c) GATO_NBN(9, c) GATO_NBN(10, c)
+                 GATO_NBN(11, c)
+                 : "+v"(acc) : "v"(x), GATO_C12(c));
+  }
+}
+#undef GATO_NBN
+
 // d0 += sum over even m of c[m] x_m, d1 += sum over odd m (two independent chains).
 template <int NX>
 __device__ __forceinline__ void row_dot2(double &d0, double &d1, double x, const double *c) {
@@ -2107,18 +2127,25 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             d1 += th[p][m + 1] * sm.pv[k][m + 1];
           }
         }
-        if (k > 0) {
+        if constexpr (kDpp && kRealA) {
+          // The neighbours' entries by row broadcasts too: each lane reads
+          // its own entry of the neighbour's vector (one LDS read, not 14).
+          if (k > 0) row_dot2<NX>(l0, l1, sm.sv[k - 1][lane], Am[p]);
+          if (k < N - 1) row_dot2<NX>(u0, u1, sm.pv[k + 1][lane], Ac[p]);
+        } else {
+          if (k > 0) {
 #pragma unroll
-          for (int m = 0; m < NX; m += 2) {
-            l0 += (Real)Am[p][m] * sm.sv[k - 1][m];
-            l1 += (Real)Am[p][m + 1] * sm.sv[k - 1][m + 1];
+            for (int m = 0; m < NX; m += 2) {
+              l0 += (Real)Am[p][m] * sm.sv[k - 1][m];
+              l1 += (Real)Am[p][m + 1] * sm.sv[k - 1][m + 1];
+            }
           }
-        }
-        if (k < N - 1) {
+          if (k < N - 1) {
 #pragma unroll
-          for (int m = 0; m < NX; m += 2) {
-            u0 += (Real)Ac[p][m] * sm.pv[k + 1][m];
-            u1 += (Real)Ac[p][m + 1] * sm.pv[k + 1][m + 1];
+            for (int m = 0; m < NX; m += 2) {
+              u0 += (Real)Ac[p][m] * sm.pv[k + 1][m];
+              u1 += (Real)Ac[p][m + 1] * sm.pv[k + 1][m + 1];
+            }
           }
         }
         return ((d0 + d1) - (l0 + l1)) - qown[p] * (u0 + u1);
@@ -2211,15 +2238,24 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     auto finish_P = [&](int p, Real v) -> Real {
       const int k = slot + p * SLOTS;
       Real oz = 0;   // (O z)_k at row `lane`
-      if (k > 0) {
+      if constexpr (kSplit && kDpp && kRealA) {
+        if (k > 0) row_dot1_sub<NX>(oz, sm.gv[k - 1][lane], Am[p]);
+        if (k < N - 1) {
+          Real t = 0;
+          row_dot1<NX>(t, sm.rv[k + 1][lane], Ac[p]);
+          oz -= qown[p] * t;
+        }
+      } else {
+        if (k > 0) {
 #pragma unroll
-        for (int m = 0; m < NX; ++m) oz -= (Real)am(p, m) * sm.gv[k - 1][m];
-      }
-      if (k < N - 1) {
-        Real t = 0;
+          for (int m = 0; m < NX; ++m) oz -= (Real)am(p, m) * sm.gv[k - 1][m];
+        }
+        if (k < N - 1) {
+          Real t = 0;
 #pragma unroll
-        for (int m = 0; m < NX; ++m) t += (Real)ac(p, m) * sm.rv[k + 1][m];
-        oz -= qown[p] * t;
+          for (int m = 0; m < NX; ++m) t += (Real)ac(p, m) * sm.rv[k + 1][m];
+          oz -= qown[p] * t;
+        }
       }
       return group_dinv(p, v - oz);
     };
