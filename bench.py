@@ -88,11 +88,12 @@ def profiled_kernel(path):
 
 
 # LDS bytes the FP64 one-knot-per-group PCG iteration moves per lane (16 lanes
-# per knot, idle lanes included): the two neighbour vectors of the S~ product
-# and the two of the preconditioner's off-diagonal product (14 FP64 each,
-# 8 x 16-byte reads), the two per-wavefront partial vectors of the reduction
-# (8 FP64 each), and the four FP64 values each lane publishes.
-LDS_BYTES_PER_LANE_PCG_ITER = 4 * 14 * 8 + 2 * 8 * 8 + 4 * 8
+# per knot, idle lanes included): one FP64 entry of each of the four neighbour
+# vectors (the two of the S~ product and the two of the preconditioner's
+# off-diagonal product; the other entries arrive by row broadcasts from the
+# lanes that read them), the two per-wavefront partial vectors of the
+# reduction (8 FP64 each), and the four FP64 values each lane publishes.
+LDS_BYTES_PER_LANE_PCG_ITER = 4 * 8 + 2 * 8 * 8 + 4 * 8
 
 
 def lds_report(g, kernel_ms, pcg_iters_launch, M=256, N=32):
@@ -106,7 +107,7 @@ def lds_report(g, kernel_ms, pcg_iters_launch, M=256, N=32):
     return dict(bytes_per_launch_pcg=bytes_launch, achieved_GBps=achieved / 1e9, peak_GBps=peak / 1e9,
                 frac=achieved / peak, peak_bytes_per_clk_cu=dict(distinct=per_clk0, broadcast16=per_clk1),
                 peak_GBps_by_pattern=dict(distinct=per_s0 / 1e9, broadcast16=per_s1 / 1e9),
-                model="PCG iterations x N knots x 16 lanes x (4 neighbour vectors x 14 FP64 + 2 x 8 partials "
+                model="PCG iterations x N knots x 16 lanes x (4 neighbour-vector FP64 entries + 2 x 8 partials "
                       "+ 4 published FP64) bytes")
 
 
