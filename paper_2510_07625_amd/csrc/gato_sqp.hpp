@@ -1068,20 +1068,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
     auto apply_S = [&](Real v) -> Real {
       Real d0 = 0, d1 = 0, l0 = 0, l1 = 0, u0 = 0, u1 = 0;
       row_dot2<NX>(d0, d1, v, th);
-      if (k > 0) {
-#pragma unroll
-        for (int m = 0; m < NX; m += 2) {
-          l0 += (Real)Am[m] * sm.sv[li - 1][m];
-          l1 += (Real)Am[m + 1] * sm.sv[li - 1][m + 1];
-        }
-      }
-      if (k < N - 1) {
-#pragma unroll
-        for (int m = 0; m < NX; m += 2) {
-          u0 += (Real)Ac[m] * sm.pv[li + 1][m];
-          u1 += (Real)Ac[m + 1] * sm.pv[li + 1][m + 1];
-        }
-      }
+      // Neighbours' entries by row broadcasts: each lane reads its own entry.
+      if (k > 0) row_dot2<NX>(l0, l1, sm.sv[li - 1][lane], Am);
+      if (k < N - 1) row_dot2<NX>(u0, u1, sm.pv[li + 1][lane], Ac);
       return ((d0 + d1) - (l0 + l1)) - qown * (u0 + u1);
     };
     auto dinv = [&](Real x) -> Real {
@@ -1099,14 +1088,10 @@ __device__ __attribute__((always_inline)) inline void sqp_solve_part(const KArgs
     };
     auto finish_P = [&](Real v) -> Real {
       Real oz = 0;
-      if (k > 0) {
-#pragma unroll
-        for (int m = 0; m < NX; ++m) oz -= (Real)Am[m] * sm.gv[li - 1][m];
-      }
+      if (k > 0) row_dot1_sub<NX>(oz, sm.gv[li - 1][lane], Am);
       if (k < N - 1) {
         Real t = 0;
-#pragma unroll
-        for (int m = 0; m < NX; ++m) t += (Real)Ac[m] * sm.rv[li + 1][m];
+        row_dot1<NX>(t, sm.rv[li + 1][lane], Ac);
         oz -= qown * t;
       }
       return dinv(v - oz);
