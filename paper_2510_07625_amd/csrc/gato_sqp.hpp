@@ -2112,11 +2112,21 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             d1 += th[p][m + 1] * sm.pv[k][m + 1];
           }
         }
-        if constexpr (kDpp && kRealA) {
+        if constexpr (kDpp) {
           // The neighbours' entries by row broadcasts too: each lane reads
           // its own entry of the neighbour's vector (one LDS read, not 14).
-          if (k > 0) row_dot2<NX>(l0, l1, sm.sv[k - 1][lane], Am[p]);
-          if (k < N - 1) row_dot2<NX>(u0, u1, sm.pv[k + 1][lane], Ac[p]);
+          if (k > 0) {
+            double c[NX];
+#pragma unroll
+            for (int m = 0; m < NX; ++m) c[m] = (double)Am[p][m];
+            row_dot2<NX>(l0, l1, sm.sv[k - 1][lane], c);
+          }
+          if (k < N - 1) {
+            double c[NX];
+#pragma unroll
+            for (int m = 0; m < NX; ++m) c[m] = (double)Ac[p][m];
+            row_dot2<NX>(u0, u1, sm.pv[k + 1][lane], c);
+          }
         } else {
           if (k > 0) {
 #pragma unroll
@@ -2145,6 +2155,9 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             else acc += th[p][m] * sm.pv[k][m];
           }
         }
+        // (Two or more knots per lane group: the neighbours' rows from LDS;
+        // the row-broadcast form measured slower here, its converted rows
+        // spill.)
         if (k > 0) {
 #pragma unroll
           for (int m = 0; m < NX; ++m) acc -= (Real)am(p, m) * sm.sv[k - 1][m];
@@ -2223,11 +2236,19 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     auto finish_P = [&](int p, Real v) -> Real {
       const int k = slot + p * SLOTS;
       Real oz = 0;   // (O z)_k at row `lane`
-      if constexpr (kSplit && kDpp && kRealA) {
-        if (k > 0) row_dot1_sub<NX>(oz, sm.gv[k - 1][lane], Am[p]);
+      if constexpr (kDpp && KPT == 1) {
+        if (k > 0) {
+          double c[NX];
+#pragma unroll
+          for (int m = 0; m < NX; ++m) c[m] = (double)am(p, m);
+          row_dot1_sub<NX>(oz, sm.gv[k - 1][lane], c);
+        }
         if (k < N - 1) {
           Real t = 0;
-          row_dot1<NX>(t, sm.rv[k + 1][lane], Ac[p]);
+          double c[NX];
+#pragma unroll
+          for (int m = 0; m < NX; ++m) c[m] = (double)ac(p, m);
+          row_dot1<NX>(t, sm.rv[k + 1][lane], c);
           oz -= qown[p] * t;
         }
       } else {
