@@ -228,6 +228,47 @@ __device__ __forceinline__ void row_dot1_sub(double &acc, double x, const double
 }
 #undef GATO_NBN
 
+// acc += sgn * sum_m c[m] x_m with FP32 coefficients converted inside the
+// statement (two temporaries), m = 0..NX-1 in order; the same roundings as
+// the loop acc = fma(sgn c[m], x_m, acc) over the converted c[m].
+#define GATO_NBF(M, T, S) "v_cvt_f64_f32 %[" #T "], %[c" #M "]\n\t"                                \
+  "v_fmac_f64_dpp %0, " S "%[x], %[" #T "] row_newbcast:" #M " row_mask:0xf bank_mask:0xf\n\t"
+#define GATO_F14(c) [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]), [c4] "v"(c[4]),     \
+    [c5] "v"(c[5]), [c6] "v"(c[6]), [c7] "v"(c[7]), [c8] "v"(c[8]), [c9] "v"(c[9]), [c10] "v"(c[10]),   \
+    [c11] "v"(c[11]), [c12] "v"(c[12]), [c13] "v"(c[13])
+#define GATO_F12(c) [c0] "v"(c[0]), [c1] "v"(c[1]), [c2] "v"(c[2]), [c3] "v"(c[3]), [c4] "v"(c[4]),     \
+    [c5] "v"(c[5]), [c6] "v"(c[6]), [c7] "v"(c[7]), [c8] "v"(c[8]), [c9] "v"(c[9]), [c10] "v"(c[10]),   \
+    [c11] "v"(c[11])
+#define GATO_DOTF(S)                                                                                      \
+  if constexpr (NX == 14) {                                                                               \
+    asm volatile("s_nop 1\n\t" GATO_NBF(0, ta, S) GATO_NBF(1, tb, S) GATO_NBF(2, ta, S) GATO_NBF(3, tb, S) \
+                 GATO_NBF(4, ta, S) GATO_NBF(5, tb, S) GATO_NBF(6, ta, S) GATO_NBF(7, tb, S)              \
+                 GATO_NBF(8, ta, S) GATO_NBF(9, tb, S) GATO_NBF(10, ta, S) GATO_NBF(11, tb, S)            \
+                 GATO_NBF(12, ta, S) GATO_NBF(13, tb, S)                                                  \
+                 : "+v"(acc), [ta] "=&v"(ta), [tb] "=&v"(tb) : [x] "v"(x), GATO_F14(c));                     \
+  } else {                                                                                                \
+    asm volatile("s_nop 1\n\t" GATO_NBF(0, ta, S) GATO_NBF(1, tb, S) GATO_NBF(2, ta, S) GATO_NBF(3, tb, S) \
+                 GATO_NBF(4, ta, S) GATO_NBF(5, tb, S) GATO_NBF(6, ta, S) GATO_NBF(7, tb, S)              \
+                 GATO_NBF(8, ta, S) GATO_NBF(9, tb, S) GATO_NBF(10, ta, S) GATO_NBF(11, tb, S)            \
+                 : "+v"(acc), [ta] "=&v"(ta), [tb] "=&v"(tb) : [x] "v"(x), GATO_F12(c));                     \
+  }
+template <int NX>
+__device__ __forceinline__ void row_dot1_f(double &acc, double x, const float *c) {
+  static_assert(NX == 12 || NX == 14, "16-lane groups hold 12 or 14 rows");
+  double ta, tb;
+  GATO_DOTF("")
+}
+template <int NX>
+__device__ __forceinline__ void row_dot1_sub_f(double &acc, double x, const float *c) {
+  static_assert(NX == 12 || NX == 14, "16-lane groups hold 12 or 14 rows");
+  double ta, tb;
+  GATO_DOTF("-")
+}
+#undef GATO_DOTF
+#undef GATO_F12
+#undef GATO_F14
+#undef GATO_NBF
+
 // d0 += sum over even m of c[m] x_m, d1 += sum over odd m (two independent chains).
 template <int NX>
 __device__ __forceinline__ void row_dot2(double &d0, double &d1, double x, const double *c) {
@@ -2155,18 +2196,24 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
             else acc += th[p][m] * sm.pv[k][m];
           }
         }
-        // (Two or more knots per lane group: the neighbours' rows from LDS;
-        // the row-broadcast form measured slower here, its converted rows
-        // spill.)
-        if (k > 0) {
+        if constexpr (kDpp && !kRowsGlobal && !kRealA) {
+          if (k > 0) row_dot1_sub_f<NX>(acc, sm.sv[k - 1][lane], Am[p]);
+          if (k < N - 1) {
+            Real t = 0;
+            row_dot1_f<NX>(t, sm.pv[k + 1][lane], Ac[p]);
+            acc -= qown[p] * t;
+          }
+        } else {
+          if (k > 0) {
 #pragma unroll
-          for (int m = 0; m < NX; ++m) acc -= (Real)am(p, m) * sm.sv[k - 1][m];
-        }
-        if (k < N - 1) {
-          Real t = 0;
+            for (int m = 0; m < NX; ++m) acc -= (Real)am(p, m) * sm.sv[k - 1][m];
+          }
+          if (k < N - 1) {
+            Real t = 0;
 #pragma unroll
-          for (int m = 0; m < NX; ++m) t += (Real)ac(p, m) * sm.pv[k + 1][m];
-          acc -= qown[p] * t;
+            for (int m = 0; m < NX; ++m) t += (Real)ac(p, m) * sm.pv[k + 1][m];
+            acc -= qown[p] * t;
+          }
         }
         return acc;
       }
@@ -2236,7 +2283,14 @@ __device__ __attribute__((always_inline)) inline void sqp_solve(const KArgs &a, 
     auto finish_P = [&](int p, Real v) -> Real {
       const int k = slot + p * SLOTS;
       Real oz = 0;   // (O z)_k at row `lane`
-      if constexpr (kDpp && KPT == 1) {
+      if constexpr (kDpp && KPT == 2 && !kRealA) {
+        if (k > 0) row_dot1_sub_f<NX>(oz, sm.gv[k - 1][lane], Am[p]);
+        if (k < N - 1) {
+          Real t = 0;
+          row_dot1_f<NX>(t, sm.rv[k + 1][lane], Ac[p]);
+          oz -= qown[p] * t;
+        }
+      } else if constexpr (kDpp && KPT == 1) {
         if (k > 0) {
           double c[NX];
 #pragma unroll
